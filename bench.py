@@ -1,0 +1,227 @@
+"""Benchmark of the DID hot path on one MI355X.
+
+A step is one full DID iteration (Alg. 3: column pass with the C sweep, V and W messages,
+their fixed-order reduction, and the incremental B update) on the resident workload
+M = 5000, N = 1,000,000, K = 50 in float32 with 64 column blocks; X is generated on the
+device (X = B0 C0 + |0.01 N(0,1)|, U[0,1] factors) and stays in HBM.
+
+Prints one JSON line:
+  value          iterations/s of the whole job (inputs resident in HBM at the start),
+  roofline       the dominant kernel (the column pass) against the FP32 MFMA peak,
+  cpu_baseline   the FP64 oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|image|planted]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DID iters/s + HBM GB/s (M=5000,N=1e6,K=50); served solves/s, p50/p99 latency"
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "large": dict(M=5000, N=1_000_000, K=50, n_blocks=64,
+                  desc="plain FP32 DID, M=5000 N=1000000 K=50, 64 column blocks, X=B0*C0+|0.01*N(0,1)|, "
+                       "B0,C0~U[0,1], X and R resident in HBM"),
+    "image": dict(M=784, N=70_000, K=16, n_blocks=4,
+                  desc="plain FP32 DID, M=784 N=70000 K=16, 4 column blocks, image-like X in [0,1]"),
+    "planted": dict(M=500, N=2000, K=10, n_blocks=1,
+                    desc="plain FP32 DID, M=500 N=2000 K=10, noiseless X=B0*C0"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_counts(M, N, K):
+    """Algorithmic work of one iteration and of the dominant kernel.
+
+    Iteration bytes: X read once (4MN), C read and written (8KN), B read (4MK).
+    Column-pass launch: flops 4MNK (E = X - BC and H = B^T E, 2MNK each); bytes 4MN + 8KN.
+    """
+    return dict(
+        iter_bytes=4.0 * M * N + 8.0 * K * N + 4.0 * M * K,
+        pass_flops=4.0 * M * N * K,
+        pass_bytes=4.0 * M * N + 8.0 * K * N,
+    )
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("did_kernels.hip", "did_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1802_08938_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+
+    Used only if the summary was taken on the current kernel source (hash match)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_input(torch, name, cfg):
+    from workloads import image_like, large_halfnormal_device, planted_lowrank
+
+    M, N, K = cfg["M"], cfg["N"], cfg["K"]
+    if name == "large":
+        return large_halfnormal_device(torch, M=M, N=N, K=K, seed=3, n_blocks=cfg["n_blocks"])
+    import numpy as np
+
+    X = image_like(M, N, K, seed=2)[0] if name == "image" else planted_lowrank(M, N, K, seed=1)[0]
+    return torch.from_numpy(np.ascontiguousarray(X.astype(np.float32).T)).to("cuda")
+
+
+def cpu_baseline(name, cfg):
+    """Time the FP64 oracle on a bounded sample of the workload (about 10-30 s of CPU)."""
+    import numpy as np
+    import threadpoolctl
+
+    import oracle
+    from workloads import image_like, large_halfnormal, planted_lowrank, uniform_init
+
+    M, N, K = cfg["M"], cfg["N"], cfg["K"]
+    if name == "large":
+        X, _ = large_halfnormal(M, N, K, seed=3, n_blocks=cfg["n_blocks"], take_blocks=1)
+        frac = X.shape[1] / N
+        sample = (f"one oracle DID iteration on column block 0 ({M}x{X.shape[1]}, 1/{cfg['n_blocks']} "
+                  f"of the workload), scaled x{cfg['n_blocks']}: per-iteration cost is linear in N")
+    elif name == "image":
+        X = image_like(M, N, K, seed=2)[0]
+        frac = 1.0
+        sample = "one oracle DID iteration on the full workload"
+    else:
+        X = planted_lowrank(M, N, K, seed=1)[0]
+        frac = 1.0
+        sample = "oracle DID iterations on the full workload"
+    X = X.astype(np.float32).astype(np.float64)
+    B0, C0 = uniform_init(M, X.shape[1], K, seed=12345)
+    info = threadpoolctl.threadpool_info()
+    threads = max([d.get("num_threads", 1) for d in info] or [1])
+    reps = 1 if name != "planted" else 20
+    t0 = time.perf_counter()
+    oracle.did_run(X, B0, C0, reps, P=1, history=False)
+    dt = (time.perf_counter() - t0) / reps
+    it_s = frac / dt  # iterations/s of the full workload
+    return {"value": it_s, "unit": "iter/s", "cores": threads, "kind": "oracle",
+            "sample": sample + f"; {dt:.2f} s per sampled iteration; numpy float64, BLAS threads={threads}, "
+                               f"host cpu_count={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1802_08938_amd as did
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = WORKLOADS[args.workload]
+    M, N, K = cfg["M"], cfg["N"], cfg["K"]
+    log(f"generating {args.workload} input {M}x{N} on the device")
+    X = make_input(torch, args.workload, cfg)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    opts = did.did_default_opts()
+    opts.n_blocks = cfg["n_blocks"]
+    opts.borrow_x = 1
+    opts.stream = stream.cuda_stream
+    t0 = time.perf_counter()
+    h = did.did_init_ex(X, M, N, K, 12345, opts)
+    init_s = time.perf_counter() - t0
+    log(f"init {init_s:.2f} s; warmup {args.warmup}")
+    try:
+        did.did_iterate(h, args.warmup)
+        did.did_sync(h)
+        did.did_profile(h, True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} steps")
+        ev0.record(stream)
+        did.did_iterate(h, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_total = ev0.elapsed_time(ev1)
+        stages, n_it = did.did_profile_read(h)
+        did.did_profile(h, False)
+        f_last = did.did_objective(h)
+        hist = did.did_history(h)
+    finally:
+        did.did_free(h)
+    ms = ms_total / args.steps
+    it_s = 1000.0 / ms
+    cnt = algorithmic_counts(M, N, K)
+    dom = max(("column_pass", "row_pass"), key=lambda k: stages[k])
+    dom_ms = stages[dom] / max(n_it, 1)
+    achieved = cnt["pass_flops"] / (dom_ms * 1e-3) / 1e12
+    traffic = measured_traffic(dom, args.workload)
+    roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
+            "kernel_ms": round(dom_ms, 4), "flops_per_launch": cnt["pass_flops"]}
+    line = {
+        "metric": METRIC,
+        "value": round(it_s, 4),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "M": M, "N": N, "K": K, "n_blocks": cfg["n_blocks"]},
+        "hbm_gbs_algorithmic": round(cnt["iter_bytes"] * it_s / 1e9, 2),
+        "stage_ms_per_iter": {k: round(v / max(n_it, 1), 4) for k, v in stages.items()},
+        "objective_last": f_last,
+        "objective_ratio": (f_last / hist[0]) if hist else None,
+        "init_s": round(init_s, 3),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        del X
+        torch.cuda.empty_cache()
+        line["cpu_baseline"] = cpu_baseline(args.workload, cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+"""Python binding of libdid, the MI355X DID engine (ctypes over the C ABI in include/did.h).
+
+The functions carry the C names and only marshal arguments: every step of an iteration
+runs in the HIP kernels of ``libdid.so``.  There is no fallback: if the library is not
+built, every call raises ``DidLibraryMissing``.
+
+Array arguments may be raw integer addresses, torch tensors (their ``data_ptr()``; device
+or host) or NumPy arrays (host).  Matrices are column-major: pass X of shape (M, N) with
+strides (1, M) -- e.g. ``torch.empty((N, M)).T`` or ``np.asfortranarray(X)``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "DID_OK", "DID_EINVAL", "DID_ENOMEM", "DID_EDEVICE", "DID_ESTATE", "DID_F32", "DID_BF16", "DID_MAX_K",
+    "DidError", "DidLibraryMissing", "did_opts", "lib", "library_path",
+    "did_default_opts", "did_init", "did_init_ex", "did_init_from_factors", "did_iterate", "did_objective",
+    "did_factors", "did_history", "did_iterations", "did_sync", "did_free", "did_last_error",
+    "did_profile", "did_profile_read", "did_stage_name", "EXPORTED_SYMBOLS",
+]
+
+DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
+DID_F32, DID_BF16 = 0, 1
+DID_MAX_K = 64
+
+EXPORTED_SYMBOLS = (
+    "did_default_opts", "did_init", "did_init_ex", "did_init_from_factors", "did_iterate", "did_objective",
+    "did_factors", "did_history", "did_iterations", "did_sync", "did_free", "did_last_error",
+    "did_profile", "did_profile_read", "did_stage_name",
+)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.environ.get("DID_LIBRARY", os.path.join(_HERE, "libdid.so"))
+
+
+class DidLibraryMissing(RuntimeError):
+    pass
+
+
+class DidError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"DID error {code}: {msg}")
+        self.code = code
+
+
+class did_opts(ctypes.Structure):
+    _fields_ = [
+        ("n_blocks", ctypes.c_int32),
+        ("x_dtype", ctypes.c_int32),
+        ("refresh_every", ctypes.c_int32),
+        ("init_scale", ctypes.c_int32),
+        ("borrow_x", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdid.so once (raises DidLibraryMissing if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise DidLibraryMissing(f"{path} not found: build it with `python -m paper_1802_08938_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "did_default_opts": [ctypes.POINTER(did_opts)],
+        "did_init": [vp, i64, i64, i32, u64, ctypes.POINTER(vp)],
+        "did_init_ex": [vp, i64, i64, i32, u64, ctypes.POINTER(did_opts), ctypes.POINTER(vp)],
+        "did_init_from_factors": [vp, i64, i64, i32, vp, vp, ctypes.POINTER(did_opts), ctypes.POINTER(vp)],
+        "did_iterate": [vp, i32],
+        "did_objective": [vp, ctypes.POINTER(ctypes.c_double)],
+        "did_factors": [vp, vp, vp],
+        "did_history": [vp, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(i64)],
+        "did_iterations": [vp, ctypes.POINTER(i64)],
+        "did_sync": [vp],
+        "did_free": [vp],
+        "did_profile": [vp, i32],
+        "did_profile_read": [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.did_last_error.argtypes = []
+    L.did_last_error.restype = ctypes.c_char_p
+    L.did_stage_name.argtypes = [i32]
+    L.did_stage_name.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def did_last_error() -> str:
+    return lib().did_last_error().decode()
+
+
+def _check(rc):
+    if rc != DID_OK:
+        raise DidError(rc, did_last_error())
+    return rc
+
+
+def _ptr(a):
+    """Address of an array-like (int, torch tensor, NumPy array) or None."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    if hasattr(a, "ctypes"):
+        return a.ctypes.data
+    raise TypeError(f"cannot take the address of {type(a).__name__}")
+
+
+def did_default_opts() -> did_opts:
+    o = did_opts()
+    _check(lib().did_default_opts(ctypes.byref(o)))
+    return o
+
+
+def did_init(X, M, N, K, seed):
+    h = ctypes.c_void_p()
+    _check(lib().did_init(_ptr(X), M, N, K, seed, ctypes.byref(h)))
+    return h
+
+
+def did_init_ex(X, M, N, K, seed, opts=None):
+    h = ctypes.c_void_p()
+    op = ctypes.byref(opts) if opts is not None else None
+    _check(lib().did_init_ex(_ptr(X), M, N, K, seed, op, ctypes.byref(h)))
+    return h
+
+
+def did_init_from_factors(X, M, N, K, B, C, opts=None):
+    h = ctypes.c_void_p()
+    op = ctypes.byref(opts) if opts is not None else None
+    _check(lib().did_init_from_factors(_ptr(X), M, N, K, _ptr(B), _ptr(C), op, ctypes.byref(h)))
+    return h
+
+
+def did_iterate(h, n):
+    _check(lib().did_iterate(h, n))
+
+
+def did_objective(h) -> float:
+    f = ctypes.c_double()
+    _check(lib().did_objective(h, ctypes.byref(f)))
+    return f.value
+
+
+def did_factors(h, B=None, C=None):
+    """Copy B (M x K) and C (K x N), column-major float32, into caller buffers."""
+    _check(lib().did_factors(h, _ptr(B), _ptr(C)))
+
+
+def did_history(h):
+    """Objective history f[0..t-1] as a list of floats."""
+    cnt = ctypes.c_int64()
+    _check(lib().did_history(h, None, 0, ctypes.byref(cnt)))
+    n = cnt.value
+    buf = (ctypes.c_double * max(n, 1))()
+    _check(lib().did_history(h, buf, n, ctypes.byref(cnt)))
+    return list(buf[:n])
+
+
+def did_iterations(h) -> int:
+    t = ctypes.c_int64()
+    _check(lib().did_iterations(h, ctypes.byref(t)))
+    return t.value
+
+
+def did_sync(h):
+    _check(lib().did_sync(h))
+
+
+def did_free(h):
+    _check(lib().did_free(h))
+
+
+def did_profile(h, enable=True):
+    _check(lib().did_profile(h, 1 if enable else 0))
+
+
+def did_profile_read(h):
+    """Summed milliseconds per kernel stage since the last read: (dict name->ms, n_iters)."""
+    buf = (ctypes.c_double * 32)()
+    ns = ctypes.c_int32()
+    ni = ctypes.c_int64()
+    _check(lib().did_profile_read(h, buf, 32, ctypes.byref(ns), ctypes.byref(ni)))
+    return {did_stage_name(i): buf[i] for i in range(ns.value)}, ni.value
+
+
+def did_stage_name(i) -> str:
+    return lib().did_stage_name(i).decode()

@@ -1,0 +1,539 @@
+// Host engine of libdid: the C ABI declared in include/did.h.
+//
+// The engine owns the device buffers of one NMF instance, validates arguments, draws the
+// initial factors, and sequences the kernels of one DID iteration (Alg. 3) on a single
+// HIP stream with no host round trips.  Every HIP status is checked; a runtime failure
+// marks the handle sticky-failed (DID_EDEVICE).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/did.h"
+#include "did_kernels.h"
+
+using didk::Shape;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+constexpr int64_t kHistCap = 1 << 16;
+
+// Kernel stages of one iteration, in launch order.
+constexpr int kStages = 8;
+const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "v_partials", "reduce_v",
+                                          "row_pass",    "reduce_w", "b_update",   "reduce_g"};
+
+}  // namespace
+
+struct did_ctx {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  Shape s{};
+  bool own_x = true;
+  float* X = nullptr;
+  float* B = nullptr;
+  float* C = nullptr;
+  float* BpE = nullptr;
+  float* BpH = nullptr;
+  double* G = nullptr;
+  double* Gpart = nullptr;
+  double* V = nullptr;
+  double* Vpart = nullptr;
+  double* W = nullptr;
+  float* Wpart = nullptr;
+  int R = 1;
+  int64_t* rbounds = nullptr;
+  double* fpart = nullptr;
+  double* fhist = nullptr;
+  double* fobj = nullptr;
+  int* flag = nullptr;
+  int64_t t = 0;
+  int sticky = 0;
+  std::vector<void*> allocs;
+  // per-stage timing: kStages+1 events per profiled iteration
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_events;
+};
+
+namespace {
+
+// Make h's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int dev_fail(did_ctx* h, hipError_t e, const char* what) {
+  if (h) h->sticky = 1;
+  return fail(DID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+int dalloc(did_ctx* h, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DID_ENOMEM, "device allocation of " + std::to_string((size_t)count * sizeof(T)) +
+                                " bytes failed: " + hipGetErrorString(e));
+  }
+  h->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return DID_OK;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+void release(did_ctx* h) {
+  if (!h) return;
+  DeviceGuard g(h->dev);
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (hipEvent_t ev : h->prof_events) (void)hipEventDestroy(ev);
+  h->prof_events.clear();
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  (void)hipGetLastError();
+  delete h;
+}
+
+// Column ranges of the row pass: P contiguous blocks (the paper's shards; the first N mod
+// P blocks get one extra column), each split into S sub-ranges; partials are summed in
+// ascending range order.
+std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks) {
+  const int64_t slab_groups = (nchunks + 3) / 4;
+  int64_t want = (2048 + slab_groups - 1) / slab_groups;
+  const int64_t max_ranges = std::max<int64_t>(1, (N + 31) / 32);
+  want = std::max<int64_t>(1, std::min<int64_t>(want, max_ranges));
+  int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, N) : 1;
+  int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
+  std::vector<int64_t> b;
+  b.push_back(0);
+  const int64_t base = N / P, extra = N % P;
+  int64_t a = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    const int64_t n = base + (p < extra ? 1 : 0);
+    const int64_t Sp = std::max<int64_t>(1, std::min<int64_t>(S, n));
+    for (int64_t q = 1; q <= Sp; ++q) b.push_back(a + (n * q) / Sp);
+    a += n;
+  }
+  return b;
+}
+
+int check_shape(int64_t M, int64_t N, int32_t K) {
+  if (M < 1 || N < 1 || K < 1) return fail(DID_EINVAL, "M, N and K must be >= 1");
+  if (K > DID_MAX_K) return fail(DID_EINVAL, "K > 64 is not supported");
+  if ((int64_t)K > std::min(M, N)) return fail(DID_EINVAL, "K must not exceed min(M, N)");
+  if (M > (int64_t(1) << 40) || N > (int64_t(1) << 40) || (double)M * (double)N >= 4.6e18)
+    return fail(DID_EINVAL, "M * N is too large");
+  return DID_OK;
+}
+
+// Allocate, copy/adopt X and validate it.  Leaves h ready for factor setup.
+int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did_opts& o) {
+  int rc;
+  if (o.x_dtype != DID_F32) return fail(DID_EINVAL, "only DID_F32 storage of X is supported");
+  if (o.refresh_every != 1) return fail(DID_EINVAL, "refresh_every must be 1");
+  if (o.n_blocks < 0) return fail(DID_EINVAL, "n_blocks must be >= 0");
+  if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
+  if (o.stream) {
+    h->st = static_cast<hipStream_t>(o.stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "hipStreamCreate");
+    h->own_stream = true;
+  }
+  Shape& s = h->s;
+  s.M = M;
+  s.N = N;
+  s.K = K;
+  s.KP = K <= 32 ? 32 : 64;
+  s.nchunks = (M + 31) / 32;
+  s.Mpad = s.nchunks * 32;
+
+  const bool xdev = is_device_ptr(Xv);
+  if (o.borrow_x && xdev) {
+    h->X = static_cast<float*>(const_cast<void*>(Xv));
+    h->own_x = false;
+  } else {
+    if ((rc = dalloc(h, &h->X, M * N))) return rc;
+    hipError_t e = hipMemcpyAsync(h->X, Xv, (size_t)(M * N) * sizeof(float), hipMemcpyDefault, h->st);
+    if (e != hipSuccess) return dev_fail(h, e, "copy of X");
+  }
+  s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(h->X) & 15) == 0);
+
+  const int NP = didk::n_pairs(s.KP);
+  const std::vector<int64_t> rb = make_ranges(N, s.nchunks, o.n_blocks);
+  h->R = (int)rb.size() - 1;
+  if ((rc = dalloc(h, &h->B, M * K))) return rc;
+  if ((rc = dalloc(h, &h->C, (int64_t)K * N))) return rc;
+  if ((rc = dalloc(h, &h->BpE, didk::packed_b_floats(s)))) return rc;
+  if ((rc = dalloc(h, &h->BpH, didk::packed_b_floats(s)))) return rc;
+  if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
+  if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
+  if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
+  if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
+  if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
+  if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
+  if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
+  if ((rc = dalloc(h, &h->fpart, didk::pass1_blocks(s)))) return rc;
+  if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
+  if ((rc = dalloc(h, &h->fobj, 1))) return rc;
+  if ((rc = dalloc(h, &h->flag, 1))) return rc;
+
+  hipError_t e;
+  if ((e = hipMemsetAsync(h->BpE, 0, (size_t)didk::packed_b_floats(s) * 4, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->BpH, 0, (size_t)didk::packed_b_floats(s) * 4, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
+          hipSuccess)
+    return dev_fail(h, e, "buffer setup");
+  if ((e = didk::validate(h->X, M * N, s.vec4, h->flag, h->st)) != hipSuccess) return dev_fail(h, e, "validate X");
+  int flag = 0;
+  if ((e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->st)) != hipSuccess)
+    return dev_fail(h, e, "validate X");
+  if (flag) return fail(DID_EINVAL, "X must be finite and nonnegative");
+  return DID_OK;
+}
+
+// Pack B and form G = B^T B.
+hipError_t refresh_b_derived(did_ctx* h) {
+  hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->BpE, h->BpH, h->Gpart, 0, h->st);
+  if (e != hipSuccess) return e;
+  return didk::reduce_sym(h->Gpart, didk::bupdate_blocks(h->s), h->s.KP, h->G, h->st);
+}
+
+int check_handle(did_ctx* h) {
+  if (!h) return fail(DID_EINVAL, "NULL handle");
+  if (h->sticky) return fail(DID_EDEVICE, "handle is in a failed state after an earlier device error");
+  return DID_OK;
+}
+
+int objective_pass(did_ctx* h) {
+  hipError_t e;
+  if ((e = didk::pass1(h->s, h->X, h->C, h->BpE, h->BpH, h->G, h->fpart, 0, h->st)) != hipSuccess)
+    return dev_fail(h, e, "objective pass");
+  if ((e = didk::reduce_f(h->fpart, didk::pass1_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
+    return dev_fail(h, e, "objective reduce");
+  return DID_OK;
+}
+
+int apply_init_scale(did_ctx* h) {
+  // alpha minimising f over a common scale: f(a) = f0 - b a + c a^2 / 2 evaluated at
+  // a = 1, 2, 4 by scaling C exactly by powers of two.
+  double fv[3];
+  const float mul[3] = {1.0f, 2.0f, 2.0f};
+  const int64_t nC = (int64_t)h->s.K * h->s.N;
+  hipError_t e;
+  for (int q = 0; q < 3; ++q) {
+    if (q && (e = didk::scale(h->C, nC, mul[q], h->st)) != hipSuccess) return dev_fail(h, e, "init scale");
+    int rc = objective_pass(h);
+    if (rc) return rc;
+    if ((e = hipMemcpyAsync(&fv[q], h->fobj, sizeof(double), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->st)) != hipSuccess)
+      return dev_fail(h, e, "init scale");
+  }
+  if ((e = didk::scale(h->C, nC, 0.25f, h->st)) != hipSuccess) return dev_fail(h, e, "init scale");
+  const double c = (fv[2] - 3.0 * fv[1] + 2.0 * fv[0]) / 3.0;
+  const double b = 1.5 * c - (fv[1] - fv[0]);
+  if (c > 0.0 && b > 0.0 && std::isfinite(b / c)) {
+    const float r = (float)std::sqrt(b / c);
+    if ((e = didk::scale(h->C, nC, r, h->st)) != hipSuccess ||
+        (e = didk::scale(h->B, h->s.M * h->s.K, r, h->st)) != hipSuccess ||
+        (e = refresh_b_derived(h)) != hipSuccess)
+      return dev_fail(h, e, "init scale");
+  }
+  return DID_OK;
+}
+
+int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const float* B0, const float* C0,
+                const did_opts* opts, did_handle* out) {
+  if (!out) return fail(DID_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!X) return fail(DID_EINVAL, "X must not be NULL");
+  int rc = check_shape(M, N, K);
+  if (rc) return rc;
+  did_opts o;
+  did_default_opts(&o);
+  if (opts) o = *opts;
+  did_ctx* h = new (std::nothrow) did_ctx();
+  if (!h) return fail(DID_ENOMEM, "host allocation failed");
+  if ((rc = setup(h, X, M, N, K, o))) {
+    release(h);
+    return rc;
+  }
+  hipError_t e;
+  if (B0) {
+    if ((e = hipMemcpyAsync(h->B, B0, (size_t)(M * K) * 4, hipMemcpyDefault, h->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->C, C0, (size_t)((int64_t)K * N) * 4, hipMemcpyDefault, h->st)) != hipSuccess) {
+      rc = dev_fail(h, e, "copy of B, C");
+      release(h);
+      return rc;
+    }
+    int flag = 0;
+    if ((e = didk::validate(h->B, M * K, 0, h->flag, h->st)) != hipSuccess ||
+        (e = didk::validate(h->C, (int64_t)K * N, 0, h->flag, h->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->st)) != hipSuccess) {
+      rc = dev_fail(h, e, "validate B, C");
+      release(h);
+      return rc;
+    }
+    if (flag) {
+      release(h);
+      return fail(DID_EINVAL, "B and C must be finite and nonnegative");
+    }
+  } else {
+    if ((e = didk::fill_uniform(h->B, M * K, didk::stream_key(seed, 1), h->st)) != hipSuccess ||
+        (e = didk::fill_uniform(h->C, (int64_t)K * N, didk::stream_key(seed, 2), h->st)) != hipSuccess) {
+      rc = dev_fail(h, e, "initial draw");
+      release(h);
+      return rc;
+    }
+  }
+  if ((e = refresh_b_derived(h)) != hipSuccess) {
+    rc = dev_fail(h, e, "pack B");
+    release(h);
+    return rc;
+  }
+  if (!B0 && o.init_scale) {
+    if ((rc = apply_init_scale(h))) {
+      release(h);
+      return rc;
+    }
+  }
+  if ((e = hipStreamSynchronize(h->st)) != hipSuccess) {
+    rc = dev_fail(h, e, "init");
+    release(h);
+    return rc;
+  }
+  *out = h;
+  g_err.clear();
+  return DID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int did_default_opts(did_opts* o) {
+  if (!o) return fail(DID_EINVAL, "opts must not be NULL");
+  memset(o, 0, sizeof(*o));
+  o->n_blocks = 0;
+  o->x_dtype = DID_F32;
+  o->refresh_every = 1;
+  o->init_scale = 0;
+  o->borrow_x = 0;
+  o->stream = nullptr;
+  return DID_OK;
+}
+
+int did_init(const float* X, int64_t M, int64_t N, int32_t K, uint64_t seed, did_handle* out) {
+  return init_common(X, M, N, K, seed, nullptr, nullptr, nullptr, out);
+}
+
+int did_init_ex(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const did_opts* opts,
+                did_handle* out) {
+  return init_common(X, M, N, K, seed, nullptr, nullptr, opts, out);
+}
+
+int did_init_from_factors(const void* X, int64_t M, int64_t N, int32_t K, const float* B, const float* C,
+                          const did_opts* opts, did_handle* out) {
+  if (!B || !C) {
+    if (out) *out = nullptr;
+    return fail(DID_EINVAL, "B and C must not be NULL");
+  }
+  return init_common(X, M, N, K, 0, B, C, opts, out);
+}
+
+int did_iterate(did_handle h, int32_t n) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (n < 0) return fail(DID_EINVAL, "n must be >= 0");
+  DeviceGuard g(h->dev);
+  const Shape& s = h->s;
+  hipError_t e;
+  for (int32_t it = 0; it < n; ++it) {
+    hipEvent_t* ev = nullptr;
+    if (h->profiling) {
+      const size_t base = h->prof_events.size();
+      h->prof_events.resize(base + kStages + 1, nullptr);
+      for (int q = 0; q <= kStages; ++q)
+        if ((e = hipEventCreate(&h->prof_events[base + q])) != hipSuccess) return dev_fail(h, e, "profile event");
+      ev = h->prof_events.data() + base;
+    }
+#define DID_MARK(q) \
+  if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
+    DID_MARK(0);
+    if ((e = didk::pass1(s, h->X, h->C, h->BpE, h->BpH, h->G, h->fpart, 1, h->st)) != hipSuccess)
+      return dev_fail(h, e, "column pass");
+    DID_MARK(1);
+    if ((e = didk::reduce_f(h->fpart, didk::pass1_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
+        hipSuccess)
+      return dev_fail(h, e, "objective reduce");
+    DID_MARK(2);
+    if ((e = didk::vgram(s, h->C, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
+    DID_MARK(3);
+    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
+      return dev_fail(h, e, "V reduce");
+    DID_MARK(4);
+    if ((e = didk::pass2(s, h->X, h->C, h->BpE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+      return dev_fail(h, e, "row pass");
+    DID_MARK(5);
+    if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
+    DID_MARK(6);
+    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BpE, h->BpH, h->Gpart, 1, h->st)) != hipSuccess)
+      return dev_fail(h, e, "B update");
+    DID_MARK(7);
+    if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
+      return dev_fail(h, e, "G reduce");
+    DID_MARK(8);
+#undef DID_MARK
+    ++h->t;
+  }
+  return DID_OK;
+}
+
+int did_objective(did_handle h, double* f) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!f) return fail(DID_EINVAL, "f must not be NULL");
+  DeviceGuard g(h->dev);
+  if ((rc = objective_pass(h))) return rc;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(f, h->fobj, sizeof(double), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->st)) != hipSuccess)
+    return dev_fail(h, e, "objective");
+  return DID_OK;
+}
+
+int did_factors(did_handle h, float* B, float* C) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceGuard g(h->dev);
+  hipError_t e;
+  if (B && (e = hipMemcpyAsync(B, h->B, (size_t)(h->s.M * h->s.K) * 4, hipMemcpyDefault, h->st)) != hipSuccess)
+    return dev_fail(h, e, "copy of B");
+  if (C && (e = hipMemcpyAsync(C, h->C, (size_t)((int64_t)h->s.K * h->s.N) * 4, hipMemcpyDefault, h->st)) !=
+               hipSuccess)
+    return dev_fail(h, e, "copy of C");
+  if ((e = hipStreamSynchronize(h->st)) != hipSuccess) return dev_fail(h, e, "factors");
+  return DID_OK;
+}
+
+int did_history(did_handle h, double* f, int64_t cap, int64_t* count) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!count) return fail(DID_EINVAL, "count must not be NULL");
+  if (cap < 0 || (cap > 0 && !f)) return fail(DID_EINVAL, "bad output buffer");
+  DeviceGuard g(h->dev);
+  const int64_t avail = std::min<int64_t>(h->t, kHistCap);
+  *count = h->t;
+  const int64_t ncopy = std::min<int64_t>(cap, avail);
+  hipError_t e;
+  if (ncopy > 0) {
+    if (h->t > kHistCap) return fail(DID_ESTATE, "objective history wrapped (more than 65536 iterations)");
+    if ((e = hipMemcpyAsync(f, h->fhist, (size_t)ncopy * sizeof(double), hipMemcpyDeviceToHost, h->st)) !=
+        hipSuccess)
+      return dev_fail(h, e, "history");
+  }
+  if ((e = hipStreamSynchronize(h->st)) != hipSuccess) return dev_fail(h, e, "history");
+  return DID_OK;
+}
+
+int did_iterations(did_handle h, int64_t* t) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!t) return fail(DID_EINVAL, "t must not be NULL");
+  *t = h->t;
+  return DID_OK;
+}
+
+int did_sync(did_handle h) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceGuard g(h->dev);
+  hipError_t e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) return dev_fail(h, e, "sync");
+  return DID_OK;
+}
+
+int did_profile(did_handle h, int32_t enable) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  h->profiling = enable != 0;
+  return DID_OK;
+}
+
+int did_profile_read(did_handle h, double* ms, int32_t cap, int32_t* n_stages, int64_t* n_iters) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!n_stages || !n_iters || cap < 0 || (cap > 0 && !ms)) return fail(DID_EINVAL, "bad output arguments");
+  DeviceGuard g(h->dev);
+  hipError_t e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) return dev_fail(h, e, "profile sync");
+  const size_t per = kStages + 1;
+  const int64_t iters = (int64_t)(h->prof_events.size() / per);
+  double acc[kStages] = {0};
+  for (int64_t it = 0; it < iters; ++it)
+    for (int q = 0; q < kStages; ++q) {
+      float t = 0.0f;
+      if ((e = hipEventElapsedTime(&t, h->prof_events[it * per + q], h->prof_events[it * per + q + 1])) !=
+          hipSuccess)
+        return dev_fail(h, e, "profile read");
+      acc[q] += t;
+    }
+  for (hipEvent_t ev : h->prof_events) (void)hipEventDestroy(ev);
+  h->prof_events.clear();
+  for (int q = 0; q < kStages && q < cap; ++q) ms[q] = acc[q];
+  *n_stages = kStages;
+  *n_iters = iters;
+  return DID_OK;
+}
+
+const char* did_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < kStages) ? kStageNames[stage] : "";
+}
+
+int did_free(did_handle h) {
+  if (!h) return DID_OK;
+  release(h);
+  return DID_OK;
+}
+
+const char* did_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Internal interface between the DID engine (did_engine.hip) and its gfx950 kernels
+// (did_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace didk {
+
+// Shapes derived once per instance.
+struct Shape {
+  int64_t M, N;      // rows (features) and columns (samples) of X
+  int K;             // coordinates
+  int KP;            // K padded to the MFMA output tile (32 or 64)
+  int64_t nchunks;   // ceil(M / 32): 32-row chunks of the basis
+  int64_t Mpad;      // nchunks * 32
+  int vec4;          // X column starts are 16-byte aligned (M % 4 == 0 and X aligned)
+};
+
+// Number of float32 entries of one packed-operand buffer (E-operand or H-operand) of B.
+inline int64_t packed_b_floats(const Shape& s) { return s.nchunks * (int64_t)s.KP * 32; }
+inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
+
+// splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed ^ (stream * 0xD1B54A32D192ED03ull));
+}
+
+// ---- launchers (all asynchronous on `st`; they return the launch status) ----
+hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
+hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
+hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
+
+// Pack B into MFMA operand order, optionally applying the incremental B update from the
+// reduced messages W (KP x Mpad, float64) and V (KP x KP, float64); writes per-block
+// partials of B^T B into Gpart (n_pairs(KP) doubles per block).  Grid: ceil(M/256).
+hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, float* BpE,
+                   float* BpH, double* Gpart, int update, hipStream_t st);
+int bupdate_blocks(const Shape& s);
+
+// Column pass: E = X - BC per 32-column tile, f partials, and (sweep=1) H = B^T E with the
+// Gram-form coordinate sweep writing C in place.  One partial of sum E^2 per block.
+hipError_t pass1(const Shape& s, const float* X, float* C, const float* BpE, const float* BpH,
+                 const double* G, double* fpart, int sweep, hipStream_t st);
+int64_t pass1_blocks(const Shape& s);
+
+// Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
+hipError_t pass2(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
+                 const int64_t* rbounds, int R, hipStream_t st);
+
+// V partials: tril(C C^T) per group of columns (float64).
+hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st);
+int64_t vgram_blocks(const Shape& s);
+
+// Fixed-order reductions.
+hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStream_t st);
+hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st);
+hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st);
+
+}  // namespace didk

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol include/did.h
+declares, and rejects bad arguments before touching a device (no compute calls here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1802_08938_amd as did
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "did.h")
+
+
+def _lib_or_skip():
+    try:
+        return did.lib()
+    except did.DidLibraryMissing:
+        pytest.skip("libdid.so not built (run __graft_entry__.build())")
+
+
+def header_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(did_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    assert set(header_symbols()) == set(did.EXPORTED_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    for name in header_symbols():
+        assert hasattr(L, name), name
+
+
+def test_default_opts_and_struct_layout():
+    _lib_or_skip()
+    o = did.did_default_opts()
+    assert (o.n_blocks, o.x_dtype, o.refresh_every, o.init_scale, o.borrow_x) == (0, did.DID_F32, 1, 0, 0)
+    assert o.stream is None
+    assert ctypes.sizeof(did.did_opts) == 32
+
+
+@pytest.mark.parametrize("M,N,K,msg", [
+    (0, 10, 1, "M, N and K"),
+    (10, 0, 1, "M, N and K"),
+    (10, 10, 0, "M, N and K"),
+    (100, 100, 65, "K > 64"),
+    (5, 100, 6, "min(M, N)"),
+    (100, 5, 6, "min(M, N)"),
+])
+def test_shape_validation_without_device(M, N, K, msg):
+    L = _lib_or_skip()
+    h = ctypes.c_void_p(12345)
+    dummy = (ctypes.c_float * 4)()
+    rc = L.did_init(ctypes.cast(dummy, ctypes.c_void_p), M, N, K, 1, ctypes.byref(h))
+    assert rc == did.DID_EINVAL
+    assert h.value is None
+    assert msg in did.did_last_error()
+
+
+def test_null_arguments():
+    L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    assert L.did_init(None, 4, 4, 1, 1, ctypes.byref(h)) == did.DID_EINVAL
+    dummy = (ctypes.c_float * 4)()
+    assert L.did_init(ctypes.cast(dummy, ctypes.c_void_p), 2, 2, 1, 1, None) == did.DID_EINVAL
+    assert L.did_iterate(None, 1) == did.DID_EINVAL
+    f = ctypes.c_double()
+    assert L.did_objective(None, ctypes.byref(f)) == did.DID_EINVAL
+    assert L.did_factors(None, None, None) == did.DID_EINVAL
+    assert L.did_free(None) == did.DID_OK
+    assert L.did_default_opts(None) == did.DID_EINVAL
+    with pytest.raises(did.DidError) as ei:
+        did.did_iterate(None, 1)
+    assert ei.value.code == did.DID_EINVAL
+
+
+def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setenv("DID_LIBRARY", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(did, "_lib", None)
+    with pytest.raises(did.DidLibraryMissing):
+        did.lib()

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same inputs.
+
+Tolerances (FP32 engine vs FP64 oracle), normwise as the projection [z]_+ can flip at
+z ~ 0 under a different summation order:
+  factors after one iteration   ||B_gpu - B_or||_F / ||B_or||_F <= 1e-5, same for C;
+  objective trajectory          max_t |f_gpu[t] - f_or[t]| / f_or[t] <= 1e-4;
+  exact worked examples         1e-6 relative.
+"""
+
+from fractions import Fraction
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1802_08938_amd as did
+from workloads import as_oracle_input, image_like, large_halfnormal, planted_lowrank, to_f32_colmajor
+
+from _gpu import announce, device_x, read_factors, rel_fro, require_gpu, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+TOL_FACTORS = 1e-5
+TOL_OBJ = 1e-4
+
+
+def _mat(rows):
+    return np.array([[float(Fraction(v)) for v in r] for r in rows])
+
+
+def _oracle_from(X32, B0, C0, T, P=1):
+    return oracle.did_run(as_oracle_input(X32), B0, C0, T, P=P)
+
+
+@pytest.mark.parametrize("name", ["k1", "k2_clipping"])
+def test_worked_examples_on_gpu(name):
+    torch = require_gpu()
+    g = json.load(open(GOLDEN))[name]
+    X, B0, C0 = _mat(g["X"]), _mat(g["B0"]), _mat(g["C0"])
+    announce(f"worked example {name}")
+    out = run_gpu(torch, to_f32_colmajor(X), B0.shape[1], iters=(1,), B0=B0, C0=C0)
+    B1, C1 = out[1]
+    np.testing.assert_allclose(C1, _mat(g["C1"]), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(B1, _mat(g["B1"]), rtol=1e-6, atol=1e-6)
+    assert out["hist"][0] == pytest.approx(float(Fraction(g["f0"])), rel=1e-6)
+    assert out["f"] == pytest.approx(float(Fraction(g["f1"])), rel=1e-6)
+
+
+def test_planted_500x2000_k10_parity_50_iterations():
+    torch = require_gpu()
+    X, _, _ = planted_lowrank(500, 2000, 10, seed=1)
+    X32 = to_f32_colmajor(X)
+    announce("planted 500x2000 K=10, 50 iterations")
+    out = run_gpu(torch, X32, 10, iters=(1, 50))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = _oracle_from(X32, B0, C0, 50)
+    fg = np.append(out["hist"], out["f"])
+    assert fg.shape == fo.shape
+    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+    assert np.all(out[50][0] >= 0) and np.all(out[50][1] >= 0)
+
+
+def test_image_like_784x70000_k16_parity():
+    torch = require_gpu()
+    X, _, _ = image_like(784, 70000, 16, seed=2)
+    X32 = to_f32_colmajor(X)
+    opts = did.did_default_opts()
+    opts.n_blocks = 4
+    announce("image-like 784x70000 K=16, 4 blocks")
+    out = run_gpu(torch, X32, 16, iters=(1, 10), opts=opts)
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1, P=4)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = _oracle_from(X32, B0, C0, 10, P=4)
+    fg = np.append(out["hist"], out["f"])
+    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+
+
+@pytest.mark.parametrize("blocks", [1])
+def test_large_slice_5000x15625_k50_parity(blocks):
+    torch = require_gpu()
+    X, _ = large_halfnormal(5000, 1_000_000, 50, seed=3, n_blocks=64, take_blocks=blocks)
+    X32 = to_f32_colmajor(X)
+    del X
+    announce(f"large slice 5000x{X32.shape[1]} K=50")
+    out = run_gpu(torch, X32, 50, iters=(1, 3))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = _oracle_from(X32, B0, C0, 3)
+    fg = np.append(out["hist"], out["f"])
+    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+
+
+@pytest.mark.parametrize("M,N,K", [
+    (37, 45, 3),     # ragged rows and columns, odd K
+    (31, 33, 1),     # K = 1, below one tile in rows
+    (100, 300, 32),  # K exactly one output tile
+    (70, 129, 33),   # K just above one tile (padded to 64)
+    (130, 260, 64),  # largest supported K
+    (64, 200, 7),    # M % 4 == 0 (vector loads) with a tail tile of columns
+    (5, 1000, 3),    # the experiments' shape, tiny M
+])
+def test_edge_shapes_parity(M, N, K):
+    """Shapes that exercise ragged tiles and K padding, on planted low-rank data with
+    half-normal noise (conditioned like the named workloads)."""
+    torch = require_gpu()
+    rng = np.random.default_rng(M * 7 + N + K)
+    X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
+    X32 = to_f32_colmajor(X)
+    announce(f"edge shape M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 5))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = _oracle_from(X32, B0, C0, 5)
+    fg = np.append(out["hist"], out["f"])
+    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+
+
+def _fp32_sensitivity(X32, B0, C0, draws=3):
+    """How far the oracle's one-iteration factors move when X is perturbed at the scale of
+    float32 rounding of the residual, eps32 * max|B0 C0|: the floor any float32 engine
+    faces on this input, whatever its summation order."""
+    X = as_oracle_input(X32)
+    B1, C1, _ = oracle.did_run(X, B0, C0, 1)
+    scale = np.finfo(np.float32).eps * float(np.max(np.abs(B0 @ C0)))
+    worst = 0.0
+    for d in range(draws):
+        r = np.random.default_rng(1000 + d)
+        Bp, Cp, _ = oracle.did_run(X + scale * r.standard_normal(X.shape), B0, C0, 1)
+        worst = max(worst, rel_fro(Bp, B1), rel_fro(Cp, C1))
+    return worst
+
+
+@pytest.mark.parametrize("M,N,K", [(100, 300, 32), (130, 260, 64), (70, 129, 33)])
+def test_unstructured_data_within_fp32_conditioning(M, N, K):
+    """Dense U[0,2] data with K close to M/3 is ill-conditioned for NMF: the tolerance is
+    max(1e-5, 10 x the oracle's own movement under float32-sized perturbations of X)."""
+    torch = require_gpu()
+    rng = np.random.default_rng(M * 7 + N + K)
+    X32 = to_f32_colmajor(rng.random((M, N)) * 2.0)
+    announce(f"unstructured data M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1,))
+    B0, C0 = out["init"]
+    tol = max(TOL_FACTORS, 10.0 * _fp32_sensitivity(X32, B0, C0))
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= tol
+    assert rel_fro(out[1][1], C1o) <= tol
+
+
+def test_zero_data_and_guard_on_gpu():
+    """X = 0 with small-integer factors: C becomes exactly 0, every v_ii = 0 keeps B."""
+    torch = require_gpu()
+    rng = np.random.default_rng(10)
+    M, N, K = 40, 50, 3
+    B0 = rng.integers(0, 4, size=(M, K)).astype(float) + np.eye(M, K)
+    C0 = rng.integers(0, 4, size=(K, N)).astype(float)
+    announce("zero data")
+    out = run_gpu(torch, to_f32_colmajor(np.zeros((M, N))), K, iters=(1,), B0=B0, C0=C0)
+    B1, C1 = out[1]
+    assert np.all(C1 == 0.0)
+    np.testing.assert_array_equal(B1, B0)
+    assert out["f"] == 0.0
+
+
+def test_zero_column_of_b_is_skipped_on_gpu():
+    torch = require_gpu()
+    rng = np.random.default_rng(12)
+    M, N, K = 48, 70, 4
+    X32 = to_f32_colmajor(rng.random((M, N)))
+    B0, C0 = rng.random((M, K)), rng.random((K, N))
+    B0[:, 2] = 0.0
+    announce("zero column of B")
+    out = run_gpu(torch, X32, K, iters=(1,), B0=B0.astype(np.float32), C0=C0.astype(np.float32))
+    np.testing.assert_array_equal(out[1][1][2], C0.astype(np.float32)[2].astype(np.float64))
+    B1o, C1o, _ = _oracle_from(X32, out["init"][0], out["init"][1], 1)
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+
+
+def test_rejects_negative_and_nonfinite_x():
+    torch = require_gpu()
+    for bad in (-1.0, np.nan, np.inf):
+        X = np.ones((40, 40), dtype=np.float32)
+        X[3, 7] = bad
+        announce(f"invalid X entry {bad}")
+        with pytest.raises(did.DidError) as ei:
+            did.did_init(device_x(torch, X), 40, 40, 2, 1)
+        assert ei.value.code == did.DID_EINVAL
+
+
+def test_host_pointer_x_matches_device_pointer():
+    torch = require_gpu()
+    rng = np.random.default_rng(4)
+    X32 = to_f32_colmajor(rng.random((64, 96)))
+    announce("host vs device X")
+    hd = did.did_init(device_x(torch, X32), 64, 96, 5, 7)
+    Xh = np.ascontiguousarray(X32.T)  # host memory, column-major X
+    hh = did.did_init(Xh, 64, 96, 5, 7)
+    try:
+        did.did_iterate(hd, 3)
+        did.did_iterate(hh, 3)
+        a = read_factors(hd, 64, 96, 5)
+        b = read_factors(hh, 64, 96, 5)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    finally:
+        did.did_free(hd)
+        did.did_free(hh)
+
+
+def test_deterministic_bitwise():
+    torch = require_gpu()
+    X, _, _ = planted_lowrank(300, 5000, 12, seed=9)
+    X32 = to_f32_colmajor(X)
+    announce("determinism")
+    a = run_gpu(torch, X32, 12, iters=(7,))
+    b = run_gpu(torch, X32, 12, iters=(7,))
+    np.testing.assert_array_equal(a[7][0], b[7][0])
+    np.testing.assert_array_equal(a[7][1], b[7][1])
+    np.testing.assert_array_equal(a["hist"], b["hist"])
+
+
+def test_block_count_only_changes_rounding():
+    torch = require_gpu()
+    X, _, _ = planted_lowrank(200, 6400, 8, seed=13)
+    X32 = to_f32_colmajor(X)
+    res = []
+    for P in (1, 4, 64):
+        o = did.did_default_opts()
+        o.n_blocks = P
+        announce(f"n_blocks={P}")
+        res.append(run_gpu(torch, X32, 8, iters=(5,), opts=o))
+    for r in res[1:]:
+        assert rel_fro(r[5][0], res[0][5][0]) <= 1e-5
+        assert rel_fro(r[5][1], res[0][5][1]) <= 1e-5
+
+
+def test_resume_from_factors_equals_uninterrupted():
+    torch = require_gpu()
+    X, _, _ = planted_lowrank(150, 900, 6, seed=17)
+    X32 = to_f32_colmajor(X)
+    announce("resume")
+    full = run_gpu(torch, X32, 6, iters=(4, 8))
+    B4, C4 = full[4]
+    resumed = run_gpu(torch, X32, 6, iters=(4,), B0=B4.astype(np.float32), C0=C4.astype(np.float32))
+    np.testing.assert_array_equal(resumed[4][0], full[8][0])
+    np.testing.assert_array_equal(resumed[4][1], full[8][1])
+
+
+def test_init_scale_minimises_common_scale():
+    torch = require_gpu()
+    X, _, _ = image_like(100, 700, 5, seed=3)
+    X32 = to_f32_colmajor(X)
+    announce("init_scale")
+    o = did.did_default_opts()
+    o.init_scale = 1
+    sc = run_gpu(torch, X32, 5, iters=(0,), opts=o)
+    un = run_gpu(torch, X32, 5, iters=(0,))
+    Bs, Cs = sc["init"]
+    Bu, Cu = un["init"]
+    Xo = as_oracle_input(X32)
+    P = Bu @ Cu
+    alpha = float(np.sum(Xo * P) / np.sum(P * P))
+    np.testing.assert_allclose(Bs @ Cs, alpha * P, rtol=1e-4)
+    assert sc["f"] < un["f"]
