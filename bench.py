@@ -156,7 +156,9 @@ def main():
     log(f"generating {args.workload} input {M}x{N} on the device")
     X = make_input(torch, args.workload, cfg)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    # a dedicated (default-priority) stream: the engine's kernels and the timing events
+    # must share it; torch's current stream is the null stream, whose handle is 0
+    stream = torch.cuda.Stream()
     opts = did.did_default_opts()
     opts.n_blocks = cfg["n_blocks"]
     opts.borrow_x = 1
@@ -165,6 +167,7 @@ def main():
     h = did.did_init_ex(X, M, N, K, 12345, opts)
     init_s = time.perf_counter() - t0
     log(f"init {init_s:.2f} s; warmup {args.warmup}")
+    assert opts.stream, "engine stream must be explicit"
     try:
         did.did_iterate(h, args.warmup)
         did.did_sync(h)

@@ -33,8 +33,8 @@ constexpr int64_t kHistCap = 1 << 16;
 
 // Kernel stages of one iteration, in launch order.
 constexpr int kStages = 8;
-const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "v_partials", "reduce_v",
-                                          "row_pass",    "reduce_w", "b_update",   "reduce_g"};
+const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "sweep",    "reduce_v",
+                                          "row_pass",    "reduce_w", "b_update", "reduce_g"};
 
 }  // namespace
 
@@ -53,6 +53,7 @@ struct did_ctx {
   double* Gpart = nullptr;
   double* V = nullptr;
   double* Vpart = nullptr;
+  float* H = nullptr;
   double* W = nullptr;
   float* Wpart = nullptr;
   int R = 1;
@@ -203,11 +204,12 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
-  if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
+  if ((rc = dalloc(h, &h->Vpart, didk::sweep_blocks(s) * s.KP * s.KP))) return rc;
+  if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
   if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
   if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
   if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
-  if ((rc = dalloc(h, &h->fpart, didk::pass1_blocks(s)))) return rc;
+  if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
   if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
   if ((rc = dalloc(h, &h->flag, 1))) return rc;
@@ -244,9 +246,9 @@ int check_handle(did_ctx* h) {
 
 int objective_pass(did_ctx* h) {
   hipError_t e;
-  if ((e = didk::pass1(h->s, h->X, h->C, h->BpE, h->BpH, h->G, h->fpart, 0, h->st)) != hipSuccess)
+  if ((e = didk::colpass(h->s, h->X, h->C, h->BpE, h->BpH, h->H, h->fpart, 0, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective pass");
-  if ((e = didk::reduce_f(h->fpart, didk::pass1_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
+  if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective reduce");
   return DID_OK;
 }
@@ -398,19 +400,19 @@ int did_iterate(did_handle h, int32_t n) {
 #define DID_MARK(q) \
   if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
     DID_MARK(0);
-    if ((e = didk::pass1(s, h->X, h->C, h->BpE, h->BpH, h->G, h->fpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::colpass(s, h->X, h->C, h->BpE, h->BpH, h->H, h->fpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "column pass");
     DID_MARK(1);
-    if ((e = didk::reduce_f(h->fpart, didk::pass1_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
+    if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
-    if ((e = didk::vgram(s, h->C, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
+    if ((e = didk::sweep(s, h->H, h->C, h->G, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
     DID_MARK(3);
-    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
+    if ((e = didk::reduce_full(h->Vpart, didk::sweep_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
     DID_MARK(4);
-    if ((e = didk::pass2(s, h->X, h->C, h->BpE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->X, h->C, h->BpE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");

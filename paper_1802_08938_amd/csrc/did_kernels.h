@@ -43,23 +43,25 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, f
                    float* BpH, double* Gpart, int update, hipStream_t st);
 int bupdate_blocks(const Shape& s);
 
-// Column pass: E = X - BC per 32-column tile, f partials, and (sweep=1) H = B^T E with the
-// Gram-form coordinate sweep writing C in place.  One partial of sum E^2 per block.
-hipError_t pass1(const Shape& s, const float* X, float* C, const float* BpE, const float* BpH,
-                 const double* G, double* fpart, int sweep, hipStream_t st);
-int64_t pass1_blocks(const Shape& s);
+// Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
+// (with_h = 1) H = B^T E written as KP x N floats (ld KP).
+hipError_t colpass(const Shape& s, const float* X, const float* C, const float* BpE, const float* BpH,
+                   float* Hout, double* fpart, int with_h, hipStream_t st);
+int64_t colpass_blocks(const Shape& s);
+
+// Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C; one
+// full KP x KP partial of C C^T per block into Vpart.
+hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, double* Vpart, hipStream_t st);
+int64_t sweep_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
-hipError_t pass2(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
-                 const int64_t* rbounds, int R, hipStream_t st);
-
-// V partials: tril(C C^T) per group of columns (float64).
-hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st);
-int64_t vgram_blocks(const Shape& s);
+hipError_t rowpass(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
+                   const int64_t* rbounds, int R, hipStream_t st);
 
 // Fixed-order reductions.
 hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStream_t st);
 hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st);
+hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st);
 
 }  // namespace didk

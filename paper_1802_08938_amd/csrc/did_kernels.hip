@@ -1,10 +1,11 @@
 // gfx950 kernels of the DID engine.
 //
 // One DID iteration (Alg. 3 of Gao & Chu, AAAI-18) is carried out as
-//   pass1   column pass over X: E = X - B C (MFMA), f partial = sum E^2 (float64),
-//           H = B^T E (MFMA) and the coordinate sweep over the rows of C,
-//   vgram   V = tril(C C^T) partials of the updated C (float64),
-//   pass2   row pass over X: E' = X - B C' (MFMA) and W = E' C'^T per column range (MFMA),
+//   colpass column pass over X: E = X - B C (MFMA), f partial = sum E^2 (float64),
+//           H = B^T E (MFMA),
+//   sweep   the coordinate sweep over the rows of C (float64, one thread per column) and
+//           V = C C^T partials of the updated C,
+//   rowpass row pass over X: E' = X - B C' (MFMA) and W = E' C'^T per column range (MFMA),
 //   reduce  fixed-order sums of the V, W and f partials (the paper's one Allreduce),
 //   bupdate incremental update of the columns of B, one thread per row of B.
 //
@@ -201,26 +202,28 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, f
 }
 
 // ------------------------------------------------------------------ column pass
-// Block = 4 waves = 128 consecutive columns; wave w owns columns j0 = 128*blockIdx + 32w
-// .. j0+31 and walks all M rows in 32-row chunks:
+// Block = 4 waves = 128 consecutive columns; wave w owns columns 128*blockIdx + 32w ..+31
+// and walks all M rows in 32-row chunks:
 //   acc  = X[chunk, cols]                        (E tile, accumulator layout)
-//   acc += (-B[chunk, :]) C[:, cols]             (K/2 MFMA steps)   -> E = X - B C
+//   acc += (-B[chunk, :]) C[:, cols]             (ceil(K/2) MFMA steps) -> E = X - B C
 //   fsum += sum acc^2                            (float64)
 //   H   += B[chunk, :]^T acc                     (16 MFMA steps per 32 rows of H)
-// then the sweep over c_j in float64 with G = B^T B staged in LDS, writing C in place.
-template <int KP, bool SWEEP>
-__global__ __launch_bounds__(256, 2) void k_pass1(const float* __restrict__ X, int64_t M, int64_t N, int K,
-                                                  float* __restrict__ C, const float* __restrict__ BpE,
-                                                  const float* __restrict__ BpH, const double* __restrict__ G,
-                                                  double* __restrict__ fpart, int64_t nchunks, int vec4) {
+// The packed B operands of chunk c+1 are staged into LDS (double buffer shared by the four
+// waves) and the X tile of chunk c+1 is loaded into registers while chunk c is computed.
+// H is written as KP x N (ld KP) for the sweep kernel.
+template <int KP, bool WITH_H>
+__global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
+                                                    const float* __restrict__ C, const float* __restrict__ BpE,
+                                                    const float* __restrict__ BpH, float* __restrict__ Hout,
+                                                    double* __restrict__ fpart, int64_t nchunks, int vec4) {
   constexpr int NB = KP / 32;
   constexpr int KS2 = KP / 2;
-  __shared__ double Gs[SWEEP ? KP * KP : 1];
-  __shared__ float Hs[SWEEP ? 4 * KP * 33 : 1];
+  constexpr int CH = KP * 32;                    // floats of one packed operand chunk
+  constexpr int STG4 = (WITH_H ? 2 * CH : CH) / 4;  // float4 staged per chunk
+  constexpr int NV4 = STG4 / 256;                 // float4 per thread per chunk
+  __shared__ f32x4 sb[2][STG4];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  if (SWEEP)
-    for (int q = tid; q < KP * KP; q += 256) Gs[q] = G[q];
   const int KSr = (K + 1) >> 1;
   const int64_t col = (int64_t)blockIdx.x * 128 + wave * 32 + lc;
   const bool colok = col < N;
@@ -239,24 +242,56 @@ __global__ __launch_bounds__(256, 2) void k_pass1(const float* __restrict__ X, i
     for (int i = 0; i < 16; ++i) H[b][i] = 0.0f;
   double fs0 = 0.0, fs1 = 0.0;
 
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int64_t m0 = c * 32;
-    f32x16 acc;
+  f32x4 stg[NV4];
+  auto gload = [&](int64_t c) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t rb = m0 + 8 * q + 4 * half;
-      if (colok && vec4 && rb + 3 < M) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(xcol + rb);
-        acc[4 * q + 0] = v[0];
-        acc[4 * q + 1] = v[1];
-        acc[4 * q + 2] = v[2];
-        acc[4 * q + 3] = v[3];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[4 * q + e] = (colok && rb + e < M) ? xcol[rb + e] : 0.0f;
-      }
+    for (int v = 0; v < NV4; ++v) {
+      const int idx = tid + 256 * v;
+      if (!WITH_H || idx < CH / 4)
+        stg[v] = reinterpret_cast<const f32x4*>(BpE + c * (int64_t)CH)[idx];
+      else
+        stg[v] = reinterpret_cast<const f32x4*>(BpH + c * (int64_t)CH)[idx - CH / 4];
     }
-    const f32x4* pe = reinterpret_cast<const f32x4*>(BpE + c * (int64_t)KP * 32) + l;
+  };
+  auto xload = [&](int64_t c) {
+    f32x16 v;
+    const int64_t m0 = c * 32;
+    if (colok && vec4 && m0 + 32 <= M) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 t = *reinterpret_cast<const f32x4*>(xcol + m0 + 8 * q + 4 * half);
+        v[4 * q + 0] = t[0];
+        v[4 * q + 1] = t[1];
+        v[4 * q + 2] = t[2];
+        v[4 * q + 3] = t[3];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = m0 + 8 * q + 4 * half + e;
+          v[4 * q + e] = (colok && r < M) ? xcol[r] : 0.0f;
+        }
+    }
+    return v;
+  };
+
+  gload(0);
+  f32x16 xn = xload(0);
+#pragma unroll
+  for (int v = 0; v < NV4; ++v) sb[0][tid + 256 * v] = stg[v];
+  __syncthreads();
+
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int buf = (int)(c & 1);
+    f32x16 acc = xn;
+    const bool more = c + 1 < nchunks;
+    if (more) {
+      gload(c + 1);
+      xn = xload(c + 1);
+    }
+    const f32x4* pe = &sb[buf][0] + l;
 #pragma unroll
     for (int s4 = 0; s4 < KP / 8; ++s4) {
       if (4 * s4 < KSr) {
@@ -271,8 +306,8 @@ __global__ __launch_bounds__(256, 2) void k_pass1(const float* __restrict__ X, i
       fs0 += (double)acc[i] * (double)acc[i];
       fs1 += (double)acc[i + 1] * (double)acc[i + 1];
     }
-    if (SWEEP) {
-      const f32x4* ph = reinterpret_cast<const f32x4*>(BpH + c * (int64_t)KP * 32) + l;
+    if (WITH_H) {
+      const f32x4* ph = &sb[buf][CH / 4] + l;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -282,36 +317,26 @@ __global__ __launch_bounds__(256, 2) void k_pass1(const float* __restrict__ X, i
           for (int u = 0; u < 4; ++u) H[b] = mfma32(a[u], acc[4 * i4 + u], H[b]);
         }
     }
+    if (more) {
+#pragma unroll
+      for (int v = 0; v < NV4; ++v) sb[buf ^ 1][tid + 256 * v] = stg[v];
+    }
+    __syncthreads();
   }
 
-  if (SWEEP) {
-    float* hs = Hs + wave * KP * 33;
+  if (WITH_H && colok) {
+    float* hcol = Hout + col * KP;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) hs[(32 * b + row32(i, half)) * 33 + lc] = H[b][i];
-    __syncthreads();  // Gs and this wave's Hs visible
-    if (half == 0 && colok) {
-      double h[KP];
-#pragma unroll
-      for (int k = 0; k < KP; ++k) h[k] = (double)hs[k * 33 + lc];
-      float* ccol = C + col * K;
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        if (k < K) {
-          const double nk = Gs[k * KP + k];
-          if (nk > 0.0) {
-            const double cold = (double)ccol[k];
-            double cn = cold + h[k] / nk;
-            cn = cn > 0.0 ? cn : 0.0;
-            const double d = cn - cold;
-            ccol[k] = (float)cn;
-#pragma unroll
-            for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * KP + k] * d;
-          }
-        }
+      for (int q = 0; q < 4; ++q) {
+        f32x4 v;
+        v[0] = H[b][4 * q + 0];
+        v[1] = H[b][4 * q + 1];
+        v[2] = H[b][4 * q + 2];
+        v[3] = H[b][4 * q + 3];
+        *reinterpret_cast<f32x4*>(hcol + 32 * b + 8 * q + 4 * half) = v;
       }
-    }
   }
 
   double fsum = fs0 + fs1;
@@ -322,22 +347,124 @@ __global__ __launch_bounds__(256, 2) void k_pass1(const float* __restrict__ X, i
   if (tid == 0) fpart[blockIdx.x] = (fw[0] + fw[1]) + (fw[2] + fw[3]);
 }
 
-int64_t pass1_blocks(const Shape& s) { return (s.N + 127) / 128; }
+int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
-hipError_t pass1(const Shape& s, const float* X, float* C, const float* BpE, const float* BpH, const double* G,
-                 double* fpart, int sweep, hipStream_t st) {
-  const unsigned g = (unsigned)pass1_blocks(s);
+hipError_t colpass(const Shape& s, const float* X, const float* C, const float* BpE, const float* BpH, float* Hout,
+                   double* fpart, int with_h, hipStream_t st) {
+  const unsigned g = (unsigned)colpass_blocks(s);
   if (s.KP == 32) {
-    if (sweep)
-      k_pass1<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, G, fpart, s.nchunks, s.vec4);
+    if (with_h)
+      k_colpass<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_pass1<32, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, G, fpart, s.nchunks, s.vec4);
+      k_colpass<32, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
   } else {
-    if (sweep)
-      k_pass1<64, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, G, fpart, s.nchunks, s.vec4);
+    if (with_h)
+      k_colpass<64, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_pass1<64, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, G, fpart, s.nchunks, s.vec4);
+      k_colpass<64, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ coordinate sweep
+// One thread per column j.  With h = B^T e_j from the column pass and G = B^T B in LDS, the
+// coordinates are updated in ascending order in float64:
+//   c_kj := [c_kj + h_k / G_kk]_+,  then h_q -= G_qk (c_kj^new - c_kj^old) for q > k,
+// which is eq. up:c with b_q^T e_j kept up to date through inner products; a coordinate
+// with G_kk = 0 (zero column of B) is skipped.  The updated column is written back to C
+// and staged in LDS, where the block adds its columns' outer products c_j c_j^T to its V
+// partial (thread t owns the 4x4 block (t / (KP/4), t % (KP/4)) of V).
+constexpr int kSweepTiles = 1024;  // upper bound on blocks (V partials) of the sweep
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C, int64_t N, int K,
+                                               const double* __restrict__ G, double* __restrict__ Vpart) {
+  constexpr int CS = KP + 4;  // LDS row stride of the staged columns
+  constexpr int NBL = KP / 4;
+  __shared__ double Gs[KP * KP];
+  __shared__ float Ct[256 * CS];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < KP * KP; q += 256) Gs[q] = G[q];
+  const int ab = tid / NBL, bb = tid % NBL;
+  const bool vown = tid < NBL * NBL;
+  double vacc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) vacc[q] = 0.0;
+  const int64_t ntiles = (N + 255) / 256;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // Gs ready (first pass); Ct free (later passes)
+    const int64_t col = tile * 256 + tid;
+    const bool colok = col < N;
+    double h[KP];
+    if (colok) {
+      const f32x4* hp = reinterpret_cast<const f32x4*>(Hin + col * KP);
+#pragma unroll
+      for (int q = 0; q < KP / 4; ++q) {
+        const f32x4 v = hp[q];
+        h[4 * q + 0] = v[0];
+        h[4 * q + 1] = v[1];
+        h[4 * q + 2] = v[2];
+        h[4 * q + 3] = v[3];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) h[k] = 0.0;
+    }
+    float* ccol = C + (colok ? col : 0) * K;
+    float* crow = Ct + tid * CS;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      float cnew = 0.0f;
+      if (k < K && colok) {
+        const double cold = (double)ccol[k];
+        double cn = cold;
+        const double nk = Gs[k * KP + k];
+        if (nk > 0.0) {
+          cn = cold + h[k] / nk;
+          cn = cn > 0.0 ? cn : 0.0;
+          const double d = cn - cold;
+#pragma unroll
+          for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * KP + k] * d;
+        }
+        cnew = (float)cn;
+        ccol[k] = cnew;
+      }
+      crow[k] = cnew;
+    }
+    __syncthreads();
+    if (vown) {
+      for (int j = 0; j < 256; ++j) {
+        const f32x4 ca = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * ab);
+        const f32x4 cb = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * bb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) vacc[4 * r + q] += (double)ca[r] * (double)cb[q];
+      }
+    }
+  }
+  if (vown) {
+    double* vp = Vpart + (int64_t)blockIdx.x * KP * KP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vp[(4 * ab + r) * KP + 4 * bb + q] = vacc[4 * r + q];
+  } else {
+    // threads without a V block (KP = 32 uses 64 of 256) have nothing to write
+  }
+}
+
+int64_t sweep_blocks(const Shape& s) {
+  const int64_t t = (s.N + 255) / 256;
+  return t < kSweepTiles ? t : kSweepTiles;
+}
+
+hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, double* Vpart, hipStream_t st) {
+  const unsigned g = (unsigned)sweep_blocks(s);
+  if (s.KP == 32)
+    k_sweep<32><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G, Vpart);
+  else
+    k_sweep<64><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G, Vpart);
   return hipGetLastError();
 }
 
@@ -347,25 +474,31 @@ hipError_t pass1(const Shape& s, const float* X, float* C, const float* BpE, con
 //   acc  = X[chunk, cols]^T
 //   acc += C[:, cols]^T (-B[chunk, :])^T          -> E'^T with E' = X - B C'
 //   WT  += C[:, cols] acc                          -> (E' C'^T)^T for this chunk
+// The C' tile of the next 32 columns is staged into LDS in both MFMA operand orders
+// (double buffer shared by the four waves); X of the next tile is prefetched.
 template <int KP>
-__global__ __launch_bounds__(256, 2) void k_pass2(const float* __restrict__ X, int64_t M, int K,
-                                                  const float* __restrict__ C, const float* __restrict__ BpE,
-                                                  float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
-                                                  const int64_t* __restrict__ rbounds) {
+__global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X, int64_t M, int K,
+                                                    const float* __restrict__ C, const float* __restrict__ BpE,
+                                                    float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
+                                                    const int64_t* __restrict__ rbounds) {
   constexpr int NB = KP / 32;
   constexpr int KS2 = KP / 2;
+  constexpr int TE = KP * 32;      // floats of the E-operand tile
+  constexpr int TT = 2 * KP * 32;  // floats of both tiles
+  constexpr int NEL = KP / 8;      // tile elements per thread (32 * KP / 256)
+  __shared__ float sc[2][TT];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
   const int64_t c = (int64_t)blockIdx.x * 4 + wave;
-  if (c >= nchunks) return;
+  const bool active = c < nchunks;  // inactive waves still take part in staging and barriers
   const int r = blockIdx.y;
   const int64_t lo = rbounds[r], hi = rbounds[r + 1];
-  const int64_t m0 = c * 32, mrow = m0 + lc;
-  const bool rowok = mrow < M;
+  const int64_t m0 = (active ? c : 0) * 32, mrow = m0 + lc;
+  const bool rowok = active && mrow < M;
   const int KSr = (K + 1) >> 1;
 
   float bneg[KS2];
   {
-    const f32x4* pe = reinterpret_cast<const f32x4*>(BpE + c * (int64_t)KP * 32) + l;
+    const f32x4* pe = reinterpret_cast<const f32x4*>(BpE + (active ? c : 0) * (int64_t)KP * 32) + l;
 #pragma unroll
     for (int s4 = 0; s4 < KP / 8; ++s4) {
       const f32x4 a = pe[s4 * 64];
@@ -379,104 +512,100 @@ __global__ __launch_bounds__(256, 2) void k_pass2(const float* __restrict__ X, i
 #pragma unroll
     for (int i = 0; i < 16; ++i) WT[b][i] = 0.0f;
 
-  for (int64_t j0 = lo; j0 < hi; j0 += 32) {
-    f32x16 acc;
+  // staging of tile elements e = tid + 256 v: jj = e / KP (column in tile), kk = e % KP
+  float stv[NEL];
+  auto cload = [&](int64_t j0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int64_t j = j0 + row32(i, half);
-      acc[i] = (rowok && j < hi) ? X[j * M + mrow] : 0.0f;
+    for (int v = 0; v < NEL; ++v) {
+      const int e = tid + 256 * v, jj = e / KP, kk = e % KP;
+      stv[v] = (j0 + jj < hi && kk < K) ? C[(j0 + jj) * K + kk] : 0.0f;
     }
-    const int64_t ja = j0 + lc;
-    const bool jaok = ja < hi;
+  };
+  auto cstore = [&](int buf) {
 #pragma unroll
-    for (int s = 0; s < KS2; ++s) {
-      if (s < KSr) {
-        const int kk = 2 * s + half;
-        const float a = (jaok && kk < K) ? C[ja * K + kk] : 0.0f;
-        acc = mfma32(a, bneg[s], acc);
+    for (int v = 0; v < NEL; ++v) {
+      const int e = tid + 256 * v, jj = e / KP, kk = e % KP;
+      {  // A operand of E'^T: lane l, step s -> C'[2s + l/32][j0 + l%32]
+        const int s = kk >> 1, hh = kk & 1, ln = jj + 32 * hh;
+        sc[buf][((s >> 2) * 64 + ln) * 4 + (s & 3)] = stv[v];
+      }
+      {  // A operand of W^T: block b, step i -> C'[32b + l%32][j0 + row32(i, l/32)]
+        const int b = kk >> 5, i4 = jj >> 3, hh = (jj >> 2) & 1, u = jj & 3, ln = (kk & 31) + 32 * hh;
+        sc[buf][TE + ((b * 4 + i4) * 64 + ln) * 4 + u] = stv[v];
       }
     }
+  };
+  const float* xrow = X + mrow;
+  auto xload = [&](int64_t j0) {
+    f32x16 v;
+    if (rowok && j0 + 32 <= hi) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int kk = 32 * b + lc;
+      for (int i = 0; i < 16; ++i) v[i] = xrow[(j0 + row32(i, half)) * M];
+    } else {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int64_t jj = j0 + row32(i, half);
-        const float a = (jj < hi && kk < K) ? C[jj * K + kk] : 0.0f;
-        WT[b] = mfma32(a, acc[i], WT[b]);
+        const int64_t j = j0 + row32(i, half);
+        v[i] = (rowok && j < hi) ? xrow[j * M] : 0.0f;
       }
     }
+    return v;
+  };
+
+  if (lo < hi) {
+    cload(lo);
+    f32x16 xn = xload(lo);
+    cstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = lo; j0 < hi; j0 += 32) {
+      f32x16 acc = xn;
+      const bool more = j0 + 32 < hi;
+      if (more) {
+        cload(j0 + 32);
+        xn = xload(j0 + 32);
+      }
+      if (active) {
+        const f32x4* pe = reinterpret_cast<const f32x4*>(&sc[buf][0]) + l;
+#pragma unroll
+        for (int s4 = 0; s4 < KP / 8; ++s4) {
+          if (4 * s4 < KSr) {
+            const f32x4 a = pe[s4 * 64];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (4 * s4 + u < KSr) acc = mfma32(a[u], bneg[4 * s4 + u], acc);
+          }
+        }
+        const f32x4* pw = reinterpret_cast<const f32x4*>(&sc[buf][TE]) + l;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int i4 = 0; i4 < 4; ++i4) {
+            const f32x4 a = pw[(b * 4 + i4) * 64];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) WT[b] = mfma32(a[u], acc[4 * i4 + u], WT[b]);
+          }
+      }
+      if (more) cstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
-  float* wp = Wpart + (int64_t)r * KP * Mpad;
+  if (active) {
+    float* wp = Wpart + (int64_t)r * KP * Mpad;
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) wp[(int64_t)(32 * b + row32(i, half)) * Mpad + m0 + lc] = WT[b][i];
+      for (int i = 0; i < 16; ++i) wp[(int64_t)(32 * b + row32(i, half)) * Mpad + m0 + lc] = WT[b][i];
+  }
 }
 
-hipError_t pass2(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
-                 const int64_t* rbounds, int R, hipStream_t st) {
+hipError_t rowpass(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
+                   const int64_t* rbounds, int R, hipStream_t st) {
   dim3 g((unsigned)((s.nchunks + 3) / 4), (unsigned)R);
   if (s.KP == 32)
-    k_pass2<32><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
+    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
   else
-    k_pass2<64><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ V = tril(C C^T)
-// Block b owns VG tiles of 256 consecutive columns; a tile of C is contiguous in memory.
-constexpr int kVTiles = 16;
-
-template <int KP>
-__global__ __launch_bounds__(256) void k_vgram(const float* __restrict__ C, int64_t N, int K,
-                                               double* __restrict__ Vpart) {
-  constexpr int NP = KP * (KP + 1) / 2;
-  constexpr int NQ = (NP + 255) / 256;
-  __shared__ float Cs[256 * KP];
-  const int tid = threadIdx.x;
-  int qa[NQ], qb[NQ];
-  double acc[NQ];
-#pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    const int q = tid + 256 * t;
-    if (q < NP) pair_of(q, qa[t], qb[t]);
-    else qa[t] = qb[t] = 0;
-    acc[t] = 0.0;
-  }
-  for (int vt = 0; vt < kVTiles; ++vt) {
-    const int64_t j0 = ((int64_t)blockIdx.x * kVTiles + vt) * 256;
-    if (j0 >= N) break;  // uniform across the block
-    const int64_t nv = (N - j0) < 256 ? (N - j0) : 256;
-    __syncthreads();
-    for (int64_t t = tid; t < nv * K; t += 256) Cs[t] = C[j0 * K + t];
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-      const int q = tid + 256 * t;
-      if (q < NP && qa[t] < K) {
-        const int a = qa[t], b = qb[t];
-        double s = 0.0;
-        for (int j = 0; j < nv; ++j) s += (double)Cs[j * K + a] * (double)Cs[j * K + b];
-        acc[t] += s;
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    const int q = tid + 256 * t;
-    if (q < NP) Vpart[(int64_t)blockIdx.x * NP + q] = acc[t];
-  }
-}
-
-int64_t vgram_blocks(const Shape& s) { return (s.N + 256 * kVTiles - 1) / (256 * kVTiles); }
-
-hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st) {
-  const unsigned g = (unsigned)vgram_blocks(s);
-  if (s.KP == 32)
-    k_vgram<32><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
-  else
-    k_vgram<64><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
+    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
   return hipGetLastError();
 }
 
@@ -493,6 +622,21 @@ __global__ void k_reduce_w(const float* __restrict__ Wpart, int R, int64_t n, do
 hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStream_t st) {
   const int64_t n = (int64_t)s.KP * s.Mpad;
   k_reduce_w<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(Wpart, R, n, W);
+  return hipGetLastError();
+}
+
+// full[i] = sum_p part[p][i] over KP*KP entries, p ascending.
+__global__ void k_reduce_full(const double* __restrict__ part, int64_t P, int n, double* __restrict__ full) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double s = 0.0;
+  for (int64_t p = 0; p < P; ++p) s += part[p * n + q];
+  full[q] = s;
+}
+
+hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipStream_t st) {
+  const int n = KP * KP;
+  k_reduce_full<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(part, P, n, full);
   return hipGetLastError();
 }
 
