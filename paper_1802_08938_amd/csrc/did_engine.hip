@@ -33,7 +33,7 @@ constexpr int64_t kHistCap = 1 << 16;
 
 // Kernel stages of one iteration, in launch order.
 constexpr int kStages = 8;
-const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "sweep",    "reduce_v",
+const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "sweep_v",  "reduce_v",
                                           "row_pass",    "reduce_w", "b_update", "reduce_g"};
 
 }  // namespace
@@ -47,8 +47,8 @@ struct did_ctx {
   float* X = nullptr;
   float* B = nullptr;
   float* C = nullptr;
-  float* BpE = nullptr;
-  float* BpH = nullptr;
+  __bf16* BqE = nullptr;
+  __bf16* BqH = nullptr;
   double* G = nullptr;
   double* Gpart = nullptr;
   double* V = nullptr;
@@ -199,12 +199,12 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   h->R = (int)rb.size() - 1;
   if ((rc = dalloc(h, &h->B, M * K))) return rc;
   if ((rc = dalloc(h, &h->C, (int64_t)K * N))) return rc;
-  if ((rc = dalloc(h, &h->BpE, didk::packed_b_floats(s)))) return rc;
-  if ((rc = dalloc(h, &h->BpH, didk::packed_b_floats(s)))) return rc;
+  if ((rc = dalloc(h, &h->BqE, didk::packed_b_elems(s)))) return rc;
+  if ((rc = dalloc(h, &h->BqH, didk::packed_b_elems(s)))) return rc;
   if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
-  if ((rc = dalloc(h, &h->Vpart, didk::sweep_blocks(s) * s.KP * s.KP))) return rc;
+  if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
   if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
   if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
@@ -215,8 +215,8 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->flag, 1))) return rc;
 
   hipError_t e;
-  if ((e = hipMemsetAsync(h->BpE, 0, (size_t)didk::packed_b_floats(s) * 4, h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->BpH, 0, (size_t)didk::packed_b_floats(s) * 4, h->st)) != hipSuccess ||
+  if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
       (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
@@ -233,7 +233,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
 
 // Pack B and form G = B^T B.
 hipError_t refresh_b_derived(did_ctx* h) {
-  hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->BpE, h->BpH, h->Gpart, 0, h->st);
+  hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st);
   if (e != hipSuccess) return e;
   return didk::reduce_sym(h->Gpart, didk::bupdate_blocks(h->s), h->s.KP, h->G, h->st);
 }
@@ -246,7 +246,7 @@ int check_handle(did_ctx* h) {
 
 int objective_pass(did_ctx* h) {
   hipError_t e;
-  if ((e = didk::colpass(h->s, h->X, h->C, h->BpE, h->BpH, h->H, h->fpart, 0, h->st)) != hipSuccess)
+  if ((e = didk::colpass(h->s, h->X, h->C, h->BqE, h->BqH, h->H, h->fpart, 0, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective pass");
   if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective reduce");
@@ -400,24 +400,25 @@ int did_iterate(did_handle h, int32_t n) {
 #define DID_MARK(q) \
   if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
     DID_MARK(0);
-    if ((e = didk::colpass(s, h->X, h->C, h->BpE, h->BpH, h->H, h->fpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::colpass(s, h->X, h->C, h->BqE, h->BqH, h->H, h->fpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "column pass");
     DID_MARK(1);
     if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->G, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    if ((e = didk::sweep(s, h->H, h->C, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    if ((e = didk::vgram(s, h->C, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
     DID_MARK(3);
-    if ((e = didk::reduce_full(h->Vpart, didk::sweep_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
+    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->X, h->C, h->BpE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->X, h->C, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
     DID_MARK(6);
-    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BpE, h->BpH, h->Gpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "B update");
     DID_MARK(7);
     if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)

@@ -16,8 +16,9 @@ struct Shape {
   int vec4;          // X column starts are 16-byte aligned (M % 4 == 0 and X aligned)
 };
 
-// Number of float32 entries of one packed-operand buffer (E-operand or H-operand) of B.
-inline int64_t packed_b_floats(const Shape& s) { return s.nchunks * (int64_t)s.KP * 32; }
+// Number of bf16 entries of one packed-operand buffer (E-operand or H-operand) of B:
+// per 32-row chunk, KP x 32 values in three pieces.
+inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)s.KP * 32 * 3; }
 inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
 
 // splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
@@ -36,26 +37,28 @@ hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
 hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
-// Pack B into MFMA operand order, optionally applying the incremental B update from the
+// Pack B (three bf16 pieces per entry) into MFMA operand order, optionally applying the incremental B update from the
 // reduced messages W (KP x Mpad, float64) and V (KP x KP, float64); writes per-block
 // partials of B^T B into Gpart (n_pairs(KP) doubles per block).  Grid: ceil(M/256).
-hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, float* BpE,
-                   float* BpH, double* Gpart, int update, hipStream_t st);
+hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, __bf16* BqE,
+                   __bf16* BqH, double* Gpart, int update, hipStream_t st);
 int bupdate_blocks(const Shape& s);
 
 // Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
-// (with_h = 1) H = B^T E written as KP x N floats (ld KP).
-hipError_t colpass(const Shape& s, const float* X, const float* C, const float* BpE, const float* BpH,
+// (with_h = 1) H = B^T E written as KP x N floats, row kk contiguous (index kk * N + j).
+hipError_t colpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, const __bf16* BqH,
                    float* Hout, double* fpart, int with_h, hipStream_t st);
 int64_t colpass_blocks(const Shape& s);
 
-// Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C; one
-// full KP x KP partial of C C^T per block into Vpart.
-hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, double* Vpart, hipStream_t st);
-int64_t sweep_blocks(const Shape& s);
+// Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C.
+hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, hipStream_t st);
+
+// V partials: tril(C C^T) per block of columns (float64, n_pairs(KP) per block).
+hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st);
+int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
-hipError_t rowpass(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
+hipError_t rowpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, float* Wpart,
                    const int64_t* rbounds, int R, hipStream_t st);
 
 // Fixed-order reductions.

@@ -3,8 +3,8 @@
 // One DID iteration (Alg. 3 of Gao & Chu, AAAI-18) is carried out as
 //   colpass column pass over X: E = X - B C (MFMA), f partial = sum E^2 (float64),
 //           H = B^T E (MFMA),
-//   sweep   the coordinate sweep over the rows of C (float64, one thread per column) and
-//           V = C C^T partials of the updated C,
+//   sweep   the coordinate sweep over the rows of C (float64, one thread per column),
+//   vgram   V = tril(C C^T) partials of the updated C (float64),
 //   rowpass row pass over X: E' = X - B C' (MFMA) and W = E' C'^T per column range (MFMA),
 //   reduce  fixed-order sums of the V, W and f partials (the paper's one Allreduce),
 //   bupdate incremental update of the columns of B, one thread per row of B.
@@ -17,11 +17,12 @@
 // v_ik delta b_k term); it turns the K dependent length-M reductions of the sweep into
 // one MFMA contraction plus O(K^2) float64 work per column.
 //
-// MFMA lane layouts used (v_mfma_f32_32x32x2_f32, one block): lane l supplies A[l%32][l/32]
-// and B[l/32][l%32]; accumulator register i of lane l holds D[row32(i, l/32)][l%32] with
-// row32(i, h) = 8*(i/4) + 4*h + i%4.  Because the accumulator's row index pairs with
-// l/32, accumulator register i can be fed back directly as the B operand of a second
-// 32x32x2 MFMA that reduces over those two rows; no lane shuffles are needed.
+// MFMA lane layouts used (v_mfma_f32_32x32x16_bf16): lane l supplies A[l%32][8(l/32) + t]
+// and B[8(l/32) + t][l%32], t = 0..7; accumulator register i of lane l holds
+// D[row32(i, l/32)][l%32] with row32(i, h) = 8*(i/4) + 4*h + i%4.  Because the
+// accumulator's row index pairs with l/32, accumulator registers 8q..8q+7 can be fed back
+// directly (after the bf16 split) as the B operand of a second MFMA that reduces over
+// those sixteen rows; no lane shuffles are needed.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -32,12 +33,61 @@ namespace didk {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int row32(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
 
-__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+// v_mfma_f32_32x32x16_bf16: D(32x32, fp32) += A(32x16) B(16x32); lane l supplies
+// A[l%32][8(l/32) + t] and B[8(l/32) + t][l%32] for t = 0..7; D as for 32x32x2.
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
+
+// Exact three-way split of float32 values into bf16 pieces: x = hi + mid + lo with
+// hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid) (round to nearest even; the
+// two differences are exact in float32), so hi + mid + lo carries x to within 2^-24
+// relative.  A float32 product a*b is then formed to float32 accuracy by the six bf16
+// products whose weight is above 2^-24: hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi
+// (each exact in float32 and accumulated in float32 by the MFMA).
+struct Split3 {
+  bf16x8 p[3];
+};
+
+__device__ __forceinline__ Split3 split3(const float (&v)[8]) {
+  Split3 r;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 h = (__bf16)v[t];
+    const float r1 = v[t] - (float)h;
+    const __bf16 m = (__bf16)r1;
+    const float r2 = r1 - (float)m;
+    r.p[0][t] = h;
+    r.p[1][t] = m;
+    r.p[2][t] = (__bf16)r2;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void split3_scalar(float v, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)v;
+  const float r1 = v - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+// acc += a * b as six bf16 MFMAs, smallest terms first.
+__device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x16 acc) {
+  acc = mfma16(a[2], b[0], acc);
+  acc = mfma16(a[1], b[1], acc);
+  acc = mfma16(a[0], b[2], acc);
+  acc = mfma16(a[1], b[0], acc);
+  acc = mfma16(a[0], b[1], acc);
+  acc = mfma16(a[0], b[0], acc);
+  return acc;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
 
 // Pair index q -> (a, b) with a >= b, q = a(a+1)/2 + b.
 __device__ __forceinline__ void pair_of(int q, int& a, int& b) {
@@ -108,45 +158,49 @@ hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t 
 }
 
 // ------------------------------------------------------------------ B update + packing
-// Packed operand buffers of B (rows >= M and columns >= K stay zero from allocation):
-//   BpE[((c*(KP/8) + s/4)*64 + l)*4 + s%4] = -B[32c + l%32][2s + l/32]
-//       (A operand of E = X - B C in the column pass; B operand of E' in the row pass)
-//   BpH[((c*(KP/32)*4 + b*4 + i/4)*64 + l)*4 + i%4] = B[32c + row32(i, l/32)][32b + l%32]
-//       (A operand of H = B^T E in the column pass)
-// so that each lane fetches four consecutive MFMA steps with one 16-byte load.
+// Packed operand buffers of B, each entry split into its three bf16 pieces p = 0, 1, 2
+// (rows >= M and columns >= K stay zero from allocation).  A 16-byte unit holds the eight
+// bf16 values lane l feeds to one MFMA:
+//   BqE unit ((c*(KP/16) + s)*3 + p)*64 + l, element t: piece p of -B[32c + l%32][16s + 8(l/32) + t]
+//       (A operand of E = X - B C in the column pass; B operand of E'^T in the row pass)
+//   BqH unit (((c*(KP/32) + b)*2 + q)*3 + p)*64 + l, element t:
+//       piece p of B[32c + row32(8q + t, l/32)][32b + l%32]   (A operand of H = B^T E)
 template <int KP>
-__device__ __forceinline__ void pack_entry(float* BpE, float* BpH, int64_t m, int kk, float v) {
+__device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, int kk, float v) {
   constexpr int NB = KP / 32;
   const int64_t c = m >> 5;
   const int r = (int)(m & 31);
+  __bf16 pc[3], nc[3];
+  split3_scalar(v, pc[0], pc[1], pc[2]);
+  split3_scalar(-v, nc[0], nc[1], nc[2]);
   {
-    const int s = kk >> 1, l = r + 32 * (kk & 1);
-    BpE[((c * (KP / 8) + (s >> 2)) * 64 + l) * 4 + (s & 3)] = -v;
+    const int s = kk >> 4, h = (kk >> 3) & 1, t = kk & 7, l = r + 32 * h;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) BqE[(((c * (KP / 16) + s) * 3 + p) * 64 + l) * 8 + t] = nc[p];
   }
   {
-    const int b = kk >> 5, l = 32 * ((r >> 2) & 1) + (kk & 31), i = 4 * (r >> 3) + (r & 3);
-    BpH[((c * NB * 4 + b * 4 + (i >> 2)) * 64 + l) * 4 + (i & 3)] = v;
+    const int i = 4 * (r >> 3) + (r & 3), h = (r >> 2) & 1, q = i >> 3, t = i & 7;
+    const int b = kk >> 5, l = (kk & 31) + 32 * h;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) BqH[((((c * NB + b) * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
   }
 }
 
-// One thread per row m of B.  With update=1 the row follows the incremental rule of
-// Section 4 (Alg. 3, 'Update B'):
-//   b_mi := [b_mi + (w_mi - sum_{k<i} v_ik delta b_mk) / v_ii]_+,  delta b_mi := new - old,
-// for i = 1..K in order, in float64; a column with v_ii = 0 is left unchanged.  Rows are
-// independent because V couples only the columns of one row.
+constexpr int kBupRows = 64;  // rows of B per block
+
 template <int KP>
-__global__ __launch_bounds__(256) void k_bupdate(float* __restrict__ B, int64_t M, int K,
+__global__ __launch_bounds__(kBupRows) void k_bupdate(float* __restrict__ B, int64_t M, int K,
                                                  const double* __restrict__ W, int64_t Mpad,
-                                                 const double* __restrict__ V, float* __restrict__ BpE,
-                                                 float* __restrict__ BpH, double* __restrict__ Gpart,
+                                                 const double* __restrict__ V, __bf16* __restrict__ BqE,
+                                                 __bf16* __restrict__ BqH, double* __restrict__ Gpart,
                                                  int update) {
   __shared__ double Vs[KP * KP];
-  __shared__ float Bt[256 * (KP + 1)];
+  __shared__ float Bt[kBupRows * (KP + 1)];
   const int tid = threadIdx.x;
   if (update)
-    for (int q = tid; q < KP * KP; q += 256) Vs[q] = V[q];
+    for (int q = tid; q < KP * KP; q += kBupRows) Vs[q] = V[q];
   __syncthreads();
-  const int64_t m = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t m = (int64_t)blockIdx.x * kBupRows + tid;
   const bool ok = m < M;
   double db[KP];
 #pragma unroll
@@ -170,18 +224,18 @@ __global__ __launch_bounds__(256) void k_bupdate(float* __restrict__ B, int64_t 
       }
       bnew = (float)bn;
       if (update) B[(int64_t)i * M + m] = bnew;
-      pack_entry<KP>(BpE, BpH, m, i, bnew);
+      pack_entry<KP>(BqE, BqH, m, i, bnew);
     }
     Bt[tid * (KP + 1) + i] = bnew;
   }
   __syncthreads();
   // Partial of G = B^T B over this block's rows, float64, pairs (a >= b).
   constexpr int NP = KP * (KP + 1) / 2;
-  for (int q = tid; q < NP; q += 256) {
+  for (int q = tid; q < NP; q += kBupRows) {
     int a, b;
     pair_of(q, a, b);
     double s0 = 0.0, s1 = 0.0;
-    for (int r = 0; r < 256; r += 2) {
+    for (int r = 0; r < kBupRows; r += 2) {
       s0 += (double)Bt[r * (KP + 1) + a] * (double)Bt[r * (KP + 1) + b];
       s1 += (double)Bt[(r + 1) * (KP + 1) + a] * (double)Bt[(r + 1) * (KP + 1) + b];
     }
@@ -189,15 +243,15 @@ __global__ __launch_bounds__(256) void k_bupdate(float* __restrict__ B, int64_t 
   }
 }
 
-int bupdate_blocks(const Shape& s) { return (int)((s.M + 255) / 256); }
+int bupdate_blocks(const Shape& s) { return (int)((s.M + kBupRows - 1) / kBupRows); }
 
-hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, float* BpE, float* BpH,
+hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, __bf16* BqE, __bf16* BqH,
                    double* Gpart, int update, hipStream_t st) {
   const unsigned g = (unsigned)bupdate_blocks(s);
   if (s.KP == 32)
-    k_bupdate<32><<<g, 256, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BpE, BpH, Gpart, update);
+    k_bupdate<32><<<g, kBupRows, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
   else
-    k_bupdate<64><<<g, 256, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BpE, BpH, Gpart, update);
+    k_bupdate<64><<<g, kBupRows, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
   return hipGetLastError();
 }
 
@@ -205,35 +259,45 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, f
 // Block = 4 waves = 128 consecutive columns; wave w owns columns 128*blockIdx + 32w ..+31
 // and walks all M rows in 32-row chunks:
 //   acc  = X[chunk, cols]                        (E tile, accumulator layout)
-//   acc += (-B[chunk, :]) C[:, cols]             (ceil(K/2) MFMA steps) -> E = X - B C
+//   acc += (-B[chunk, :]) C[:, cols]             (ceil(K/16) split-bf16 steps) -> E = X - B C
 //   fsum += sum acc^2                            (float64)
-//   H   += B[chunk, :]^T acc                     (16 MFMA steps per 32 rows of H)
-// The packed B operands of chunk c+1 are staged into LDS (double buffer shared by the four
-// waves) and the X tile of chunk c+1 is loaded into registers while chunk c is computed.
-// H is written as KP x N (ld KP) for the sweep kernel.
+//   H   += B[chunk, :]^T acc                     (2 split-bf16 steps per 32 rows of H)
+// Every float32 product is formed by six bf16 MFMAs over exact three-way splits (split3),
+// which keeps float32 accuracy at the bf16 MFMA rate.  The packed B pieces of chunk c+1
+// are staged into LDS (double buffer shared by the four waves) and the X tile of chunk
+// c+1 is loaded into registers while chunk c is computed.  H is written as KP x N with
+// row kk contiguous over the columns.
 template <int KP, bool WITH_H>
 __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const float* __restrict__ C, const float* __restrict__ BpE,
-                                                    const float* __restrict__ BpH, float* __restrict__ Hout,
+                                                    const float* __restrict__ C, const __bf16* __restrict__ BqE,
+                                                    const __bf16* __restrict__ BqH, float* __restrict__ Hout,
                                                     double* __restrict__ fpart, int64_t nchunks, int vec4) {
   constexpr int NB = KP / 32;
-  constexpr int KS2 = KP / 2;
-  constexpr int CH = KP * 32;                    // floats of one packed operand chunk
-  constexpr int STG4 = (WITH_H ? 2 * CH : CH) / 4;  // float4 staged per chunk
-  constexpr int NV4 = STG4 / 256;                 // float4 per thread per chunk
-  __shared__ f32x4 sb[2][STG4];
+  constexpr int KS = KP / 16;
+  constexpr int UE = KS * 3 * 64;              // 16-byte units of the E operand per chunk
+  constexpr int UH = NB * 2 * 3 * 64;          // 16-byte units of the H operand per chunk
+  constexpr int U = WITH_H ? UE + UH : UE;
+  constexpr int NV = (U + 255) / 256;          // units per thread per chunk
+  __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  const int KSr = (K + 1) >> 1;
+  const int KSr = (K + 15) >> 4;
   const int64_t col = (int64_t)blockIdx.x * 128 + wave * 32 + lc;
   const bool colok = col < N;
   const float* xcol = X + (colok ? col : 0) * M;
 
-  float creg[KS2];
+  bf16x8 cP[KS][3];  // pieces of C[16s + 8*half + t][col]
 #pragma unroll
-  for (int s = 0; s < KS2; ++s) {
-    const int kk = 2 * s + half;
-    creg[s] = (colok && kk < K) ? C[col * K + kk] : 0.0f;
+  for (int s = 0; s < KS; ++s) {
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int kk = 16 * s + 8 * half + t;
+      v[t] = (colok && kk < K) ? C[col * K + kk] : 0.0f;
+    }
+    const Split3 sp = split3(v);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) cP[s][p] = sp.p[p];
   }
   f32x16 H[NB];
 #pragma unroll
@@ -242,15 +306,22 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
     for (int i = 0; i < 16; ++i) H[b][i] = 0.0f;
   double fs0 = 0.0, fs1 = 0.0;
 
-  f32x4 stg[NV4];
+  f32x4 stg[NV];
   auto gload = [&](int64_t c) {
 #pragma unroll
-    for (int v = 0; v < NV4; ++v) {
-      const int idx = tid + 256 * v;
-      if (!WITH_H || idx < CH / 4)
-        stg[v] = reinterpret_cast<const f32x4*>(BpE + c * (int64_t)CH)[idx];
-      else
-        stg[v] = reinterpret_cast<const f32x4*>(BpH + c * (int64_t)CH)[idx - CH / 4];
+    for (int v = 0; v < NV; ++v) {
+      const int u = tid + 256 * v;
+      if (u < UE)
+        stg[v] = reinterpret_cast<const f32x4*>(BqE)[c * UE + u];
+      else if (WITH_H && u < U)
+        stg[v] = reinterpret_cast<const f32x4*>(BqH)[c * UH + (u - UE)];
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int u = tid + 256 * v;
+      if (u < U) sb[buf][u] = stg[v];
     }
   };
   auto xload = [&](int64_t c) {
@@ -279,8 +350,7 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 
   gload(0);
   f32x16 xn = xload(0);
-#pragma unroll
-  for (int v = 0; v < NV4; ++v) sb[0][tid + 256 * v] = stg[v];
+  sstore(0);
   __syncthreads();
 
   for (int64_t c = 0; c < nchunks; ++c) {
@@ -291,14 +361,14 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
       gload(c + 1);
       xn = xload(c + 1);
     }
-    const f32x4* pe = &sb[buf][0] + l;
+    const f32x4* ue = &sb[buf][0] + l;
 #pragma unroll
-    for (int s4 = 0; s4 < KP / 8; ++s4) {
-      if (4 * s4 < KSr) {
-        const f32x4 a = pe[s4 * 64];
+    for (int s = 0; s < KS; ++s) {
+      if (s < KSr) {
+        bf16x8 a[3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (4 * s4 + u < KSr) acc = mfma32(a[u], creg[4 * s4 + u], acc);
+        for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[(s * 3 + p) * 64]);
+        acc = mfma_x6(a, cP[s], acc);
       }
     }
 #pragma unroll
@@ -307,36 +377,36 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
       fs1 += (double)acc[i + 1] * (double)acc[i + 1];
     }
     if (WITH_H) {
-      const f32x4* ph = &sb[buf][CH / 4] + l;
+      bf16x8 eP[2][3];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
+        const Split3 sp = split3(v);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+      }
+      const f32x4* uh = &sb[buf][UE] + l;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i4 = 0; i4 < 4; ++i4) {
-          const f32x4 a = ph[(b * 4 + i4) * 64];
+        for (int q = 0; q < 2; ++q) {
+          bf16x8 a[3];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) H[b] = mfma32(a[u], acc[4 * i4 + u], H[b]);
+          for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(uh[((b * 2 + q) * 3 + p) * 64]);
+          H[b] = mfma_x6(a, eP[q], H[b]);
         }
     }
-    if (more) {
-#pragma unroll
-      for (int v = 0; v < NV4; ++v) sb[buf ^ 1][tid + 256 * v] = stg[v];
-    }
+    if (more) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  if (WITH_H && colok) {
-    float* hcol = Hout + col * KP;
+  if (WITH_H && colok) {  // row kk of H contiguous over columns: coalesced stores
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        f32x4 v;
-        v[0] = H[b][4 * q + 0];
-        v[1] = H[b][4 * q + 1];
-        v[2] = H[b][4 * q + 2];
-        v[3] = H[b][4 * q + 3];
-        *reinterpret_cast<f32x4*>(hcol + 32 * b + 8 * q + 4 * half) = v;
-      }
+      for (int i = 0; i < 16; ++i) Hout[(int64_t)(32 * b + row32(i, half)) * N + col] = H[b][i];
   }
 
   double fsum = fs0 + fs1;
@@ -349,19 +419,19 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
-hipError_t colpass(const Shape& s, const float* X, const float* C, const float* BpE, const float* BpH, float* Hout,
-                   double* fpart, int with_h, hipStream_t st) {
+hipError_t colpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, const __bf16* BqH,
+                   float* Hout, double* fpart, int with_h, hipStream_t st) {
   const unsigned g = (unsigned)colpass_blocks(s);
   if (s.KP == 32) {
     if (with_h)
-      k_colpass<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<32, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
   } else {
     if (with_h)
-      k_colpass<64, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<64, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BpE, BpH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
   }
   return hipGetLastError();
 }
@@ -371,100 +441,150 @@ hipError_t colpass(const Shape& s, const float* X, const float* C, const float* 
 // coordinates are updated in ascending order in float64:
 //   c_kj := [c_kj + h_k / G_kk]_+,  then h_q -= G_qk (c_kj^new - c_kj^old) for q > k,
 // which is eq. up:c with b_q^T e_j kept up to date through inner products; a coordinate
-// with G_kk = 0 (zero column of B) is skipped.  The updated column is written back to C
-// and staged in LDS, where the block adds its columns' outer products c_j c_j^T to its V
-// partial (thread t owns the 4x4 block (t / (KP/4), t % (KP/4)) of V).
-constexpr int kSweepTiles = 1024;  // upper bound on blocks (V partials) of the sweep
-
+// with G_kk = 0 (zero column of B) is skipped.  The updated column is written back to C.
 template <int KP>
 __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C, int64_t N, int K,
-                                               const double* __restrict__ G, double* __restrict__ Vpart) {
-  constexpr int CS = KP + 4;  // LDS row stride of the staged columns
-  constexpr int NBL = KP / 4;
+                                               const double* __restrict__ G) {
   __shared__ double Gs[KP * KP];
-  __shared__ float Ct[256 * CS];
   const int tid = threadIdx.x;
   for (int q = tid; q < KP * KP; q += 256) Gs[q] = G[q];
-  const int ab = tid / NBL, bb = tid % NBL;
-  const bool vown = tid < NBL * NBL;
-  double vacc[16];
+  __syncthreads();
+  const int64_t col = (int64_t)blockIdx.x * 256 + tid;
+  if (col >= N) return;  // no barrier below
+  double h[KP];
+  float cv[KP];
+  float* ccol = C + col * K;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) vacc[q] = 0.0;
+  for (int k = 0; k < KP; ++k) {
+    h[k] = (double)Hin[(int64_t)k * N + col];
+    cv[k] = k < K ? ccol[k] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (k < K) {
+      const double nk = Gs[k * KP + k];
+      if (nk > 0.0) {
+        const double cold = (double)cv[k];
+        double cn = cold + h[k] / nk;
+        cn = cn > 0.0 ? cn : 0.0;
+        const double d = cn - cold;
+        cv[k] = (float)cn;
+#pragma unroll
+        for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * KP + k] * d;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k)
+    if (k < K) ccol[k] = cv[k];
+}
+
+hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, hipStream_t st) {
+  const unsigned g = (unsigned)((s.N + 255) / 256);
+  if (s.KP == 32)
+    k_sweep<32><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G);
+  else
+    k_sweep<64><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ V = tril(C C^T)
+// Each block accumulates, in float64, the lower triangle of C C^T over its tiles of 256
+// columns (a tile of C is contiguous).  The tile is staged in LDS with row stride KP + 4;
+// wave w takes the columns j = w (mod 4) of the tile and lane t owns the 4x4 blocks t and
+// t + 64 of the list of lower-triangle blocks (ab >= bb, 4ab < K).  The four waves'
+// partials are then added in wave order and written as tril pairs.
+constexpr int kVBlocks = 256;
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_vgram(const float* __restrict__ C, int64_t N, int K,
+                                               double* __restrict__ Vpart) {
+  constexpr int CS = KP + 4;
+  constexpr int NP = KP * (KP + 1) / 2;
+  constexpr int NBMAX = (KP / 4) * (KP / 4 + 1) / 2;  // lower-triangle 4x4 blocks
+  constexpr int NT = (NBMAX + 63) / 64;              // blocks per lane
+  constexpr int CT_D = 256 * CS / 2;                 // staged tile, in doubles
+  constexpr int SM_D = CT_D > 4 * NP ? CT_D : 4 * NP;
+  __shared__ double smem[SM_D];
+  float* Ct = reinterpret_cast<float*>(smem);  // tile phase
+  double* Vs = smem;                           // reduction phase: [4][NP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nb4 = (K + 3) / 4;
+  const int nblk = nb4 * (nb4 + 1) / 2;
+  int ab[NT], bb[NT];
+  bool own[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int q = lane + 64 * t;
+    own[t] = q < nblk;
+    int a = 0, b = 0;
+    if (own[t]) pair_of(q, a, b);
+    ab[t] = a;
+    bb[t] = b;
+  }
+  double acc[NT][16];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.0;
   const int64_t ntiles = (N + 255) / 256;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    __syncthreads();  // Gs ready (first pass); Ct free (later passes)
-    const int64_t col = tile * 256 + tid;
-    const bool colok = col < N;
-    double h[KP];
-    if (colok) {
-      const f32x4* hp = reinterpret_cast<const f32x4*>(Hin + col * KP);
-#pragma unroll
-      for (int q = 0; q < KP / 4; ++q) {
-        const f32x4 v = hp[q];
-        h[4 * q + 0] = v[0];
-        h[4 * q + 1] = v[1];
-        h[4 * q + 2] = v[2];
-        h[4 * q + 3] = v[3];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < KP; ++k) h[k] = 0.0;
+    const int64_t j0 = tile * 256;
+    const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
+    __syncthreads();
+    for (int e = tid; e < 256 * K; e += 256) {
+      const int j = e / K, kk = e - j * K;
+      Ct[j * CS + kk] = (j < nv) ? C[j0 * K + e] : 0.0f;
     }
-    float* ccol = C + (colok ? col : 0) * K;
-    float* crow = Ct + tid * CS;
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      float cnew = 0.0f;
-      if (k < K && colok) {
-        const double cold = (double)ccol[k];
-        double cn = cold;
-        const double nk = Gs[k * KP + k];
-        if (nk > 0.0) {
-          cn = cold + h[k] / nk;
-          cn = cn > 0.0 ? cn : 0.0;
-          const double d = cn - cold;
-#pragma unroll
-          for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * KP + k] * d;
-        }
-        cnew = (float)cn;
-        ccol[k] = cnew;
-      }
-      crow[k] = cnew;
+    for (int e = tid; e < 256 * (KP - K); e += 256) {  // zero the padding rows kk >= K
+      const int j = e / (KP - K), kk = K + (e - j * (KP - K));
+      Ct[j * CS + kk] = 0.0f;
     }
     __syncthreads();
-    if (vown) {
-      for (int j = 0; j < 256; ++j) {
-        const f32x4 ca = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * ab);
-        const f32x4 cb = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * bb);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (!own[t]) continue;
+      for (int j = wave; j < 256; j += 4) {
+        const f32x4 ca = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * ab[t]);
+        const f32x4 cb = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * bb[t]);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) vacc[4 * r + q] += (double)ca[r] * (double)cb[q];
+          for (int q = 0; q < 4; ++q) acc[t][4 * r + q] += (double)ca[r] * (double)cb[q];
       }
     }
   }
-  if (vown) {
-    double* vp = Vpart + (int64_t)blockIdx.x * KP * KP;
+  // per-wave partials to LDS as tril pairs, then the sum over waves in wave order
+  __syncthreads();  // tile reads done before Vs overwrites the tile
+  for (int q = lane; q < NP; q += 64) Vs[wave * NP + q] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (!own[t]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vp[(4 * ab + r) * KP + 4 * bb + q] = vacc[4 * r + q];
-  } else {
-    // threads without a V block (KP = 32 uses 64 of 256) have nothing to write
+      for (int q = 0; q < 4; ++q) {
+        const int a = 4 * ab[t] + r, b = 4 * bb[t] + q;
+        if (a >= b) Vs[wave * NP + a * (a + 1) / 2 + b] = acc[t][4 * r + q];
+      }
   }
+  __syncthreads();
+  for (int q = tid; q < NP; q += 256)
+    Vpart[(int64_t)blockIdx.x * NP + q] = ((Vs[q] + Vs[NP + q]) + Vs[2 * NP + q]) + Vs[3 * NP + q];
 }
 
-int64_t sweep_blocks(const Shape& s) {
+int64_t vgram_blocks(const Shape& s) {
   const int64_t t = (s.N + 255) / 256;
-  return t < kSweepTiles ? t : kSweepTiles;
+  return t < kVBlocks ? t : kVBlocks;
 }
 
-hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, double* Vpart, hipStream_t st) {
-  const unsigned g = (unsigned)sweep_blocks(s);
+hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st) {
+  const unsigned g = (unsigned)vgram_blocks(s);
   if (s.KP == 32)
-    k_sweep<32><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G, Vpart);
+    k_vgram<32><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
   else
-    k_sweep<64><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G, Vpart);
+    k_vgram<64><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
   return hipGetLastError();
 }
 
@@ -474,19 +594,19 @@ hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, do
 //   acc  = X[chunk, cols]^T
 //   acc += C[:, cols]^T (-B[chunk, :])^T          -> E'^T with E' = X - B C'
 //   WT  += C[:, cols] acc                          -> (E' C'^T)^T for this chunk
-// The C' tile of the next 32 columns is staged into LDS in both MFMA operand orders
-// (double buffer shared by the four waves); X of the next tile is prefetched.
+// with split-bf16 products as in the column pass.  The C' tile of the next 32 columns is
+// split and staged into LDS in both MFMA operand orders (double buffer shared by the four
+// waves); X of the next tile is prefetched into registers.
 template <int KP>
 __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X, int64_t M, int K,
-                                                    const float* __restrict__ C, const float* __restrict__ BpE,
+                                                    const float* __restrict__ C, const __bf16* __restrict__ BqE,
                                                     float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
                                                     const int64_t* __restrict__ rbounds) {
   constexpr int NB = KP / 32;
-  constexpr int KS2 = KP / 2;
-  constexpr int TE = KP * 32;      // floats of the E-operand tile
-  constexpr int TT = 2 * KP * 32;  // floats of both tiles
-  constexpr int NEL = KP / 8;      // tile elements per thread (32 * KP / 256)
-  __shared__ float sc[2][TT];
+  constexpr int KS = KP / 16;
+  constexpr int UE = KS * 3 * 64;      // 16-byte units of the E'^T A operand per tile
+  constexpr int UW = NB * 2 * 3 * 64;  // 16-byte units of the W A operand per tile
+  __shared__ f32x4 sc[2][UE + UW];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
   const int64_t c = (int64_t)blockIdx.x * 4 + wave;
   const bool active = c < nchunks;  // inactive waves still take part in staging and barriers
@@ -494,17 +614,15 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
   const int64_t lo = rbounds[r], hi = rbounds[r + 1];
   const int64_t m0 = (active ? c : 0) * 32, mrow = m0 + lc;
   const bool rowok = active && mrow < M;
-  const int KSr = (K + 1) >> 1;
+  const int KSr = (K + 15) >> 4;
 
-  float bneg[KS2];
+  bf16x8 bP[KS][3];  // pieces of -B[m0 + l%32][16s + 8*half + t]
   {
-    const f32x4* pe = reinterpret_cast<const f32x4*>(BpE + (active ? c : 0) * (int64_t)KP * 32) + l;
+    const f32x4* pe = reinterpret_cast<const f32x4*>(BqE) + (active ? c : 0) * UE + l;
 #pragma unroll
-    for (int s4 = 0; s4 < KP / 8; ++s4) {
-      const f32x4 a = pe[s4 * 64];
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bneg[4 * s4 + u] = a[u];
-    }
+      for (int p = 0; p < 3; ++p) bP[s][p] = as_bf16x8(pe[(s * 3 + p) * 64]);
   }
   f32x16 WT[NB];
 #pragma unroll
@@ -512,26 +630,32 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
 #pragma unroll
     for (int i = 0; i < 16; ++i) WT[b][i] = 0.0f;
 
-  // staging of tile elements e = tid + 256 v: jj = e / KP (column in tile), kk = e % KP
-  float stv[NEL];
+  // Staging roles (KP * 4 threads each; thread tid takes E group tid and W group tid):
+  //   E group (s, h, jj): C'[16s + 8h + t][j0 + jj], t = 0..7 -> unit (s*3 + p)*64 + jj + 32h
+  //   W group (b, q, h, kk): C'[32b + kk][j0 + row32(8q + t, h)] -> unit UE + ((b*2 + q)*3 + p)*64 + kk + 32h
+  constexpr int NG = KP * 4;
+  const bool eg = tid < NG;
+  const int es = tid >> 6, eh = (tid >> 5) & 1, ejj = tid & 31;
+  const int wb = tid >> 7, wq = (tid >> 6) & 1, wh = (tid >> 5) & 1, wkk = tid & 31;
+  float ev[8], wv[8];
   auto cload = [&](int64_t j0) {
 #pragma unroll
-    for (int v = 0; v < NEL; ++v) {
-      const int e = tid + 256 * v, jj = e / KP, kk = e % KP;
-      stv[v] = (j0 + jj < hi && kk < K) ? C[(j0 + jj) * K + kk] : 0.0f;
+    for (int t = 0; t < 8; ++t) {
+      const int kk = 16 * es + 8 * eh + t;
+      ev[t] = (eg && j0 + ejj < hi && kk < K) ? C[(j0 + ejj) * K + kk] : 0.0f;
+      const int64_t jo = j0 + row32(8 * wq + t, wh);
+      const int kw = 32 * wb + wkk;
+      wv[t] = (eg && jo < hi && kw < K) ? C[jo * K + kw] : 0.0f;
     }
   };
   auto cstore = [&](int buf) {
+    if (eg) {
+      const Split3 se = split3(ev);
+      const Split3 sw = split3(wv);
 #pragma unroll
-    for (int v = 0; v < NEL; ++v) {
-      const int e = tid + 256 * v, jj = e / KP, kk = e % KP;
-      {  // A operand of E'^T: lane l, step s -> C'[2s + l/32][j0 + l%32]
-        const int s = kk >> 1, hh = kk & 1, ln = jj + 32 * hh;
-        sc[buf][((s >> 2) * 64 + ln) * 4 + (s & 3)] = stv[v];
-      }
-      {  // A operand of W^T: block b, step i -> C'[32b + l%32][j0 + row32(i, l/32)]
-        const int b = kk >> 5, i4 = jj >> 3, hh = (jj >> 2) & 1, u = jj & 3, ln = (kk & 31) + 32 * hh;
-        sc[buf][TE + ((b * 4 + i4) * 64 + ln) * 4 + u] = stv[v];
+      for (int p = 0; p < 3; ++p) {
+        sc[buf][(es * 3 + p) * 64 + ejj + 32 * eh] = as_f32x4(se.p[p]);
+        sc[buf][UE + ((wb * 2 + wq) * 3 + p) * 64 + wkk + 32 * wh] = as_f32x4(sw.p[p]);
       }
     }
   };
@@ -565,24 +689,35 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
         xn = xload(j0 + 32);
       }
       if (active) {
-        const f32x4* pe = reinterpret_cast<const f32x4*>(&sc[buf][0]) + l;
+        const f32x4* ue = &sc[buf][0] + l;
 #pragma unroll
-        for (int s4 = 0; s4 < KP / 8; ++s4) {
-          if (4 * s4 < KSr) {
-            const f32x4 a = pe[s4 * 64];
+        for (int s = 0; s < KS; ++s) {
+          if (s < KSr) {
+            bf16x8 a[3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (4 * s4 + u < KSr) acc = mfma32(a[u], bneg[4 * s4 + u], acc);
+            for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[(s * 3 + p) * 64]);
+            acc = mfma_x6(a, bP[s], acc);
           }
         }
-        const f32x4* pw = reinterpret_cast<const f32x4*>(&sc[buf][TE]) + l;
+        bf16x8 eP[2][3];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float v[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
+          const Split3 sp = split3(v);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+        }
+        const f32x4* uw = &sc[buf][UE] + l;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int i4 = 0; i4 < 4; ++i4) {
-            const f32x4 a = pw[(b * 4 + i4) * 64];
+          for (int q = 0; q < 2; ++q) {
+            bf16x8 a[3];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) WT[b] = mfma32(a[u], acc[4 * i4 + u], WT[b]);
+            for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(uw[((b * 2 + q) * 3 + p) * 64]);
+            WT[b] = mfma_x6(a, eP[q], WT[b]);
           }
       }
       if (more) cstore(buf ^ 1);
@@ -599,13 +734,13 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
   }
 }
 
-hipError_t rowpass(const Shape& s, const float* X, const float* C, const float* BpE, float* Wpart,
+hipError_t rowpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, float* Wpart,
                    const int64_t* rbounds, int R, hipStream_t st) {
   dim3 g((unsigned)((s.nchunks + 3) / 4), (unsigned)R);
   if (s.KP == 32)
-    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
+    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.K, C, BqE, Wpart, s.Mpad, s.nchunks, rbounds);
   else
-    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.K, C, BpE, Wpart, s.Mpad, s.nchunks, rbounds);
+    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.K, C, BqE, Wpart, s.Mpad, s.nchunks, rbounds);
   return hipGetLastError();
 }
 
