@@ -54,6 +54,7 @@ struct did_ctx {
   double* V = nullptr;
   double* Vpart = nullptr;
   float* H = nullptr;
+  void* Cq = nullptr;
   double* W = nullptr;
   float* Wpart = nullptr;
   int R = 1;
@@ -129,25 +130,24 @@ void release(did_ctx* h) {
   delete h;
 }
 
-// Column ranges of the row pass: P contiguous blocks (the paper's shards; the first N mod
-// P blocks get one extra column), each split into S sub-ranges; partials are summed in
-// ascending range order.
+// Column ranges of the row pass, in 32-column tiles: P contiguous blocks of tiles (the
+// paper's shards; block p holds tiles [T p / P, T (p+1) / P)), each split into S
+// sub-ranges; W partials are summed in ascending range order.  Returns R + 1 tile bounds.
 std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks) {
+  const int64_t T = (N + 31) / 32;
   const int64_t slab_groups = (nchunks + 3) / 4;
-  int64_t want = (2048 + slab_groups - 1) / slab_groups;
-  const int64_t max_ranges = std::max<int64_t>(1, (N + 31) / 32);
-  want = std::max<int64_t>(1, std::min<int64_t>(want, max_ranges));
-  int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, N) : 1;
-  int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
+  // about 4096 blocks of (range, slab group): several rounds of resident blocks, so the
+  // last partial round costs little
+  int64_t want = (4096 + slab_groups - 1) / slab_groups;
+  want = std::max<int64_t>(1, std::min<int64_t>(want, T));
+  const int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, T) : 1;
+  const int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
   std::vector<int64_t> b;
   b.push_back(0);
-  const int64_t base = N / P, extra = N % P;
-  int64_t a = 0;
   for (int64_t p = 0; p < P; ++p) {
-    const int64_t n = base + (p < extra ? 1 : 0);
+    const int64_t a0 = T * p / P, a1 = T * (p + 1) / P, n = a1 - a0;
     const int64_t Sp = std::max<int64_t>(1, std::min<int64_t>(S, n));
-    for (int64_t q = 1; q <= Sp; ++q) b.push_back(a + (n * q) / Sp);
-    a += n;
+    for (int64_t q = 1; q <= Sp; ++q) b.push_back(a0 + (n * q) / Sp);
   }
   return b;
 }
@@ -206,6 +206,11 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
+  {
+    unsigned char* cq = nullptr;
+    if ((rc = dalloc(h, &cq, didk::cq_bytes(s)))) return rc;
+    h->Cq = cq;
+  }
   if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
   if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
   if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
@@ -218,6 +223,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->Cq, 0, (size_t)didk::cq_bytes(s), h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
       (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
           hipSuccess)
@@ -246,7 +252,7 @@ int check_handle(did_ctx* h) {
 
 int objective_pass(did_ctx* h) {
   hipError_t e;
-  if ((e = didk::colpass(h->s, h->X, h->C, h->BqE, h->BqH, h->H, h->fpart, 0, h->st)) != hipSuccess)
+  if ((e = didk::colpass(h->s, h->X, h->Cq, h->BqE, h->BqH, h->H, h->fpart, 0, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective pass");
   if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective reduce");
@@ -261,21 +267,25 @@ int apply_init_scale(did_ctx* h) {
   const int64_t nC = (int64_t)h->s.K * h->s.N;
   hipError_t e;
   for (int q = 0; q < 3; ++q) {
-    if (q && (e = didk::scale(h->C, nC, mul[q], h->st)) != hipSuccess) return dev_fail(h, e, "init scale");
+    if (q && ((e = didk::scale(h->C, nC, mul[q], h->st)) != hipSuccess ||
+              (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess))
+      return dev_fail(h, e, "init scale");
     int rc = objective_pass(h);
     if (rc) return rc;
     if ((e = hipMemcpyAsync(&fv[q], h->fobj, sizeof(double), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
         (e = hipStreamSynchronize(h->st)) != hipSuccess)
       return dev_fail(h, e, "init scale");
   }
-  if ((e = didk::scale(h->C, nC, 0.25f, h->st)) != hipSuccess) return dev_fail(h, e, "init scale");
+  if ((e = didk::scale(h->C, nC, 0.25f, h->st)) != hipSuccess ||
+      (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess)
+    return dev_fail(h, e, "init scale");
   const double c = (fv[2] - 3.0 * fv[1] + 2.0 * fv[0]) / 3.0;
   const double b = 1.5 * c - (fv[1] - fv[0]);
   if (c > 0.0 && b > 0.0 && std::isfinite(b / c)) {
     const float r = (float)std::sqrt(b / c);
     if ((e = didk::scale(h->C, nC, r, h->st)) != hipSuccess ||
         (e = didk::scale(h->B, h->s.M * h->s.K, r, h->st)) != hipSuccess ||
-        (e = refresh_b_derived(h)) != hipSuccess)
+        (e = refresh_b_derived(h)) != hipSuccess || (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess)
       return dev_fail(h, e, "init scale");
   }
   return DID_OK;
@@ -326,8 +336,8 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
       return rc;
     }
   }
-  if ((e = refresh_b_derived(h)) != hipSuccess) {
-    rc = dev_fail(h, e, "pack B");
+  if ((e = refresh_b_derived(h)) != hipSuccess || (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess) {
+    rc = dev_fail(h, e, "pack B, C");
     release(h);
     return rc;
   }
@@ -400,20 +410,20 @@ int did_iterate(did_handle h, int32_t n) {
 #define DID_MARK(q) \
   if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
     DID_MARK(0);
-    if ((e = didk::colpass(s, h->X, h->C, h->BqE, h->BqH, h->H, h->fpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::colpass(s, h->X, h->Cq, h->BqE, h->BqH, h->H, h->fpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "column pass");
     DID_MARK(1);
     if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
     if ((e = didk::vgram(s, h->C, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
     DID_MARK(3);
     if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->X, h->C, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->X, h->Cq, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");

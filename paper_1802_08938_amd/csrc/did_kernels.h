@@ -21,6 +21,15 @@ struct Shape {
 inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)s.KP * 32 * 3; }
 inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
 
+// Packed C: per 32-column tile, the bf16 pieces of C in the two MFMA operand orders, as
+// 16-byte units: E order (KP/16 * 3 * 64 units) then W order (KP/32 * 2 * 3 * 64 units).
+inline int cq_units_e(int KP) { return (KP / 16) * 3 * 64; }
+inline int cq_units_w(int KP) { return (KP / 32) * 2 * 3 * 64; }
+inline int cq_units(int KP) { return cq_units_e(KP) + cq_units_w(KP); }
+inline int64_t n_tiles32(const Shape& s) { return (s.N + 31) / 32; }
+// bytes of the packed C buffer
+inline int64_t cq_bytes(const Shape& s) { return n_tiles32(s) * cq_units(s.KP) * 16; }
+
 // splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -46,20 +55,25 @@ int bupdate_blocks(const Shape& s);
 
 // Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
 // (with_h = 1) H = B^T E written as KP x N floats, row kk contiguous (index kk * N + j).
-hipError_t colpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, const __bf16* BqH,
+// C enters through its packed pieces Cq.
+hipError_t colpass(const Shape& s, const float* X, const void* Cq, const __bf16* BqE, const __bf16* BqH,
                    float* Hout, double* fpart, int with_h, hipStream_t st);
 int64_t colpass_blocks(const Shape& s);
 
-// Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C.
-hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, hipStream_t st);
+// Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C, and
+// repacking of the updated columns into Cq.
+hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st);
+// Pack C into Cq (after C was set from outside the sweep).
+hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st);
 
 // V partials: tril(C C^T) per block of columns (float64, n_pairs(KP) per block).
 hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st);
 int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
-hipError_t rowpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, float* Wpart,
-                   const int64_t* rbounds, int R, hipStream_t st);
+// Range r covers 32-column tiles [tb[r], tb[r+1]); C enters through Cq.
+hipError_t rowpass(const Shape& s, const float* X, const void* Cq, const __bf16* BqE, float* Wpart,
+                   const int64_t* tb, int R, hipStream_t st);
 
 // Fixed-order reductions.
 hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStream_t st);

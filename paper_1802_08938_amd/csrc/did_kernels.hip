@@ -89,6 +89,45 @@ __device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b
 __device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
 
+// Packed C (Cq), per 32-column tile T, in 16-byte units of eight bf16:
+//   E order, unit (s*3 + p)*64 + l, element t: piece p of C[16s + 8(l/32) + t][32T + l%32]
+//       (B operand of E = X - BC in the column pass; A operand of E'^T in the row pass)
+//   W order, unit UE + ((b*2 + q)*3 + p)*64 + l, element t:
+//       piece p of C[32b + l%32][32T + row32(8q + t, l/32)]   (A operand of W^T)
+// Entries with kk >= K or column >= N are zero (the buffer is cleared once at setup).
+template <int KP>
+__device__ __forceinline__ void pack_column(f32x4* __restrict__ Cq, int64_t col, const float* c, int K) {
+  constexpr int KS = KP / 16;
+  constexpr int UE = KS * 3 * 64;
+  constexpr int UT = UE + (KP / 32) * 2 * 3 * 64;
+  const int64_t T = col >> 5;
+  const int jj = (int)(col & 31);
+  f32x4* tile = Cq + T * UT;
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int kk = 16 * s + 8 * h + t;
+        v[t] = kk < K ? c[kk] : 0.0f;
+      }
+      const Split3 sp = split3(v);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) tile[(s * 3 + p) * 64 + jj + 32 * h] = as_f32x4(sp.p[p]);
+    }
+  const int q = jj >> 4, h = (jj >> 2) & 1, t = 4 * ((jj >> 3) & 1) + (jj & 3);
+  __bf16* wbase = reinterpret_cast<__bf16*>(tile + UE);
+  for (int kk = 0; kk < K; ++kk) {
+    __bf16 pc[3];
+    split3_scalar(c[kk], pc[0], pc[1], pc[2]);
+    const int b = kk >> 5, l = (kk & 31) + 32 * h;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) wbase[(((b * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
+  }
+}
+
 // Pair index q -> (a, b) with a >= b, q = a(a+1)/2 + b.
 __device__ __forceinline__ void pair_of(int q, int& a, int& b) {
   int r = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
@@ -269,7 +308,7 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
 // row kk contiguous over the columns.
 template <int KP, bool WITH_H>
 __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const float* __restrict__ C, const __bf16* __restrict__ BqE,
+                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
                                                     const __bf16* __restrict__ BqH, float* __restrict__ Hout,
                                                     double* __restrict__ fpart, int64_t nchunks, int vec4) {
   constexpr int NB = KP / 32;
@@ -281,24 +320,21 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
   __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  const int KSr = (K + 15) >> 4;
-  const int64_t col = (int64_t)blockIdx.x * 128 + wave * 32 + lc;
+  const int64_t T = (int64_t)blockIdx.x * 4 + wave;  // this wave's 32-column tile
+  const int64_t j0 = T * 32;
+  const int64_t col = j0 + lc;
   const bool colok = col < N;
-  const float* xcol = X + (colok ? col : 0) * M;
+  const bool tileok = j0 < N;
+  // X of this tile from a wave-uniform base plus a 32-bit lane offset
+  const float* xtile = X + (tileok ? j0 : 0) * M;
+  const uint32_t loff = (uint32_t)(lc * M + 4 * half);
 
-  bf16x8 cP[KS][3];  // pieces of C[16s + 8*half + t][col]
+  bf16x8 cP[KS][3];  // pieces of C[16s + 8*half + t][col], from the packed tile
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    float v[8];
+  for (int s = 0; s < KS; ++s)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kk = 16 * s + 8 * half + t;
-      v[t] = (colok && kk < K) ? C[col * K + kk] : 0.0f;
-    }
-    const Split3 sp = split3(v);
-#pragma unroll
-    for (int p = 0; p < 3; ++p) cP[s][p] = sp.p[p];
-  }
+    for (int p = 0; p < 3; ++p)
+      cP[s][p] = tileok ? as_bf16x8(Cq[T * (UE + NB * 2 * 3 * 64) + (s * 3 + p) * 64 + l]) : as_bf16x8(f32x4{0, 0, 0, 0});
   f32x16 H[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -311,10 +347,10 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
-      if (u < UE)
-        stg[v] = reinterpret_cast<const f32x4*>(BqE)[c * UE + u];
-      else if (WITH_H && u < U)
-        stg[v] = reinterpret_cast<const f32x4*>(BqH)[c * UH + (u - UE)];
+      const int uu = u < U ? u : U - 1;  // threads past the end reload the last unit
+      const f32x4* src = (uu < UE) ? reinterpret_cast<const f32x4*>(BqE) + c * UE + uu
+                                   : reinterpret_cast<const f32x4*>(BqH) + c * UH + (uu - UE);
+      stg[v] = *src;
     }
   };
   auto sstore = [&](int buf) {
@@ -324,13 +360,15 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
       if (u < U) sb[buf][u] = stg[v];
     }
   };
+  const bool tilefull = vec4 && (j0 + 32 <= N);  // wave-uniform
   auto xload = [&](int64_t c) {
     f32x16 v;
     const int64_t m0 = c * 32;
-    if (colok && vec4 && m0 + 32 <= M) {
+    if (tilefull && m0 + 32 <= M) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f32x4 t = *reinterpret_cast<const f32x4*>(xcol + m0 + 8 * q + 4 * half);
+        const float* xb = xtile + m0 + 8 * q;  // wave-uniform base, 32-bit lane offset
+        const f32x4 t = *reinterpret_cast<const f32x4*>(xb + loff);
         v[4 * q + 0] = t[0];
         v[4 * q + 1] = t[1];
         v[4 * q + 2] = t[2];
@@ -342,65 +380,85 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t r = m0 + 8 * q + 4 * half + e;
-          v[4 * q + e] = (colok && r < M) ? xcol[r] : 0.0f;
+          v[4 * q + e] = (colok && r < M) ? xtile[(int64_t)lc * M + r] : 0.0f;
         }
     }
     return v;
   };
 
+  // One chunk: compute chunk c from the X tile in xr (loaded one chunk earlier) and the
+  // staged B operands in LDS buffer c & 1; meanwhile stage chunk c+1's B operands and load
+  // its X tile into xr.
+  auto step = [&](int64_t c, f32x16& xr) {
+    const int buf = (int)(c & 1);
+    f32x16 acc = xr;
+    const int64_t cn = c + 1 < nchunks ? c + 1 : c;
+    gload(cn);
+    xr = xload(cn);
+      // E = X - B C: KS steps of six MFMAs, operands of step s+1 read from LDS during step s
+      const f32x4* ue = &sb[buf][0] + l;
+      bf16x8 a[3], an[3];
+  #pragma unroll
+      for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[p * 64]);
+  #pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if (s + 1 < KS) {
+  #pragma unroll
+          for (int p = 0; p < 3; ++p) an[p] = as_bf16x8(ue[((s + 1) * 3 + p) * 64]);
+        }
+        acc = mfma_x6(a, cP[s], acc);
+        if (s + 1 < KS) {
+  #pragma unroll
+          for (int p = 0; p < 3; ++p) a[p] = an[p];
+        }
+      }
+      {  // sum of squares of this 32x32 tile in float32, accumulated across tiles in float64
+        float a0 = 0.0f, a1 = 0.0f;
+  #pragma unroll
+        for (int i = 0; i < 16; i += 2) {
+          a0 += acc[i] * acc[i];
+          a1 += acc[i + 1] * acc[i + 1];
+        }
+        if (c & 1) fs1 += (double)(a0 + a1);
+        else fs0 += (double)(a0 + a1);
+      }
+      if (WITH_H) {
+        const f32x4* uh = &sb[buf][UE] + l;
+        bf16x8 h[3], hn[3];
+  #pragma unroll
+        for (int p = 0; p < 3; ++p) h[p] = as_bf16x8(uh[p * 64]);
+        bf16x8 eP[2][3];
+  #pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float v[8];
+  #pragma unroll
+          for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
+          const Split3 sp = split3(v);
+  #pragma unroll
+          for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+        }
+  #pragma unroll
+        for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
+          if (g + 1 < NB * 2) {
+  #pragma unroll
+            for (int p = 0; p < 3; ++p) hn[p] = as_bf16x8(uh[((g + 1) * 3 + p) * 64]);
+          }
+          H[g >> 1] = mfma_x6(h, eP[g & 1], H[g >> 1]);
+          if (g + 1 < NB * 2) {
+  #pragma unroll
+            for (int p = 0; p < 3; ++p) h[p] = hn[p];
+          }
+        }
+      }
+      sstore(buf ^ 1);
+    __syncthreads();
+  };
+
+  f32x16 x0 = xload(0);
   gload(0);
-  f32x16 xn = xload(0);
   sstore(0);
   __syncthreads();
-
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int buf = (int)(c & 1);
-    f32x16 acc = xn;
-    const bool more = c + 1 < nchunks;
-    if (more) {
-      gload(c + 1);
-      xn = xload(c + 1);
-    }
-    const f32x4* ue = &sb[buf][0] + l;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      if (s < KSr) {
-        bf16x8 a[3];
-#pragma unroll
-        for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[(s * 3 + p) * 64]);
-        acc = mfma_x6(a, cP[s], acc);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i += 2) {
-      fs0 += (double)acc[i] * (double)acc[i];
-      fs1 += (double)acc[i + 1] * (double)acc[i + 1];
-    }
-    if (WITH_H) {
-      bf16x8 eP[2][3];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        float v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
-        const Split3 sp = split3(v);
-#pragma unroll
-        for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
-      }
-      const f32x4* uh = &sb[buf][UE] + l;
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          bf16x8 a[3];
-#pragma unroll
-          for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(uh[((b * 2 + q) * 3 + p) * 64]);
-          H[b] = mfma_x6(a, eP[q], H[b]);
-        }
-    }
-    if (more) sstore(buf ^ 1);
-    __syncthreads();
-  }
+  for (int64_t c = 0; c < nchunks; ++c) step(c, x0);
 
   if (WITH_H && colok) {  // row kk of H contiguous over columns: coalesced stores
 #pragma unroll
@@ -419,9 +477,10 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
-hipError_t colpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, const __bf16* BqH,
+hipError_t colpass(const Shape& s, const float* X, const void* Cqv, const __bf16* BqE, const __bf16* BqH,
                    float* Hout, double* fpart, int with_h, hipStream_t st) {
   const unsigned g = (unsigned)colpass_blocks(s);
+  const f32x4* C = static_cast<const f32x4*>(Cqv);
   if (s.KP == 32) {
     if (with_h)
       k_colpass<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
@@ -440,70 +499,106 @@ hipError_t colpass(const Shape& s, const float* X, const float* C, const __bf16*
 // One thread per column j.  With h = B^T e_j from the column pass and G = B^T B in LDS, the
 // coordinates are updated in ascending order in float64:
 //   c_kj := [c_kj + h_k / G_kk]_+,  then h_q -= G_qk (c_kj^new - c_kj^old) for q > k,
+// (the division is a multiplication by 1 / G_kk, formed once per block, which keeps the
+// per-column dependency chain short),
 // which is eq. up:c with b_q^T e_j kept up to date through inner products; a coordinate
-// with G_kk = 0 (zero column of B) is skipped.  The updated column is written back to C.
+// with G_kk = 0 (zero column of B) is skipped.  The block's 256 columns of C (contiguous
+// in memory) are staged through LDS so that global loads and stores are coalesced, and
+// each updated column is repacked into Cq for the row pass and the next column pass.
 template <int KP>
-__global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C, int64_t N, int K,
+__global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
+                                               f32x4* __restrict__ Cq, int64_t N, int K,
                                                const double* __restrict__ G) {
-  __shared__ double Gs[KP * KP];
+  __shared__ double Gs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
+  __shared__ double Ginv[KP];               // 1 / G_kk, or 0 for a zero column of B
+  extern __shared__ float Ct[];             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
-  for (int q = tid; q < KP * KP; q += 256) Gs[q] = G[q];
-  __syncthreads();
-  const int64_t col = (int64_t)blockIdx.x * 256 + tid;
-  if (col >= N) return;  // no barrier below
-  double h[KP];
-  float cv[KP];
-  float* ccol = C + col * K;
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    h[k] = (double)Hin[(int64_t)k * N + col];
-    cv[k] = k < K ? ccol[k] : 0.0f;
+  for (int q = tid; q < KP * (KP + 1) / 2; q += 256) {
+    int a, b;
+    pair_of(q, a, b);
+    Gs[q] = G[a * KP + b];
   }
+  if (tid < KP) {
+    const double g = G[tid * KP + tid];
+    Ginv[tid] = g > 0.0 ? 1.0 / g : 0.0;
+  }
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
+  const int ne = nv * K;
+  for (int e = tid; e < ne; e += 256) Ct[e] = C[j0 * K + e];
+  __syncthreads();
+  const int64_t col = j0 + tid;
+  if (tid < nv) {
+    double h[KP];
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    if (k < K) {
-      const double nk = Gs[k * KP + k];
-      if (nk > 0.0) {
-        const double cold = (double)cv[k];
-        double cn = cold + h[k] / nk;
-        cn = cn > 0.0 ? cn : 0.0;
-        const double d = cn - cold;
-        cv[k] = (float)cn;
+    for (int k = 0; k < KP; ++k) h[k] = (double)Hin[(int64_t)k * N + col];
+    float* cl = Ct + tid * K;
 #pragma unroll
-        for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * KP + k] * d;
+    for (int k = 0; k < KP; ++k) {
+      if (k < K) {
+        const double ik = Ginv[k];
+        if (ik > 0.0) {
+          const double cold = (double)cl[k];
+          double cn = cold + h[k] * ik;
+          cn = cn > 0.0 ? cn : 0.0;
+          const double d = cn - cold;
+          cl[k] = (float)cn;
+#pragma unroll
+          for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * (q + 1) / 2 + k] * d;
+        }
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < KP; ++k)
-    if (k < K) ccol[k] = cv[k];
+  __syncthreads();
+  for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
+  if (tid < nv) pack_column<KP>(Cq, col, Ct + tid * K, K);
 }
 
-hipError_t sweep(const Shape& s, const float* Hin, float* C, const double* G, hipStream_t st) {
+hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st) {
   const unsigned g = (unsigned)((s.N + 255) / 256);
+  f32x4* q = static_cast<f32x4*>(Cq);
   if (s.KP == 32)
-    k_sweep<32><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G);
+    k_sweep<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, s.N, s.K, G);
   else
-    k_sweep<64><<<g, 256, 0, st>>>(Hin, C, s.N, s.K, G);
+    k_sweep<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, s.N, s.K, G);
+  return hipGetLastError();
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_packc(const float* __restrict__ C, f32x4* __restrict__ Cq, int64_t N, int K) {
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= N) return;
+  float c[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) c[k] = k < K ? C[col * K + k] : 0.0f;
+  pack_column<KP>(Cq, col, c, K);
+}
+
+hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st) {
+  const unsigned g = (unsigned)((s.N + 255) / 256);
+  f32x4* q = static_cast<f32x4*>(Cq);
+  if (s.KP == 32)
+    k_packc<32><<<g, 256, 0, st>>>(C, q, s.N, s.K);
+  else
+    k_packc<64><<<g, 256, 0, st>>>(C, q, s.N, s.K);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ V = tril(C C^T)
 // Each block accumulates, in float64, the lower triangle of C C^T over its tiles of 256
-// columns (a tile of C is contiguous).  The tile is staged in LDS with row stride KP + 4;
-// wave w takes the columns j = w (mod 4) of the tile and lane t owns the 4x4 blocks t and
-// t + 64 of the list of lower-triangle blocks (ab >= bb, 4ab < K).  The four waves'
-// partials are then added in wave order and written as tril pairs.
+// columns.  A tile of C is contiguous in memory and is copied flat into LDS (stride K);
+// wave w takes the columns j = w (mod 4) of the tile and lane t owns the 4x4 blocks
+// t, t + 64, ... of the list of lower-triangle blocks (ab >= bb, 4ab < K).  The four
+// waves' partials are then added in wave order and written as tril pairs.
 constexpr int kVBlocks = 256;
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_vgram(const float* __restrict__ C, int64_t N, int K,
                                                double* __restrict__ Vpart) {
-  constexpr int CS = KP + 4;
   constexpr int NP = KP * (KP + 1) / 2;
   constexpr int NBMAX = (KP / 4) * (KP / 4 + 1) / 2;  // lower-triangle 4x4 blocks
   constexpr int NT = (NBMAX + 63) / 64;              // blocks per lane
-  constexpr int CT_D = 256 * CS / 2;                 // staged tile, in doubles
+  constexpr int CT_D = 256 * KP / 2 + 2;             // staged tile (stride K), in doubles
   constexpr int SM_D = CT_D > 4 * NP ? CT_D : 4 * NP;
   __shared__ double smem[SM_D];
   float* Ct = reinterpret_cast<float*>(smem);  // tile phase
@@ -531,26 +626,26 @@ __global__ __launch_bounds__(256) void k_vgram(const float* __restrict__ C, int6
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t j0 = tile * 256;
     const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
+    const int ne = nv * K;
     __syncthreads();
-    for (int e = tid; e < 256 * K; e += 256) {
-      const int j = e / K, kk = e - j * K;
-      Ct[j * CS + kk] = (j < nv) ? C[j0 * K + e] : 0.0f;
-    }
-    for (int e = tid; e < 256 * (KP - K); e += 256) {  // zero the padding rows kk >= K
-      const int j = e / (KP - K), kk = K + (e - j * (KP - K));
-      Ct[j * CS + kk] = 0.0f;
-    }
+    for (int e = tid; e < ne; e += 256) Ct[e] = C[j0 * K + e];
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (!own[t]) continue;
-      for (int j = wave; j < 256; j += 4) {
-        const f32x4 ca = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * ab[t]);
-        const f32x4 cb = *reinterpret_cast<const f32x4*>(Ct + j * CS + 4 * bb[t]);
+      const int ka = 4 * ab[t], kb = 4 * bb[t];
+      for (int j = wave; j < nv; j += 4) {
+        const float* cj = Ct + j * K;
+        double ca[4], cb[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          ca[r] = (ka + r < K) ? (double)cj[ka + r] : 0.0;
+          cb[r] = (kb + r < K) ? (double)cj[kb + r] : 0.0;
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[t][4 * r + q] += (double)ca[r] * (double)cb[q];
+          for (int q = 0; q < 4; ++q) acc[t][4 * r + q] += ca[r] * cb[q];
       }
     }
   }
@@ -589,32 +684,39 @@ hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st) 
 }
 
 // ------------------------------------------------------------------ row pass
-// Block = 4 waves; wave w owns the 32-row chunk c = 4*blockIdx.x + w and column range r =
-// blockIdx.y.  Per 32 columns of the range (transposed tiles, rows = columns of X):
-//   acc  = X[chunk, cols]^T
-//   acc += C[:, cols]^T (-B[chunk, :])^T          -> E'^T with E' = X - B C'
-//   WT  += C[:, cols] acc                          -> (E' C'^T)^T for this chunk
-// with split-bf16 products as in the column pass.  The C' tile of the next 32 columns is
-// split and staged into LDS in both MFMA operand orders (double buffer shared by the four
-// waves); X of the next tile is prefetched into registers.
+// Block = 4 waves; wave w owns the 32-row chunk c = 4*sg + w of slab group sg and column
+// range r.  Per 32-column tile T of the range (transposed tiles, rows = columns of X):
+//   acc  = X[chunk, tile]^T
+//   acc += C[:, tile]^T (-B[chunk, :])^T          -> E'^T with E' = X - B C'
+//   WT  += C[:, tile] acc                          -> (E' C'^T)^T for this chunk
+// with split-bf16 products as in the column pass.  The packed C' tile (both operand
+// orders, already split) is copied into LDS for the next tile (double buffer shared by the
+// four waves) and X of the next tile is prefetched into registers.
+// Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
+// (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
+// into a single L2.
 template <int KP>
-__global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X, int64_t M, int K,
-                                                    const float* __restrict__ C, const __bf16* __restrict__ BqE,
+__global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
+                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
                                                     float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
-                                                    const int64_t* __restrict__ rbounds) {
+                                                    const int64_t* __restrict__ tb, int R, int nsg) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = KS * 3 * 64;      // 16-byte units of the E'^T A operand per tile
   constexpr int UW = NB * 2 * 3 * 64;  // 16-byte units of the W A operand per tile
-  __shared__ f32x4 sc[2][UE + UW];
+  constexpr int UT = UE + UW;
+  constexpr int NV = (UT + 255) / 256;
+  __shared__ f32x4 sc[2][UT];
+  const int id = blockIdx.x, xcd = id & 7, local = id >> 3;
+  const int r = xcd + 8 * (local / nsg), sg = local % nsg;
+  if (r >= R) return;  // whole block
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  const int64_t c = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t c = (int64_t)sg * 4 + wave;
   const bool active = c < nchunks;  // inactive waves still take part in staging and barriers
-  const int r = blockIdx.y;
-  const int64_t lo = rbounds[r], hi = rbounds[r + 1];
+  const int64_t tlo = tb[r], thi = tb[r + 1];
+  const int64_t hi = (thi * 32 < N) ? thi * 32 : N;  // column end of the range
   const int64_t m0 = (active ? c : 0) * 32, mrow = m0 + lc;
   const bool rowok = active && mrow < M;
-  const int KSr = (K + 15) >> 4;
 
   bf16x8 bP[KS][3];  // pieces of -B[m0 + l%32][16s + 8*half + t]
   {
@@ -630,75 +732,68 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
 #pragma unroll
     for (int i = 0; i < 16; ++i) WT[b][i] = 0.0f;
 
-  // Staging roles (KP * 4 threads each; thread tid takes E group tid and W group tid):
-  //   E group (s, h, jj): C'[16s + 8h + t][j0 + jj], t = 0..7 -> unit (s*3 + p)*64 + jj + 32h
-  //   W group (b, q, h, kk): C'[32b + kk][j0 + row32(8q + t, h)] -> unit UE + ((b*2 + q)*3 + p)*64 + kk + 32h
-  constexpr int NG = KP * 4;
-  const bool eg = tid < NG;
-  const int es = tid >> 6, eh = (tid >> 5) & 1, ejj = tid & 31;
-  const int wb = tid >> 7, wq = (tid >> 6) & 1, wh = (tid >> 5) & 1, wkk = tid & 31;
-  float ev[8], wv[8];
-  auto cload = [&](int64_t j0) {
+  f32x4 stg[NV];
+  auto cload = [&](int64_t T) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kk = 16 * es + 8 * eh + t;
-      ev[t] = (eg && j0 + ejj < hi && kk < K) ? C[(j0 + ejj) * K + kk] : 0.0f;
-      const int64_t jo = j0 + row32(8 * wq + t, wh);
-      const int kw = 32 * wb + wkk;
-      wv[t] = (eg && jo < hi && kw < K) ? C[jo * K + kw] : 0.0f;
+    for (int v = 0; v < NV; ++v) {
+      const int u = tid + 256 * v;
+      stg[v] = Cq[T * UT + (u < UT ? u : UT - 1)];
     }
   };
   auto cstore = [&](int buf) {
-    if (eg) {
-      const Split3 se = split3(ev);
-      const Split3 sw = split3(wv);
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        sc[buf][(es * 3 + p) * 64 + ejj + 32 * eh] = as_f32x4(se.p[p]);
-        sc[buf][UE + ((wb * 2 + wq) * 3 + p) * 64 + wkk + 32 * wh] = as_f32x4(sw.p[p]);
-      }
+    for (int v = 0; v < NV; ++v) {
+      const int u = tid + 256 * v;
+      if (u < UT) sc[buf][u] = stg[v];
     }
   };
-  const float* xrow = X + mrow;
-  auto xload = [&](int64_t j0) {
+  const uint32_t loff = (uint32_t)(4 * half * M + mrow);  // lane offset within a tile
+  const bool rowsfull = active && m0 + 32 <= M;            // wave-uniform
+  auto xload = [&](int64_t T) {
     f32x16 v;
-    if (rowok && j0 + 32 <= hi) {
+    const int64_t j0 = T * 32;
+    const float* xt = X + j0 * M;  // wave-uniform
+    if (rowsfull && j0 + 32 <= hi) {  // wave-uniform
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = xrow[(j0 + row32(i, half)) * M];
+      for (int i = 0; i < 16; ++i) v[i] = (xt + (int64_t)(8 * (i >> 2) + (i & 3)) * M)[loff];
     } else {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int64_t j = j0 + row32(i, half);
-        v[i] = (rowok && j < hi) ? xrow[j * M] : 0.0f;
+        v[i] = (rowok && j < hi) ? X[j * M + mrow] : 0.0f;
       }
     }
     return v;
   };
 
-  if (lo < hi) {
-    cload(lo);
-    f32x16 xn = xload(lo);
-    cstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t j0 = lo; j0 < hi; j0 += 32) {
-      f32x16 acc = xn;
-      const bool more = j0 + 32 < hi;
-      if (more) {
-        cload(j0 + 32);
-        xn = xload(j0 + 32);
-      }
+  // One tile: compute tile T from the X tile in xr (loaded one tile earlier) and the
+  // staged C' operands in LDS buffer buf; meanwhile stage tile T+1 and load its X tile.
+  auto step = [&](int64_t T, int buf, f32x16& xr) {
+    f32x16 acc = xr;
+    const int64_t Tn = T + 1 < thi ? T + 1 : T;
+    cload(Tn);
+    xr = xload(Tn);
       if (active) {
         const f32x4* ue = &sc[buf][0] + l;
+        bf16x8 a[3], an[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[p * 64]);
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          if (s < KSr) {
-            bf16x8 a[3];
+          if (s + 1 < KS) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[(s * 3 + p) * 64]);
-            acc = mfma_x6(a, bP[s], acc);
+            for (int p = 0; p < 3; ++p) an[p] = as_bf16x8(ue[((s + 1) * 3 + p) * 64]);
+          }
+          acc = mfma_x6(a, bP[s], acc);
+          if (s + 1 < KS) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) a[p] = an[p];
           }
         }
+        const f32x4* uw = &sc[buf][UE] + l;
+        bf16x8 w[3], wn[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) w[p] = as_bf16x8(uw[p * 64]);
         bf16x8 eP[2][3];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -709,19 +804,31 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
 #pragma unroll
           for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
         }
-        const f32x4* uw = &sc[buf][UE] + l;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
+          if (g + 1 < NB * 2) {
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            bf16x8 a[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(uw[((b * 2 + q) * 3 + p) * 64]);
-            WT[b] = mfma_x6(a, eP[q], WT[b]);
+            for (int p = 0; p < 3; ++p) wn[p] = as_bf16x8(uw[((g + 1) * 3 + p) * 64]);
           }
+          WT[g >> 1] = mfma_x6(w, eP[g & 1], WT[g >> 1]);
+          if (g + 1 < NB * 2) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) w[p] = wn[p];
+          }
+        }
       }
-      if (more) cstore(buf ^ 1);
-      __syncthreads();
+    cstore(buf ^ 1);
+    __syncthreads();
+  };
+
+  if (tlo < thi) {
+    f32x16 x0 = xload(tlo);
+    cload(tlo);
+    cstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t T = tlo; T < thi; ++T) {
+      step(T, buf, x0);
       buf ^= 1;
     }
   }
@@ -734,13 +841,16 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
   }
 }
 
-hipError_t rowpass(const Shape& s, const float* X, const float* C, const __bf16* BqE, float* Wpart,
-                   const int64_t* rbounds, int R, hipStream_t st) {
-  dim3 g((unsigned)((s.nchunks + 3) / 4), (unsigned)R);
+hipError_t rowpass(const Shape& s, const float* X, const void* Cqv, const __bf16* BqE, float* Wpart,
+                   const int64_t* tb, int R, hipStream_t st) {
+  const int nsg = (int)((s.nchunks + 3) / 4);
+  const int R8 = (R + 7) / 8 * 8;
+  const unsigned g = (unsigned)((int64_t)nsg * R8);
+  const f32x4* Cq = static_cast<const f32x4*>(Cqv);
   if (s.KP == 32)
-    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.K, C, BqE, Wpart, s.Mpad, s.nchunks, rbounds);
+    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
   else
-    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.K, C, BqE, Wpart, s.Mpad, s.nchunks, rbounds);
+    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
   return hipGetLastError();
 }
 
