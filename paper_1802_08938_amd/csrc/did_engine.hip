@@ -418,7 +418,7 @@ int did_iterate(did_handle h, int32_t n) {
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
     if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
-    if ((e = didk::vgram(s, h->C, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
+    if ((e = didk::vgram(s, h->Cq, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
     DID_MARK(3);
     if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
       return dev_fail(h, e, "V reduce");

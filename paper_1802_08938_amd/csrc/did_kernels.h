@@ -66,8 +66,9 @@ hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const dou
 // Pack C into Cq (after C was set from outside the sweep).
 hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st);
 
-// V partials: tril(C C^T) per block of columns (float64, n_pairs(KP) per block).
-hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st);
+// V partials: tril(C C^T) per block of tiles from the packed C (float64, n_pairs(KP) per
+// block).
+hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st);
 int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.

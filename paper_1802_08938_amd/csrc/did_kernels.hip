@@ -4,7 +4,7 @@
 //   colpass column pass over X: E = X - B C (MFMA), f partial = sum E^2 (float64),
 //           H = B^T E (MFMA),
 //   sweep   the coordinate sweep over the rows of C (float64, one thread per column),
-//   vgram   V = tril(C C^T) partials of the updated C (float64),
+//   vgram   V = tril(C C^T) partials of the updated C (split-bf16 MFMA, float64 sums),
 //   rowpass row pass over X: E' = X - B C' (MFMA) and W = E' C'^T per column range (MFMA),
 //   reduce  fixed-order sums of the V, W and f partials (the paper's one Allreduce),
 //   bupdate incremental update of the columns of B, one thread per row of B.
@@ -93,38 +93,55 @@ __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(
 //   E order, unit (s*3 + p)*64 + l, element t: piece p of C[16s + 8(l/32) + t][32T + l%32]
 //       (B operand of E = X - BC in the column pass; A operand of E'^T in the row pass)
 //   W order, unit UE + ((b*2 + q)*3 + p)*64 + l, element t:
-//       piece p of C[32b + l%32][32T + row32(8q + t, l/32)]   (A operand of W^T)
-// Entries with kk >= K or column >= N are zero (the buffer is cleared once at setup).
+//       piece p of C[32b + l%32][32T + row32(8q + t, l/32)]
+//       (A operand of W^T in the row pass; both operands of C C^T)
+// Entries with kk >= K or column >= N are zero.
+//
+// pack_block: the 256 threads of a block pack the (up to) eight tiles of columns
+// j0 .. j0 + nv - 1, whose values sit in LDS as Ct[j * K + kk] (j relative to j0); every
+// thread builds whole 16-byte units, so the global stores are coalesced.
 template <int KP>
-__device__ __forceinline__ void pack_column(f32x4* __restrict__ Cq, int64_t col, const float* c, int K) {
+__device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, int64_t j0, int nv, const float* Ct, int K,
+                                           int64_t ntiles) {
   constexpr int KS = KP / 16;
+  constexpr int NB = KP / 32;
   constexpr int UE = KS * 3 * 64;
-  constexpr int UT = UE + (KP / 32) * 2 * 3 * 64;
-  const int64_t T = col >> 5;
-  const int jj = (int)(col & 31);
-  f32x4* tile = Cq + T * UT;
+  constexpr int UT = UE + NB * 2 * 3 * 64;
+  constexpr int GE = 8 * KS * 64;  // E groups per block: (tile, s, half, jj)
+  constexpr int GW = 8 * NB * 128; // W groups per block: (tile, b, q, lane)
+  const int tid = threadIdx.x;
+  const int64_t T0 = j0 >> 5;
+  for (int g = tid; g < GE; g += 256) {
+    const int tb = g / (KS * 64), rem = g % (KS * 64), sh = rem >> 5, jj = rem & 31;
+    const int s = sh >> 1, h = sh & 1;
+    if (T0 + tb >= ntiles) continue;
+    const int j = 32 * tb + jj;
+    float v[8];
 #pragma unroll
-  for (int s = 0; s < KS; ++s)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      float v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int kk = 16 * s + 8 * h + t;
-        v[t] = kk < K ? c[kk] : 0.0f;
-      }
-      const Split3 sp = split3(v);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) tile[(s * 3 + p) * 64 + jj + 32 * h] = as_f32x4(sp.p[p]);
+    for (int t = 0; t < 8; ++t) {
+      const int kk = 16 * s + 8 * h + t;
+      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] : 0.0f;
     }
-  const int q = jj >> 4, h = (jj >> 2) & 1, t = 4 * ((jj >> 3) & 1) + (jj & 3);
-  __bf16* wbase = reinterpret_cast<__bf16*>(tile + UE);
-  for (int kk = 0; kk < K; ++kk) {
-    __bf16 pc[3];
-    split3_scalar(c[kk], pc[0], pc[1], pc[2]);
-    const int b = kk >> 5, l = (kk & 31) + 32 * h;
+    const Split3 sp = split3(v);
+    f32x4* tile = Cq + (T0 + tb) * UT;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) wbase[(((b * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
+    for (int p = 0; p < 3; ++p) tile[(s * 3 + p) * 64 + jj + 32 * h] = as_f32x4(sp.p[p]);
+  }
+  for (int g = tid; g < GW; g += 256) {
+    const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
+    const int b = bq >> 1, q = bq & 1;
+    if (T0 + tb >= ntiles) continue;
+    const int kk = 32 * b + (l & 31), h = l >> 5;
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int j = 32 * tb + row32(8 * q + t, h);
+      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] : 0.0f;
+    }
+    const Split3 sp = split3(v);
+    f32x4* tile = Cq + (T0 + tb) * UT;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) tile[UE + ((b * 2 + q) * 3 + p) * 64 + l] = as_f32x4(sp.p[p]);
   }
 }
 
@@ -499,8 +516,7 @@ hipError_t colpass(const Shape& s, const float* X, const void* Cqv, const __bf16
 // One thread per column j.  With h = B^T e_j from the column pass and G = B^T B in LDS, the
 // coordinates are updated in ascending order in float64:
 //   c_kj := [c_kj + h_k / G_kk]_+,  then h_q -= G_qk (c_kj^new - c_kj^old) for q > k,
-// (the division is a multiplication by 1 / G_kk, formed once per block, which keeps the
-// per-column dependency chain short),
+// (a true division, so that cancellations the closed form makes exact stay exact),
 // which is eq. up:c with b_q^T e_j kept up to date through inner products; a coordinate
 // with G_kk = 0 (zero column of B) is skipped.  The block's 256 columns of C (contiguous
 // in memory) are staged through LDS so that global loads and stores are coalesced, and
@@ -510,7 +526,6 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
                                                f32x4* __restrict__ Cq, int64_t N, int K,
                                                const double* __restrict__ G) {
   __shared__ double Gs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
-  __shared__ double Ginv[KP];               // 1 / G_kk, or 0 for a zero column of B
   extern __shared__ float Ct[];             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
   for (int q = tid; q < KP * (KP + 1) / 2; q += 256) {
@@ -518,10 +533,7 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
     pair_of(q, a, b);
     Gs[q] = G[a * KP + b];
   }
-  if (tid < KP) {
-    const double g = G[tid * KP + tid];
-    Ginv[tid] = g > 0.0 ? 1.0 / g : 0.0;
-  }
+
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
   const int ne = nv * K;
@@ -536,10 +548,10 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (k < K) {
-        const double ik = Ginv[k];
-        if (ik > 0.0) {
+        const double nk = Gs[k * (k + 1) / 2 + k];
+        if (nk > 0.0) {
           const double cold = (double)cl[k];
-          double cn = cold + h[k] * ik;
+          double cn = cold + h[k] / nk;
           cn = cn > 0.0 ? cn : 0.0;
           const double d = cn - cold;
           cl[k] = (float)cn;
@@ -551,7 +563,7 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
   }
   __syncthreads();
   for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
-  if (tid < nv) pack_column<KP>(Cq, col, Ct + tid * K, K);
+  pack_block<KP>(Cq, j0, nv, Ct, K, (N + 31) / 32);
 }
 
 hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st) {
@@ -566,120 +578,110 @@ hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const dou
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_packc(const float* __restrict__ C, f32x4* __restrict__ Cq, int64_t N, int K) {
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= N) return;
-  float c[KP];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) c[k] = k < K ? C[col * K + k] : 0.0f;
-  pack_column<KP>(Cq, col, c, K);
+  extern __shared__ float Ct[];  // 256 * K floats
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
+  const int ne = nv * K;
+  for (int e = threadIdx.x; e < ne; e += 256) Ct[e] = C[j0 * K + e];
+  __syncthreads();
+  pack_block<KP>(Cq, j0, nv, Ct, K, (N + 31) / 32);
 }
 
 hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st) {
   const unsigned g = (unsigned)((s.N + 255) / 256);
   f32x4* q = static_cast<f32x4*>(Cq);
   if (s.KP == 32)
-    k_packc<32><<<g, 256, 0, st>>>(C, q, s.N, s.K);
+    k_packc<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, s.N, s.K);
   else
-    k_packc<64><<<g, 256, 0, st>>>(C, q, s.N, s.K);
+    k_packc<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, s.N, s.K);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ V = tril(C C^T)
-// Each block accumulates, in float64, the lower triangle of C C^T over its tiles of 256
-// columns.  A tile of C is contiguous in memory and is copied flat into LDS (stride K);
-// wave w takes the columns j = w (mod 4) of the tile and lane t owns the 4x4 blocks
-// t, t + 64, ... of the list of lower-triangle blocks (ab >= bb, 4ab < K).  The four
-// waves' partials are then added in wave order and written as tril pairs.
+// V = C C^T from the packed W-order units of C: a W unit holds, for one coordinate kk,
+// eight columns of a tile, which is both the A fragment (rows kk, reduction over columns)
+// and the B fragment (reduction over columns, columns kk') of the product.  Each block
+// takes a contiguous run of tiles; wave w takes every fourth tile of the run and forms the
+// lower 32x32 blocks (b1 >= b2) of the tile's contribution with split-bf16 MFMAs (float32
+// within the tile), adding them to float64 accumulators.  The four waves' partials are
+// then added in wave order and written as tril pairs.
 constexpr int kVBlocks = 256;
 
 template <int KP>
-__global__ __launch_bounds__(256) void k_vgram(const float* __restrict__ C, int64_t N, int K,
+__global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int64_t ntiles,
                                                double* __restrict__ Vpart) {
+  constexpr int NB = KP / 32;
+  constexpr int KS = KP / 16;
+  constexpr int UE = KS * 3 * 64;
+  constexpr int UT = UE + NB * 2 * 3 * 64;
+  constexpr int NBL = NB * (NB + 1) / 2;  // lower blocks (b1 >= b2)
   constexpr int NP = KP * (KP + 1) / 2;
-  constexpr int NBMAX = (KP / 4) * (KP / 4 + 1) / 2;  // lower-triangle 4x4 blocks
-  constexpr int NT = (NBMAX + 63) / 64;              // blocks per lane
-  constexpr int CT_D = 256 * KP / 2 + 2;             // staged tile (stride K), in doubles
-  constexpr int SM_D = CT_D > 4 * NP ? CT_D : 4 * NP;
-  __shared__ double smem[SM_D];
-  float* Ct = reinterpret_cast<float*>(smem);  // tile phase
-  double* Vs = smem;                           // reduction phase: [4][NP]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int nb4 = (K + 3) / 4;
-  const int nblk = nb4 * (nb4 + 1) / 2;
-  int ab[NT], bb[NT];
-  bool own[NT];
+  __shared__ double Vs[4][NP];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
+  double acc[NBL][16];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int q = lane + 64 * t;
-    own[t] = q < nblk;
-    int a = 0, b = 0;
-    if (own[t]) pair_of(q, a, b);
-    ab[t] = a;
-    bb[t] = b;
-  }
-  double acc[NT][16];
+  for (int k = 0; k < NBL; ++k)
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int i = 0; i < 16; ++i) acc[k][i] = 0.0;
+  for (int64_t T = t0 + wave; T < t1; T += 4) {
+    const f32x4* wu = Cq + T * UT + UE + l;
+    f32x16 v[NBL];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[t][e] = 0.0;
-  const int64_t ntiles = (N + 255) / 256;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t j0 = tile * 256;
-    const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
-    const int ne = nv * K;
-    __syncthreads();
-    for (int e = tid; e < ne; e += 256) Ct[e] = C[j0 * K + e];
-    __syncthreads();
+    for (int k = 0; k < NBL; ++k)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (!own[t]) continue;
-      const int ka = 4 * ab[t], kb = 4 * bb[t];
-      for (int j = wave; j < nv; j += 4) {
-        const float* cj = Ct + j * K;
-        double ca[4], cb[4];
+      for (int i = 0; i < 16; ++i) v[k][i] = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          ca[r] = (ka + r < K) ? (double)cj[ka + r] : 0.0;
-          cb[r] = (kb + r < K) ? (double)cj[kb + r] : 0.0;
-        }
+    for (int q = 0; q < 2; ++q) {
+      bf16x8 w[NB][3];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[t][4 * r + q] += ca[r] * cb[q];
-      }
+        for (int p = 0; p < 3; ++p) w[b][p] = as_bf16x8(wu[((b * 2 + q) * 3 + p) * 64]);
+      int k = 0;
+#pragma unroll
+      for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+        for (int b2 = 0; b2 <= b1; ++b2, ++k) v[k] = mfma_x6(w[b1], w[b2], v[k]);
     }
+#pragma unroll
+    for (int k = 0; k < NBL; ++k)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[k][i] += (double)v[k][i];
   }
-  // per-wave partials to LDS as tril pairs, then the sum over waves in wave order
-  __syncthreads();  // tile reads done before Vs overwrites the tile
-  for (int q = lane; q < NP; q += 64) Vs[wave * NP + q] = 0.0;
+  for (int q = l; q < NP; q += 64) Vs[wave][q] = 0.0;
   __syncthreads();
+  {
+    int k = 0;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    if (!own[t]) continue;
+    for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int b2 = 0; b2 <= b1; ++b2, ++k)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int a = 4 * ab[t] + r, b = 4 * bb[t] + q;
-        if (a >= b) Vs[wave * NP + a * (a + 1) / 2 + b] = acc[t][4 * r + q];
-      }
+        for (int i = 0; i < 16; ++i) {
+          const int a = 32 * b1 + row32(i, half), b = 32 * b2 + lc;
+          if (a >= b) Vs[wave][a * (a + 1) / 2 + b] = acc[k][i];
+        }
   }
   __syncthreads();
   for (int q = tid; q < NP; q += 256)
-    Vpart[(int64_t)blockIdx.x * NP + q] = ((Vs[q] + Vs[NP + q]) + Vs[2 * NP + q]) + Vs[3 * NP + q];
+    Vpart[(int64_t)blockIdx.x * NP + q] = ((Vs[0][q] + Vs[1][q]) + Vs[2][q]) + Vs[3][q];
 }
 
 int64_t vgram_blocks(const Shape& s) {
-  const int64_t t = (s.N + 255) / 256;
+  const int64_t t = n_tiles32(s);
   return t < kVBlocks ? t : kVBlocks;
 }
 
-hipError_t vgram(const Shape& s, const float* C, double* Vpart, hipStream_t st) {
+hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) {
   const unsigned g = (unsigned)vgram_blocks(s);
+  const f32x4* q = static_cast<const f32x4*>(Cq);
   if (s.KP == 32)
-    k_vgram<32><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
+    k_vgram<32><<<g, 256, 0, st>>>(q, n_tiles32(s), Vpart);
   else
-    k_vgram<64><<<g, 256, 0, st>>>(C, s.N, s.K, Vpart);
+    k_vgram<64><<<g, 256, 0, st>>>(q, n_tiles32(s), Vpart);
   return hipGetLastError();
 }
 
