@@ -33,6 +33,9 @@ WORKLOADS = {
     "large": dict(M=5000, N=1_000_000, K=50, n_blocks=64,
                   desc="plain FP32 DID, M=5000 N=1000000 K=50, 64 column blocks, X=B0*C0+|0.01*N(0,1)|, "
                        "B0,C0~U[0,1], X and R resident in HBM"),
+    "large_bf16": dict(M=5000, N=1_000_000, K=50, n_blocks=64, x_bf16=True,
+                       desc="precision form: X stored as bf16 (RNE), B/C/residual float32-accurate, float64 "
+                            "objective; M=5000 N=1000000 K=50, 64 column blocks, X=B0*C0+|0.01*N(0,1)|"),
     "image": dict(M=784, N=70_000, K=16, n_blocks=4,
                   desc="plain FP32 DID, M=784 N=70000 K=16, 4 column blocks, image-like X in [0,1]"),
     "planted": dict(M=500, N=2000, K=10, n_blocks=1,
@@ -89,7 +92,7 @@ def make_input(torch, name, cfg):
     from workloads import image_like, large_halfnormal_device, planted_lowrank
 
     M, N, K = cfg["M"], cfg["N"], cfg["K"]
-    if name == "large":
+    if name in ("large", "large_bf16"):
         return large_halfnormal_device(torch, M=M, N=N, K=K, seed=3, n_blocks=cfg["n_blocks"])
     import numpy as np
 
@@ -106,7 +109,7 @@ def cpu_baseline(name, cfg):
     from workloads import image_like, large_halfnormal, planted_lowrank, uniform_init
 
     M, N, K = cfg["M"], cfg["N"], cfg["K"]
-    if name == "large":
+    if name in ("large", "large_bf16"):
         X, _ = large_halfnormal(M, N, K, seed=3, n_blocks=cfg["n_blocks"], take_blocks=1)
         frac = X.shape[1] / N
         sample = (f"one oracle DID iteration on column block 0 ({M}x{X.shape[1]}, 1/{cfg['n_blocks']} "
@@ -161,7 +164,8 @@ def main():
     stream = torch.cuda.Stream()
     opts = did.did_default_opts()
     opts.n_blocks = cfg["n_blocks"]
-    opts.borrow_x = 1
+    opts.borrow_x = 0 if cfg.get("x_bf16") else 1
+    opts.x_dtype = did.DID_BF16 if cfg.get("x_bf16") else did.DID_F32
     opts.stream = stream.cuda_stream
     t0 = time.perf_counter()
     h = did.did_init_ex(X, M, N, K, 12345, opts)
@@ -185,8 +189,23 @@ def main():
         did.did_profile(h, False)
         f_last = did.did_objective(h)
         hist = did.did_history(h)
+        n_total = did.did_iterations(h)
     finally:
         did.did_free(h)
+    f32_ref = None
+    if cfg.get("x_bf16"):
+        # the plain float32 form from the same initial factors and iteration count, for the
+        # objective error of the bf16 storage form
+        o2 = did.did_default_opts()
+        o2.n_blocks = cfg["n_blocks"]
+        o2.borrow_x = 1
+        o2.stream = stream.cuda_stream
+        h2 = did.did_init_ex(X, M, N, K, 12345, o2)
+        try:
+            did.did_iterate(h2, n_total)
+            f32_ref = did.did_objective(h2)
+        finally:
+            did.did_free(h2)
     ms = ms_total / args.steps
     it_s = 1000.0 / ms
     cnt = algorithmic_counts(M, N, K)
@@ -218,6 +237,10 @@ def main():
         "init_s": round(init_s, 3),
         "roofline": roof,
     }
+    if f32_ref is not None:
+        line["config"]["x_storage"] = "bf16"
+        line["objective_f32_form_same_iterations"] = f32_ref
+        line["objective_rel_diff_vs_f32_form"] = (f_last - f32_ref) / f32_ref
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         del X

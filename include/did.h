@@ -59,10 +59,16 @@ enum { DID_F32 = 0, DID_BF16 = 1 }; /* storage type of X inside the engine */
  *                  Section 3 "Distributed ADMM" / Section 4): the messages W_p, V_p are
  *                  formed per block and added in ascending block order.  0 lets the
  *                  engine choose; results depend on P only through summation order.
- *   x_dtype        DID_F32 (X used as given).  DID_BF16 is reserved for the reduced-
- *                  precision storage form and currently returns DID_EINVAL.
- *   refresh_every  1: the residual is formed afresh as X - BC at the start of every
- *                  iteration, as Alg. 3 does.  Other values are reserved (DID_EINVAL).
+ *   x_dtype        DID_F32: X is used as given.  DID_BF16: X (still passed as float32)
+ *                  is rounded to bf16 (round to nearest even) on the device and stored in
+ *                  that form, halving the bytes streamed per iteration; B, C, the residual
+ *                  and every product stay float32-accurate and the objective is reduced in
+ *                  float64, so the engine solves the problem for the rounded data exactly
+ *                  as DID_F32 would.  borrow_x does not apply to DID_BF16.
+ *   refresh_every  1: the residual is formed afresh from X at the start of every
+ *                  iteration, as Alg. 3 does.  Other values are reserved (DID_EINVAL):
+ *                  carrying the residual between refreshes would stream and write 8 bytes
+ *                  per entry per pass instead of re-reading 2 or 4 bytes of X.
  *   init_scale     0: initial B, C are U[0,1) draws as they are.  1: both are then scaled
  *                  by sqrt(alpha), alpha = <X, BC> / ||BC||_F^2, which minimises f over a
  *                  common scale (the experiments' "well scaled initial points").

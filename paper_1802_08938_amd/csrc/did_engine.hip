@@ -44,7 +44,7 @@ struct did_ctx {
   bool own_stream = false;
   Shape s{};
   bool own_x = true;
-  float* X = nullptr;
+  void* X = nullptr;  // float32 or bf16 (s.xbf16)
   float* B = nullptr;
   float* C = nullptr;
   __bf16* BqE = nullptr;
@@ -164,7 +164,7 @@ int check_shape(int64_t M, int64_t N, int32_t K) {
 // Allocate, copy/adopt X and validate it.  Leaves h ready for factor setup.
 int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   int rc;
-  if (o.x_dtype != DID_F32) return fail(DID_EINVAL, "only DID_F32 storage of X is supported");
+  if (o.x_dtype != DID_F32 && o.x_dtype != DID_BF16) return fail(DID_EINVAL, "x_dtype must be DID_F32 or DID_BF16");
   if (o.refresh_every != 1) return fail(DID_EINVAL, "refresh_every must be 1");
   if (o.n_blocks < 0) return fail(DID_EINVAL, "n_blocks must be >= 0");
   if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
@@ -182,17 +182,66 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   s.KP = K <= 32 ? 32 : 64;
   s.nchunks = (M + 31) / 32;
   s.Mpad = s.nchunks * 32;
+  s.xbf16 = o.x_dtype == DID_BF16;
 
+  // float32 view of X on the device: the caller's device buffer (borrowed, or read once for
+  // the bf16 form) or an upload
+  if ((rc = dalloc(h, &h->flag, 1))) return rc;
+  hipError_t e;
   const bool xdev = is_device_ptr(Xv);
-  if (o.borrow_x && xdev) {
-    h->X = static_cast<float*>(const_cast<void*>(Xv));
-    h->own_x = false;
+  const float* xin = nullptr;
+  float* xtmp = nullptr;  // temporary upload for the bf16 form, freed below
+  if (xdev && (o.borrow_x || s.xbf16)) {
+    xin = static_cast<const float*>(Xv);
+    h->own_x = !s.xbf16 ? false : true;
+  } else if (!s.xbf16) {
+    float* xc = nullptr;
+    if ((rc = dalloc(h, &xc, M * N))) return rc;
+    if ((e = hipMemcpyAsync(xc, Xv, (size_t)(M * N) * sizeof(float), hipMemcpyDefault, h->st)) != hipSuccess)
+      return dev_fail(h, e, "copy of X");
+    xin = xc;
   } else {
-    if ((rc = dalloc(h, &h->X, M * N))) return rc;
-    hipError_t e = hipMemcpyAsync(h->X, Xv, (size_t)(M * N) * sizeof(float), hipMemcpyDefault, h->st);
-    if (e != hipSuccess) return dev_fail(h, e, "copy of X");
+    if ((e = hipMalloc(&xtmp, (size_t)(M * N) * sizeof(float))) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DID_ENOMEM, "device allocation for the upload of X failed");
+    }
+    if ((e = hipMemcpyAsync(xtmp, Xv, (size_t)(M * N) * sizeof(float), hipMemcpyDefault, h->st)) != hipSuccess) {
+      (void)hipFree(xtmp);
+      return dev_fail(h, e, "copy of X");
+    }
+    xin = xtmp;
   }
-  s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(h->X) & 15) == 0);
+  {  // X must be finite and nonnegative
+    const int v4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xin) & 15) == 0);
+    int flag = 0;
+    if ((e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
+        (e = didk::validate(xin, M * N, v4, h->flag, h->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->st)) != hipSuccess) {
+      if (xtmp) (void)hipFree(xtmp);
+      return dev_fail(h, e, "validate X");
+    }
+    if (flag) {
+      if (xtmp) (void)hipFree(xtmp);
+      return fail(DID_EINVAL, "X must be finite and nonnegative");
+    }
+  }
+  if (s.xbf16) {
+    __bf16* xb = nullptr;
+    if ((rc = dalloc(h, &xb, M * N))) {
+      if (xtmp) (void)hipFree(xtmp);
+      return rc;
+    }
+    e = didk::to_bf16(xin, xb, M * N, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (xtmp) (void)hipFree(xtmp);
+    if (e != hipSuccess) return dev_fail(h, e, "bf16 storage of X");
+    h->X = xb;
+    s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xb) & 7) == 0);
+  } else {
+    h->X = const_cast<float*>(xin);
+    s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xin) & 15) == 0);
+  }
 
   const int NP = didk::n_pairs(s.KP);
   const std::vector<int64_t> rb = make_ranges(N, s.nchunks, o.n_blocks);
@@ -217,9 +266,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
   if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
-  if ((rc = dalloc(h, &h->flag, 1))) return rc;
 
-  hipError_t e;
   if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
@@ -228,12 +275,6 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
           hipSuccess)
     return dev_fail(h, e, "buffer setup");
-  if ((e = didk::validate(h->X, M * N, s.vec4, h->flag, h->st)) != hipSuccess) return dev_fail(h, e, "validate X");
-  int flag = 0;
-  if ((e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
-      (e = hipStreamSynchronize(h->st)) != hipSuccess)
-    return dev_fail(h, e, "validate X");
-  if (flag) return fail(DID_EINVAL, "X must be finite and nonnegative");
   return DID_OK;
 }
 

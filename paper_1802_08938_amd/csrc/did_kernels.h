@@ -13,7 +13,8 @@ struct Shape {
   int KP;            // K padded to the MFMA output tile (32 or 64)
   int64_t nchunks;   // ceil(M / 32): 32-row chunks of the basis
   int64_t Mpad;      // nchunks * 32
-  int vec4;          // X column starts are 16-byte aligned (M % 4 == 0 and X aligned)
+  int vec4;          // vector loads of X are aligned (M % 4 == 0 and X aligned)
+  int xbf16;         // X is stored as bf16 (reduced-precision storage form), else float32
 };
 
 // Number of bf16 entries of one packed-operand buffer (E-operand or H-operand) of B:
@@ -44,6 +45,8 @@ inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
 // ---- launchers (all asynchronous on `st`; they return the launch status) ----
 hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
 hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
+// dst = bf16(src), round to nearest even
+hipError_t to_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
 // Pack B (three bf16 pieces per entry) into MFMA operand order, optionally applying the incremental B update from the
@@ -56,7 +59,7 @@ int bupdate_blocks(const Shape& s);
 // Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
 // (with_h = 1) H = B^T E written as KP x N floats, row kk contiguous (index kk * N + j).
 // C enters through its packed pieces Cq.
-hipError_t colpass(const Shape& s, const float* X, const void* Cq, const __bf16* BqE, const __bf16* BqH,
+hipError_t colpass(const Shape& s, const void* X, const void* Cq, const __bf16* BqE, const __bf16* BqH,
                    float* Hout, double* fpart, int with_h, hipStream_t st);
 int64_t colpass_blocks(const Shape& s);
 
@@ -73,7 +76,7 @@ int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
 // Range r covers 32-column tiles [tb[r], tb[r+1]); C enters through Cq.
-hipError_t rowpass(const Shape& s, const float* X, const void* Cq, const __bf16* BqE, float* Wpart,
+hipError_t rowpass(const Shape& s, const void* X, const void* Cq, const __bf16* BqE, float* Wpart,
                    const int64_t* tb, int R, hipStream_t st);
 
 // Fixed-order reductions.

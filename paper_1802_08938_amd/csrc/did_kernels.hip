@@ -87,6 +87,23 @@ __device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// X is stored either as float32 or as bf16 (the reduced-precision storage form); both load
+// paths return float32 (bf16 -> float32 is exact).
+__device__ __forceinline__ float ldx(const float* p) { return *p; }
+__device__ __forceinline__ float ldx(const __bf16* p) { return (float)*p; }
+// four consecutive elements; p is 16-byte (float) or 8-byte (bf16) aligned
+__device__ __forceinline__ f32x4 ldx4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+__device__ __forceinline__ f32x4 ldx4(const __bf16* p) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 w = *reinterpret_cast<const u32x2*>(p);
+  f32x4 r;
+  r[0] = __builtin_bit_cast(float, w[0] << 16);
+  r[1] = __builtin_bit_cast(float, w[0] & 0xffff0000u);
+  r[2] = __builtin_bit_cast(float, w[1] << 16);
+  r[3] = __builtin_bit_cast(float, w[1] & 0xffff0000u);
+  return r;
+}
 __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
 
 // Packed C (Cq), per 32-column tile T, in 16-byte units of eight bf16:
@@ -181,6 +198,21 @@ hipError_t scale(float* p, int64_t n, float a, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   k_scale<<<(unsigned)blocks, 256, 0, st>>>(p, n, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ bf16 storage of X
+// dst[i] = bf16(src[i]), round to nearest even (the reduced-precision storage form of X).
+__global__ void k_to_bf16(const float* __restrict__ src, __bf16* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (__bf16)src[i];
+}
+
+hipError_t to_bf16(const float* src, void* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(src, static_cast<__bf16*>(dst), n);
   return hipGetLastError();
 }
 
@@ -323,8 +355,8 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
 // are staged into LDS (double buffer shared by the four waves) and the X tile of chunk
 // c+1 is loaded into registers while chunk c is computed.  H is written as KP x N with
 // row kk contiguous over the columns.
-template <int KP, bool WITH_H>
-__global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
+template <int KP, bool WITH_H, typename XT>
+__global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
                                                     const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
                                                     const __bf16* __restrict__ BqH, float* __restrict__ Hout,
                                                     double* __restrict__ fpart, int64_t nchunks, int vec4) {
@@ -343,7 +375,7 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
   const bool colok = col < N;
   const bool tileok = j0 < N;
   // X of this tile from a wave-uniform base plus a 32-bit lane offset
-  const float* xtile = X + (tileok ? j0 : 0) * M;
+  const XT* xtile = X + (tileok ? j0 : 0) * M;
   const uint32_t loff = (uint32_t)(lc * M + 4 * half);
 
   bf16x8 cP[KS][3];  // pieces of C[16s + 8*half + t][col], from the packed tile
@@ -384,8 +416,8 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
     if (tilefull && m0 + 32 <= M) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float* xb = xtile + m0 + 8 * q;  // wave-uniform base, 32-bit lane offset
-        const f32x4 t = *reinterpret_cast<const f32x4*>(xb + loff);
+        const XT* xb = xtile + m0 + 8 * q;  // wave-uniform base, 32-bit lane offset
+        const f32x4 t = ldx4(xb + loff);
         v[4 * q + 0] = t[0];
         v[4 * q + 1] = t[1];
         v[4 * q + 2] = t[2];
@@ -397,7 +429,7 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t r = m0 + 8 * q + 4 * half + e;
-          v[4 * q + e] = (colok && r < M) ? xtile[(int64_t)lc * M + r] : 0.0f;
+          v[4 * q + e] = (colok && r < M) ? ldx(xtile + (int64_t)lc * M + r) : 0.0f;
         }
     }
     return v;
@@ -494,21 +526,30 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const float* __restrict__ X,
 
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
-hipError_t colpass(const Shape& s, const float* X, const void* Cqv, const __bf16* BqE, const __bf16* BqH,
-                   float* Hout, double* fpart, int with_h, hipStream_t st) {
+template <typename XT>
+static void colpass_launch(const Shape& s, const XT* X, const f32x4* C, const __bf16* BqE, const __bf16* BqH,
+                           float* Hout, double* fpart, int with_h, hipStream_t st) {
   const unsigned g = (unsigned)colpass_blocks(s);
-  const f32x4* C = static_cast<const f32x4*>(Cqv);
   if (s.KP == 32) {
     if (with_h)
-      k_colpass<32, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<32, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
   } else {
     if (with_h)
-      k_colpass<64, true><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<64, false><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
   }
+}
+
+hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const __bf16* BqE, const __bf16* BqH,
+                   float* Hout, double* fpart, int with_h, hipStream_t st) {
+  const f32x4* C = static_cast<const f32x4*>(Cqv);
+  if (s.xbf16)
+    colpass_launch(s, static_cast<const __bf16*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
+  else
+    colpass_launch(s, static_cast<const float*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
   return hipGetLastError();
 }
 
@@ -697,8 +738,8 @@ hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) 
 // Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
-template <int KP>
-__global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X, int64_t M, int64_t N, int K,
+template <int KP, typename XT>
+__global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
                                                     const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
                                                     float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
                                                     const int64_t* __restrict__ tb, int R, int nsg) {
@@ -754,15 +795,15 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
   auto xload = [&](int64_t T) {
     f32x16 v;
     const int64_t j0 = T * 32;
-    const float* xt = X + j0 * M;  // wave-uniform
+    const XT* xt = X + j0 * M;  // wave-uniform
     if (rowsfull && j0 + 32 <= hi) {  // wave-uniform
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = (xt + (int64_t)(8 * (i >> 2) + (i & 3)) * M)[loff];
+      for (int i = 0; i < 16; ++i) v[i] = ldx(xt + (int64_t)(8 * (i >> 2) + (i & 3)) * M + loff);
     } else {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int64_t j = j0 + row32(i, half);
-        v[i] = (rowok && j < hi) ? X[j * M + mrow] : 0.0f;
+        v[i] = (rowok && j < hi) ? ldx(X + j * M + mrow) : 0.0f;
       }
     }
     return v;
@@ -843,16 +884,25 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const float* __restrict__ X,
   }
 }
 
-hipError_t rowpass(const Shape& s, const float* X, const void* Cqv, const __bf16* BqE, float* Wpart,
-                   const int64_t* tb, int R, hipStream_t st) {
+template <typename XT>
+static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const __bf16* BqE, float* Wpart,
+                           const int64_t* tb, int R, hipStream_t st) {
   const int nsg = (int)((s.nchunks + 3) / 4);
   const int R8 = (R + 7) / 8 * 8;
   const unsigned g = (unsigned)((int64_t)nsg * R8);
-  const f32x4* Cq = static_cast<const f32x4*>(Cqv);
   if (s.KP == 32)
-    k_rowpass<32><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
   else
-    k_rowpass<64><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+}
+
+hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const __bf16* BqE, float* Wpart,
+                   const int64_t* tb, int R, hipStream_t st) {
+  const f32x4* Cq = static_cast<const f32x4*>(Cqv);
+  if (s.xbf16)
+    rowpass_launch(s, static_cast<const __bf16*>(X), Cq, BqE, Wpart, tb, R, st);
+  else
+    rowpass_launch(s, static_cast<const float*>(X), Cq, BqE, Wpart, tb, R, st);
   return hipGetLastError();
 }
 

@@ -84,3 +84,18 @@ def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(did, "_lib", None)
     with pytest.raises(did.DidLibraryMissing):
         did.lib()
+
+
+def test_bf16_rounding_helper_matches_torch():
+    """workloads.round_to_bf16 (used to build the oracle's input for the bf16 storage form)
+    agrees with torch's own float32 -> bfloat16 conversion (round to nearest even)."""
+    import numpy as np
+    import torch
+
+    from workloads import round_to_bf16
+
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.random(5000) * 20.0, rng.random(5000) * 1e-3, np.array([0.0, 1.0, 3.0e38])])
+    x = x.astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(round_to_bf16(x), ref)

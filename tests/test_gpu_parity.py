@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import paper_1802_08938_amd as did
-from workloads import as_oracle_input, image_like, large_halfnormal, planted_lowrank, to_f32_colmajor
+from workloads import as_oracle_input, image_like, large_halfnormal, planted_lowrank, round_to_bf16, to_f32_colmajor
 
 from _gpu import announce, device_x, read_factors, rel_fro, require_gpu, run_gpu
 
@@ -274,3 +274,47 @@ def test_init_scale_minimises_common_scale():
     alpha = float(np.sum(Xo * P) / np.sum(P * P))
     np.testing.assert_allclose(Bs @ Cs, alpha * P, rtol=1e-4)
     assert sc["f"] < un["f"]
+
+
+@pytest.mark.parametrize("M,N,K", [(500, 2000, 10), (130, 260, 64), (37, 45, 3)])
+def test_bf16_storage_form_matches_oracle_on_rounded_x(M, N, K):
+    """x_dtype = DID_BF16: the engine solves the problem for bf16(X) with float32-accurate
+    arithmetic, so it meets the float32 tolerances against the oracle run on bf16(X)."""
+    torch = require_gpu()
+    rng = np.random.default_rng(M + N + K)
+    X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
+    X32 = to_f32_colmajor(X)
+    Xr = round_to_bf16(X32)
+    o = did.did_default_opts()
+    o.x_dtype = did.DID_BF16
+    announce(f"bf16 storage M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 10), opts=o)
+    B0, C0 = out["init"]
+    B1o, C1o, _ = oracle.did_run(Xr, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = oracle.did_run(Xr, B0, C0, 10)
+    fg = np.append(out["hist"], out["f"])
+    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+
+
+def test_bf16_storage_rejects_bad_x_and_borrow_is_ignored():
+    torch = require_gpu()
+    X = np.ones((40, 40), dtype=np.float32)
+    X[1, 1] = -2.0
+    o = did.did_default_opts()
+    o.x_dtype = did.DID_BF16
+    o.borrow_x = 1
+    announce("bf16 storage invalid X")
+    with pytest.raises(did.DidError) as ei:
+        did.did_init_ex(device_x(torch, X), 40, 40, 2, 1, o)
+    assert ei.value.code == did.DID_EINVAL
+    X[1, 1] = 2.0
+    Xd = device_x(torch, X)
+    h = did.did_init_ex(Xd, 40, 40, 2, 1, o)
+    try:
+        Xd.zero_()  # the engine holds its own bf16 copy: changing the caller's X has no effect
+        did.did_iterate(h, 2)
+        assert did.did_objective(h) > 0.0
+    finally:
+        did.did_free(h)

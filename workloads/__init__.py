@@ -40,6 +40,7 @@ __all__ = [
     "to_f32_colmajor",
     "as_oracle_input",
     "serving_jobs",
+    "round_to_bf16",
 ]
 
 
@@ -163,3 +164,13 @@ def serving_jobs(n_jobs, seed=5, rate=200.0, M_range=(100, 4000), N_range=(1000,
     seeds = rng.integers(0, 2**31 - 1, size=n_jobs)
     return [dict(t=float(t[i]), M=int(Ms[i]), N=int(Ns[i]), K=int(min(Ks[i], Ms[i], Ns[i])),
                  seed=int(seeds[i])) for i in range(n_jobs)]
+
+
+def round_to_bf16(X):
+    """Values of bf16(X) (round to nearest even) as float64: the data the reduced-precision
+    storage form of X holds.  Finite inputs only (a storage format conversion, done on bits)."""
+    x32 = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+    u = x32.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64).reshape(x32.shape)
