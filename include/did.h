@@ -51,6 +51,12 @@ enum {
 
 enum { DID_F32 = 0, DID_BF16 = 1 }; /* storage type of X inside the engine */
 
+/* Update order of one iteration (did_opts.algorithm). */
+enum {
+  DID_ALG_DID = 0, /* Alg. 3: C sweep, one reduction of (W, V), incremental B update */
+  DID_ALG_DBCD = 1 /* Alg. 2 (DBCD), an ablation: one reduction per column of B; same iterates */
+};
+
 #define DID_MAX_K 64
 
 /*
@@ -75,7 +81,13 @@ enum { DID_F32 = 0, DID_BF16 = 1 }; /* storage type of X inside the engine */
  *   borrow_x       0: X is copied into engine-owned memory.  1: a device X is adopted
  *                  without a copy; the caller keeps it alive and unmodified until
  *                  did_free.  Ignored (copy) for host pointers.
+ *   algorithm      DID_ALG_DID (default) or DID_ALG_DBCD.  DBCD is available on the
+ *                  thin-matrix path only (M <= 16 and K <= 8; DID_EINVAL otherwise).
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
+ *
+ * Shapes with M <= 16 and K <= 8 (such as the experiments' synthetic sets, M = 5, K = 3)
+ * run on a thin-matrix path that keeps each column in registers and makes one fused pass
+ * over X per iteration; other shapes run the MFMA column/row passes.
  */
 typedef struct did_opts {
   int32_t n_blocks;
@@ -83,12 +95,12 @@ typedef struct did_opts {
   int32_t refresh_every;
   int32_t init_scale;
   int32_t borrow_x;
-  int32_t reserved0;
+  int32_t algorithm;
   void* stream;
 } did_opts;
 
 /* Fill *opts with the defaults: n_blocks 0, DID_F32, refresh_every 1, init_scale 0,
- * borrow_x 0, stream NULL.  Returns DID_EINVAL for a NULL pointer. */
+ * borrow_x 0, DID_ALG_DID, stream NULL.  Returns DID_EINVAL for a NULL pointer. */
 int did_default_opts(did_opts* opts);
 
 /*

@@ -16,6 +16,7 @@ import os
 
 __all__ = [
     "DID_OK", "DID_EINVAL", "DID_ENOMEM", "DID_EDEVICE", "DID_ESTATE", "DID_F32", "DID_BF16", "DID_MAX_K",
+    "DID_ALG_DID", "DID_ALG_DBCD",
     "DidError", "DidLibraryMissing", "did_opts", "lib", "library_path",
     "did_default_opts", "did_init", "did_init_ex", "did_init_from_factors", "did_iterate", "did_objective",
     "did_factors", "did_history", "did_iterations", "did_sync", "did_free", "did_last_error",
@@ -24,6 +25,7 @@ __all__ = [
 
 DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
 DID_F32, DID_BF16 = 0, 1
+DID_ALG_DID, DID_ALG_DBCD = 0, 1
 DID_MAX_K = 64
 
 EXPORTED_SYMBOLS = (
@@ -56,7 +58,7 @@ class did_opts(ctypes.Structure):
         ("refresh_every", ctypes.c_int32),
         ("init_scale", ctypes.c_int32),
         ("borrow_x", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("algorithm", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

@@ -57,6 +57,8 @@ struct did_ctx {
   void* Cq = nullptr;
   double* W = nullptr;
   float* Wpart = nullptr;
+  double* tpart = nullptr;  // thin path: block partials
+  int algorithm = DID_ALG_DID;
   int R = 1;
   int64_t* rbounds = nullptr;
   double* fpart = nullptr;
@@ -183,6 +185,12 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   s.nchunks = (M + 31) / 32;
   s.Mpad = s.nchunks * 32;
   s.xbf16 = o.x_dtype == DID_BF16;
+  s.thin = (M <= 16 && K <= 8) ? 1 : 0;
+  if (o.algorithm != DID_ALG_DID && o.algorithm != DID_ALG_DBCD) return fail(DID_EINVAL, "unknown algorithm");
+  if (o.algorithm == DID_ALG_DBCD && !s.thin)
+    return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8)");
+  if (s.thin && s.xbf16) return fail(DID_EINVAL, "the thin-matrix path stores X as float32 only");
+  h->algorithm = o.algorithm;
 
   // float32 view of X on the device: the caller's device buffer (borrowed, or read once for
   // the bf16 form) or an upload
@@ -253,27 +261,32 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
-  if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
-  if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
-  {
+  if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
+  if (s.thin) {
+    if ((rc = dalloc(h, &h->tpart, didk::thin_blocks(s) * didk::thin_slots(16, 8)))) return rc;
+  } else {
+    if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
+    if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
     unsigned char* cq = nullptr;
     if ((rc = dalloc(h, &cq, didk::cq_bytes(s)))) return rc;
     h->Cq = cq;
+    if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
+    if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
+    if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
   }
-  if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
-  if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
-  if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
-  if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
   if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
 
   if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->Cq, 0, (size_t)didk::cq_bytes(s), h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
-      (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
-          hipSuccess)
+      (e = hipMemsetAsync(h->W, 0, (size_t)s.KP * s.Mpad * 8, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess)
+    return dev_fail(h, e, "buffer setup");
+  if (!s.thin &&
+      ((e = hipMemsetAsync(h->Cq, 0, (size_t)didk::cq_bytes(s), h->st)) != hipSuccess ||
+       (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
+           hipSuccess))
     return dev_fail(h, e, "buffer setup");
   return DID_OK;
 }
@@ -293,11 +306,24 @@ int check_handle(did_ctx* h) {
 
 int objective_pass(did_ctx* h) {
   hipError_t e;
+  if (h->s.thin) {
+    if ((e = didk::thin_pass(h->s, static_cast<const float*>(h->X), h->B, h->G, h->C, h->tpart, 1, h->st)) !=
+            hipSuccess ||
+        (e = didk::thin_reduce(h->s, h->tpart, h->W, h->V, h->fobj, 0.5, 0, h->st)) != hipSuccess)
+      return dev_fail(h, e, "objective pass");
+    return DID_OK;
+  }
   if ((e = didk::colpass(h->s, h->X, h->Cq, h->BqE, h->BqH, h->H, h->fpart, 0, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective pass");
   if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective reduce");
   return DID_OK;
+}
+
+// Repack C after it was changed outside the sweep (the thin path keeps no packed copy).
+hipError_t pack_c(did_ctx* h) {
+  if (h->s.thin) return hipSuccess;
+  return didk::packc(h->s, h->C, h->Cq, h->st);
 }
 
 int apply_init_scale(did_ctx* h) {
@@ -309,7 +335,7 @@ int apply_init_scale(did_ctx* h) {
   hipError_t e;
   for (int q = 0; q < 3; ++q) {
     if (q && ((e = didk::scale(h->C, nC, mul[q], h->st)) != hipSuccess ||
-              (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess))
+              (e = pack_c(h)) != hipSuccess))
       return dev_fail(h, e, "init scale");
     int rc = objective_pass(h);
     if (rc) return rc;
@@ -318,7 +344,7 @@ int apply_init_scale(did_ctx* h) {
       return dev_fail(h, e, "init scale");
   }
   if ((e = didk::scale(h->C, nC, 0.25f, h->st)) != hipSuccess ||
-      (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess)
+      (e = pack_c(h)) != hipSuccess)
     return dev_fail(h, e, "init scale");
   const double c = (fv[2] - 3.0 * fv[1] + 2.0 * fv[0]) / 3.0;
   const double b = 1.5 * c - (fv[1] - fv[0]);
@@ -326,7 +352,7 @@ int apply_init_scale(did_ctx* h) {
     const float r = (float)std::sqrt(b / c);
     if ((e = didk::scale(h->C, nC, r, h->st)) != hipSuccess ||
         (e = didk::scale(h->B, h->s.M * h->s.K, r, h->st)) != hipSuccess ||
-        (e = refresh_b_derived(h)) != hipSuccess || (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess)
+        (e = refresh_b_derived(h)) != hipSuccess || (e = pack_c(h)) != hipSuccess)
       return dev_fail(h, e, "init scale");
   }
   return DID_OK;
@@ -377,7 +403,7 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
       return rc;
     }
   }
-  if ((e = refresh_b_derived(h)) != hipSuccess || (e = didk::packc(h->s, h->C, h->Cq, h->st)) != hipSuccess) {
+  if ((e = refresh_b_derived(h)) != hipSuccess || (e = pack_c(h)) != hipSuccess) {
     rc = dev_fail(h, e, "pack B, C");
     release(h);
     return rc;
@@ -410,6 +436,7 @@ int did_default_opts(did_opts* o) {
   o->refresh_every = 1;
   o->init_scale = 0;
   o->borrow_x = 0;
+  o->algorithm = DID_ALG_DID;
   o->stream = nullptr;
   return DID_OK;
 }
@@ -432,6 +459,53 @@ int did_init_from_factors(const void* X, int64_t M, int64_t N, int32_t K, const 
   return init_common(X, M, N, K, 0, B, C, opts, out);
 }
 
+// Thin-matrix iterations.  DID: one fused column pass (sweep, W/V/f partials), their
+// fixed-order reduction, the B update and G.  DBCD: the C half, then per column of B one
+// pass over X and one reduction, then G.  Stages are recorded at the same positions as the
+// main path's (column_pass, reduce_f/_v/_w, b_update, reduce_g); unused ones are empty.
+static int iterate_thin(did_ctx* h, int32_t n) {
+  const Shape& s = h->s;
+  hipError_t e;
+  const float* X = static_cast<const float*>(h->X);
+  for (int32_t it = 0; it < n; ++it) {
+    hipEvent_t* ev = nullptr;
+    if (h->profiling) {
+      const size_t base = h->prof_events.size();
+      h->prof_events.resize(base + kStages + 1, nullptr);
+      for (int q = 0; q <= kStages; ++q)
+        if ((e = hipEventCreate(&h->prof_events[base + q])) != hipSuccess) return dev_fail(h, e, "profile event");
+      ev = h->prof_events.data() + base;
+    }
+    auto mark = [&](int q) { return ev ? hipEventRecord(ev[q], h->st) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return dev_fail(h, e, "profile record");
+    const int mode = h->algorithm == DID_ALG_DBCD ? 2 : 0;
+    if ((e = didk::thin_pass(s, X, h->B, h->G, h->C, h->tpart, mode, h->st)) != hipSuccess)
+      return dev_fail(h, e, "thin column pass");
+    if ((e = mark(1)) != hipSuccess) return dev_fail(h, e, "profile record");
+    if ((e = didk::thin_reduce(s, h->tpart, h->W, h->V, h->fhist + (h->t % kHistCap), 0.5, mode == 0, h->st)) !=
+        hipSuccess)
+      return dev_fail(h, e, "thin reduce");
+    for (int q = 2; q <= 5; ++q)
+      if ((e = mark(q)) != hipSuccess) return dev_fail(h, e, "profile record");
+    if (mode == 0) {
+      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
+        return dev_fail(h, e, "B update");
+    } else {
+      for (int i = 0; i < s.K; ++i)
+        if ((e = didk::dbcd_b_step(s, X, h->B, h->C, h->tpart, i, h->st)) != hipSuccess)
+          return dev_fail(h, e, "DBCD B step");
+      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st)) != hipSuccess)
+        return dev_fail(h, e, "pack B");
+    }
+    if ((e = mark(7)) != hipSuccess) return dev_fail(h, e, "profile record");
+    if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
+      return dev_fail(h, e, "G reduce");
+    if ((e = mark(8)) != hipSuccess) return dev_fail(h, e, "profile record");
+    ++h->t;
+  }
+  return DID_OK;
+}
+
 int did_iterate(did_handle h, int32_t n) {
   int rc = check_handle(h);
   if (rc) return rc;
@@ -439,6 +513,7 @@ int did_iterate(did_handle h, int32_t n) {
   DeviceGuard g(h->dev);
   const Shape& s = h->s;
   hipError_t e;
+  if (s.thin) return iterate_thin(h, n);
   for (int32_t it = 0; it < n; ++it) {
     hipEvent_t* ev = nullptr;
     if (h->profiling) {

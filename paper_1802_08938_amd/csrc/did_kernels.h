@@ -15,6 +15,7 @@ struct Shape {
   int64_t Mpad;      // nchunks * 32
   int vec4;          // vector loads of X are aligned (M % 4 == 0 and X aligned)
   int xbf16;         // X is stored as bf16 (reduced-precision storage form), else float32
+  int thin;          // thin-matrix path (M <= 16, K <= 8): one fused pass per iteration
 };
 
 // Number of bf16 entries of one packed-operand buffer (E-operand or H-operand) of B:
@@ -84,5 +85,18 @@ hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStr
 hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st);
+
+// ---- thin-matrix path (did_thin.hip) ----
+// mode 0: DID column work (sweep, W/V/f block partials); 1: objective partials only;
+// 2: DBCD C half (sweep, f partials).
+hipError_t thin_pass(const Shape& s, const float* X, const float* B, const double* G, float* C, double* part,
+                     int mode, hipStream_t st);
+// W (KP x Mpad), V (KP x KP) and *fout = scale * f from the block partials (with_wv = 0: f only)
+hipError_t thin_reduce(const Shape& s, const double* part, double* W, double* V, double* fout, double scale,
+                       int with_wv, hipStream_t st);
+// one DBCD column update b_i (a pass over X and a reduction)
+hipError_t dbcd_b_step(const Shape& s, const float* X, float* B, const float* C, double* part, int i, hipStream_t st);
+int64_t thin_blocks(const Shape& s);
+int thin_slots(int MM, int KK);
 
 }  // namespace didk

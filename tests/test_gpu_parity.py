@@ -318,3 +318,96 @@ def test_bf16_storage_rejects_bad_x_and_borrow_is_ignored():
         assert did.did_objective(h) > 0.0
     finally:
         did.did_free(h)
+
+
+@pytest.mark.parametrize("M,N,K", [(5, 4000, 3), (16, 700, 8), (9, 333, 5), (1, 100, 1), (8, 257, 4)])
+def test_thin_path_parity(M, N, K):
+    """M <= 16, K <= 8 runs the fused single-pass thin-matrix path."""
+    torch = require_gpu()
+    rng = np.random.default_rng(M * 31 + N + K)
+    X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
+    X32 = to_f32_colmajor(X)
+    announce(f"thin path M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 20))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    _, _, fo = _oracle_from(X32, B0, C0, 20)
+    fg = np.append(out["hist"], out["f"])
+    # M = 1, K = 1 factors exactly, so f falls to its float32 rounding floor (about
+    # 1e-14 f^0); relative error is measured against max(f, 1e-8 f^0).
+    assert np.max(np.abs(fg - fo) / np.maximum(fo, 1e-8 * fo[0])) <= TOL_OBJ
+
+
+def test_dbcd_ablation_follows_the_same_iterates():
+    """Alg. 2 (DBCD, K reductions per iteration) and Alg. 3 (DID, one) give the same
+    iterates; the GPU's DBCD also matches the oracle's DBCD."""
+    from oracle import bcd
+
+    torch = require_gpu()
+    rng = np.random.default_rng(77)
+    M, N, K = 5, 3000, 3
+    X = rng.random((M, K)) @ rng.random((K, N))
+    X32 = to_f32_colmajor(X)
+    o = did.did_default_opts()
+    o.algorithm = did.DID_ALG_DBCD
+    announce("DBCD vs DID")
+    dbcd_run = run_gpu(torch, X32, K, iters=(1, 10), opts=o)
+    did_run = run_gpu(torch, X32, K, iters=(1, 10))
+    for n in (1, 10):
+        assert rel_fro(dbcd_run[n][0], did_run[n][0]) <= TOL_FACTORS
+        assert rel_fro(dbcd_run[n][1], did_run[n][1]) <= TOL_FACTORS
+    B0, C0 = dbcd_run["init"]
+    Bo, Co = B0.copy(), C0.copy()
+    Xo = as_oracle_input(X32)
+    for _ in range(10):
+        bcd.dbcd_iteration(Xo, Bo, Co, oracle.column_blocks(N, 4))
+    assert rel_fro(dbcd_run[10][0], Bo) <= 1e-4
+    assert rel_fro(dbcd_run[10][1], Co) <= 1e-4
+
+
+def test_dbcd_needs_the_thin_path():
+    torch = require_gpu()
+    o = did.did_default_opts()
+    o.algorithm = did.DID_ALG_DBCD
+    X = np.ones((40, 50), dtype=np.float32)
+    announce("DBCD on a wide shape")
+    with pytest.raises(did.DidError) as ei:
+        did.did_init_ex(device_x(torch, X), 40, 50, 3, 1, o)
+    assert ei.value.code == did.DID_EINVAL
+
+
+def test_stopping_rule_iteration_count_matches_oracle():
+    """The experiments' stopping rule ||E^t||^2 <= 1e-6 ||E^0||^2 on the experiments' shape
+    (M = 5, K = 3): the GPU stops at the oracle's iteration (within one, for float32
+    rounding at the threshold), and DID and DBCD stop together (the paper's Correctness
+    paragraph)."""
+    from workloads import paper_synthetic
+
+    torch = require_gpu()
+    X, _, _ = paper_synthetic(20000, seed=4)
+    X32 = to_f32_colmajor(X)
+
+    def gpu_count(alg):
+        o = did.did_default_opts()
+        o.algorithm = alg
+        h = did.did_init_ex(device_x(torch, X32), 5, 20000, 3, 2024, o)
+        try:
+            Bt = np.empty((3, 5), np.float32)
+            Ct = np.empty((20000, 3), np.float32)
+            did.did_factors(h, Bt, Ct)
+            did.did_iterate(h, 3000)
+            f = np.append(did.did_history(h), did.did_objective(h))
+        finally:
+            did.did_free(h)
+        hit = np.nonzero(f <= 1e-6 * f[0])[0]
+        return (int(hit[0]) if hit.size else None), Bt.T.astype(np.float64), Ct.T.astype(np.float64)
+
+    announce("stopping rule on the experiments' shape")
+    t_did, B0, C0 = gpu_count(did.DID_ALG_DID)
+    t_dbcd, _, _ = gpu_count(did.DID_ALG_DBCD)
+    t_or, _ = oracle.iterations_to_tolerance(as_oracle_input(X32), B0, C0, eps=1e-6, max_iter=3000)
+    assert t_did is not None and t_dbcd is not None
+    assert abs(t_did - t_dbcd) <= 1
+    assert abs(t_did - t_or) <= 1, (t_did, t_or)
