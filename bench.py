@@ -7,10 +7,16 @@ device (X = B0 C0 + |0.01 N(0,1)|, U[0,1] factors) and stays in HBM.
 
 Prints one JSON line:
   value          iterations/s of the whole job (inputs resident in HBM at the start),
-  roofline       the dominant kernel (the column pass) against the FP32 MFMA peak,
+  roofline       the dominant kernel (column or row pass) against the float32-accurate
+                 MFMA peak of its split-bf16 products,
   cpu_baseline   the FP64 oracle timed on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|image|planted]
+``--workload paper`` runs the experiments' synthetic shape instead (M = 5, K = 3,
+N = 10^5 ... 10^8, X = B0 C0 with U[0,1] factors): iterations and seconds to the stopping
+rule ||E^t||^2 <= 1e-6 ||E^0||^2 for DID and for the DBCD ablation, beside the paper's
+Table 2 (16 CPU nodes), and iterations/s at N = 10^8 as the line's value.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|large_bf16|image|planted|paper]
 """
 
 from __future__ import annotations
@@ -26,7 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DID iters/s + HBM GB/s (M=5000,N=1e6,K=50); served solves/s, p50/p99 latency"
-PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
+# The passes form every float32 product from six bf16 MFMA products of three-way splits of
+# the operands, so their float32-accurate peak is the bf16 peak over six.
+SPLIT_PRODUCTS = 6
+PEAK_SPLIT_TFLOPS = PEAK_BF16_MFMA_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
@@ -40,6 +50,18 @@ WORKLOADS = {
                   desc="plain FP32 DID, M=784 N=70000 K=16, 4 column blocks, image-like X in [0,1]"),
     "planted": dict(M=500, N=2000, K=10, n_blocks=1,
                     desc="plain FP32 DID, M=500 N=2000 K=10, noiseless X=B0*C0"),
+    "paper": dict(M=5, N=100_000_000, K=3, n_blocks=16,
+                  desc="experiments' synthetic shape: M=5 K=3, N=1e5..1e8, X=B0*C0 with B0,C0~U[0,1], "
+                       "stopping rule ||E||^2 <= 1e-6 ||E0||^2, DID and DBCD (thin-matrix path)"),
+}
+
+# Table 2 of the paper (16 CPU nodes, one core each; C + GSL + OpenMPI): iterations to the
+# stopping rule and seconds for DID and DBCD on the synthetic sets M = 5, K = 3.
+PAPER_TABLE2 = {
+    100_000: dict(iterations=549, did_s=1.17, dbcd_s=1.42),
+    1_000_000: dict(iterations=396, did_s=8.61, dbcd_s=14.04),
+    10_000_000: dict(iterations=654, did_s=106.60, dbcd_s=126.01),
+    100_000_000: dict(iterations=302, did_s=610.09, dbcd_s=785.57),
 }
 
 
@@ -62,7 +84,7 @@ def algorithmic_counts(M, N, K):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("did_kernels.hip", "did_kernels.h"):
+    for f in ("did_kernels.hip", "did_kernels.h", "did_thin.hip"):
         with open(os.path.join(ROOT, "paper_1802_08938_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,6 +158,123 @@ def cpu_baseline(name, cfg):
                                f"host cpu_count={os.cpu_count()}"}
 
 
+def _solve_to_eps(torch, did, X, M, N, K, alg, stream, eps, cap, n_blocks):
+    """Iterations to the stopping rule from the seed-12345 initial factors, then the time of
+    exactly that many iterations from the same start (HIP events on the engine's stream)."""
+    def start():
+        o = did.did_default_opts()
+        o.n_blocks = n_blocks
+        o.borrow_x = 1
+        o.algorithm = alg
+        o.stream = stream.cuda_stream
+        return did.did_init_ex(X, M, N, K, 12345, o)
+
+    h = start()
+    try:
+        did.did_iterate(h, cap)
+        f = did.did_history(h) + [did.did_objective(h)]
+    finally:
+        did.did_free(h)
+    t_eps = next((t for t, v in enumerate(f) if v <= eps * f[0]), None)
+    if t_eps is None:
+        return None, None, f[-1] / f[0]
+    h = start()
+    try:
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        did.did_iterate(h, t_eps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        seconds = ev0.elapsed_time(ev1) / 1e3
+    finally:
+        did.did_free(h)
+    return t_eps, seconds, f[t_eps] / f[0]
+
+
+def run_paper_shape(args, torch, did):
+    from workloads import paper_synthetic_device
+
+    cfg = WORKLOADS["paper"]
+    M, K = cfg["M"], cfg["K"]
+    stream = torch.cuda.Stream()
+    table = []
+    X = None
+    sizes = [n for n in sorted(PAPER_TABLE2) if n <= args.paper_max_n]
+    for N in sizes:
+        del X
+        torch.cuda.empty_cache()
+        log(f"paper shape N={N}: generating")
+        X = paper_synthetic_device(torch, N, M=M, K=K, seed=4)
+        torch.cuda.synchronize()
+        row = {"N": N}
+        if args.no_table:
+            continue
+        for name, alg in (("did", did.DID_ALG_DID), ("dbcd", did.DID_ALG_DBCD)):
+            log(f"paper shape N={N}: {name} to eps")
+            t, sec, ratio = _solve_to_eps(torch, did, X, M, N, K, alg, stream, 1e-6, 5000, cfg["n_blocks"])
+            row[f"{name}_iterations"] = t
+            row[f"{name}_seconds"] = None if sec is None else round(sec, 5)
+            row[f"{name}_final_ratio"] = ratio
+        ref = PAPER_TABLE2[N]
+        row["paper_iterations"] = ref["iterations"]
+        row["paper_did_seconds"] = ref["did_s"]
+        row["paper_dbcd_seconds"] = ref["dbcd_s"]
+        table.append(row)
+    # steady-state rate at the largest N, DID, with the per-stage split
+    N = sizes[-1]
+    opts = did.did_default_opts()
+    opts.n_blocks = cfg["n_blocks"]
+    opts.borrow_x = 1
+    opts.stream = stream.cuda_stream
+    h = did.did_init_ex(X, M, N, K, 12345, opts)
+    try:
+        did.did_iterate(h, args.warmup)
+        did.did_profile(h, True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} DID steps at N={N}")
+        ev0.record(stream)
+        did.did_iterate(h, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        stages, n_it = did.did_profile_read(h)
+        did.did_profile(h, False)
+    finally:
+        did.did_free(h)
+    kern_ms = stages["column_pass"] / max(n_it, 1)
+    # thin pass: X read once (4MN), C read and written (8KN)
+    kbytes = 4.0 * M * N + 8.0 * K * N
+    achieved = kbytes / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 4),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "M": M, "N": N, "K": K, "n_blocks": cfg["n_blocks"]},
+        "stage_ms_per_iter": {k: round(v / max(n_it, 1), 4) for k, v in stages.items()},
+        "roofline": {"bound": "hbm", "kernel": "thin_pass", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic("thin_pass", "paper"),
+                     "kernel_ms": round(kern_ms, 4), "bytes_per_launch": kbytes},
+        "table2": table,
+        "table2_note": "GPU seconds = time of exactly t_eps iterations from the same start; paper's seconds are "
+                       "its Table 2 on 16 CPU nodes (one core each), other random data of the same recipe",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +282,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paper-max-n", type=float, default=1e8, help="paper workload: largest N")
+    ap.add_argument("--no-table", action="store_true", help="paper workload: skip the runs to the stopping rule")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "
@@ -154,6 +295,9 @@ def main():
     import paper_1802_08938_amd as did
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "paper":
+        run_paper_shape(args, torch, did)
+        return
     cfg = WORKLOADS[args.workload]
     M, N, K = cfg["M"], cfg["N"], cfg["K"]
     log(f"generating {args.workload} input {M}x{N} on the device")
@@ -213,9 +357,19 @@ def main():
     dom_ms = stages[dom] / max(n_it, 1)
     achieved = cnt["pass_flops"] / (dom_ms * 1e-3) / 1e12
     traffic = measured_traffic(dom, args.workload)
-    roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic,
-            "kernel_ms": round(dom_ms, 4), "flops_per_launch": cnt["pass_flops"]}
+    KP = 32 if K <= 32 else 64
+    issued = SPLIT_PRODUCTS * 4.0 * M * N * KP  # bf16 MFMA flops the pass issues (K padded to KP)
+    roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_SPLIT_TFLOPS, 2),
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic,
+            "kernel_ms": round(dom_ms, 4), "flops_per_launch": cnt["pass_flops"],
+            "peak_note": "float32-accurate flops (4MNK per pass) against the bf16 MFMA peak / 6 "
+                         "(six bf16 products per float32 product)",
+            "mfma_bf16_issued_tflops": round(issued / (dom_ms * 1e-3) / 1e12, 1),
+            "mfma_bf16_issued_frac": round(issued / (dom_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
+            "hbm_algorithmic_gbs": round(cnt["pass_bytes"] / (dom_ms * 1e-3) / 1e9, 1),
+            "hbm_algorithmic_frac": round(cnt["pass_bytes"] / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    if traffic is not None:
+        roof["hbm_measured_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
     line = {
         "metric": METRIC,
         "value": round(it_s, 4),

@@ -82,11 +82,11 @@ enum {
  *                  without a copy; the caller keeps it alive and unmodified until
  *                  did_free.  Ignored (copy) for host pointers.
  *   algorithm      DID_ALG_DID (default) or DID_ALG_DBCD.  DBCD is available on the
- *                  thin-matrix path only (M <= 16 and K <= 8; DID_EINVAL otherwise).
+ *                  thin-matrix path only (DID_EINVAL otherwise).
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
  *
- * Shapes with M <= 16 and K <= 8 (such as the experiments' synthetic sets, M = 5, K = 3)
- * run on a thin-matrix path that keeps each column in registers and makes one fused pass
+ * Shapes with M <= 16, K <= 8 and M <= 8 or K <= 4 (such as the experiments' synthetic
+ * sets, M = 5, K = 3) run on a thin-matrix path that keeps each column in registers and makes one fused pass
  * over X per iteration; other shapes run the MFMA column/row passes.
  */
 typedef struct did_opts {

@@ -185,12 +185,14 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   s.nchunks = (M + 31) / 32;
   s.Mpad = s.nchunks * 32;
   s.xbf16 = o.x_dtype == DID_BF16;
-  s.thin = (M <= 16 && K <= 8) ? 1 : 0;
+  s.thin = (M <= 16 && K <= 8 && (M <= 8 || K <= 4)) ? 1 : 0;
   if (o.algorithm != DID_ALG_DID && o.algorithm != DID_ALG_DBCD) return fail(DID_EINVAL, "unknown algorithm");
   if (o.algorithm == DID_ALG_DBCD && !s.thin)
-    return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8)");
+    return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8, M <= 8 or K <= 4)");
   if (s.thin && s.xbf16) return fail(DID_EINVAL, "the thin-matrix path stores X as float32 only");
   h->algorithm = o.algorithm;
+  if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
+    return fail(DID_EDEVICE, "thin path: occupancy query failed");
 
   // float32 view of X on the device: the caller's device buffer (borrowed, or read once for
   // the bf16 form) or an upload
@@ -263,7 +265,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
   if (s.thin) {
-    if ((rc = dalloc(h, &h->tpart, didk::thin_blocks(s) * didk::thin_slots(16, 8)))) return rc;
+    if ((rc = dalloc(h, &h->tpart, didk::thin_blocks(s) * didk::thin_slots(16, 4)))) return rc;
   } else {
     if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
     if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;
@@ -485,14 +487,15 @@ static int iterate_thin(did_ctx* h, int32_t n) {
     if ((e = didk::thin_reduce(s, h->tpart, h->W, h->V, h->fhist + (h->t % kHistCap), 0.5, mode == 0, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "thin reduce");
-    for (int q = 2; q <= 5; ++q)
+    // the thin path has no separate sweep, V or row pass: their stages are empty
+    for (int q = 2; q <= 6; ++q)
       if ((e = mark(q)) != hipSuccess) return dev_fail(h, e, "profile record");
     if (mode == 0) {
       if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
         return dev_fail(h, e, "B update");
     } else {
       for (int i = 0; i < s.K; ++i)
-        if ((e = didk::dbcd_b_step(s, X, h->B, h->C, h->tpart, i, h->st)) != hipSuccess)
+        if ((e = didk::dbcd_b_step(s, X, h->B, h->C, h->tpart, h->W, i, h->st)) != hipSuccess)
           return dev_fail(h, e, "DBCD B step");
       if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st)) != hipSuccess)
         return dev_fail(h, e, "pack B");

@@ -15,7 +15,8 @@ struct Shape {
   int64_t Mpad;      // nchunks * 32
   int vec4;          // vector loads of X are aligned (M % 4 == 0 and X aligned)
   int xbf16;         // X is stored as bf16 (reduced-precision storage form), else float32
-  int thin;          // thin-matrix path (M <= 16, K <= 8): one fused pass per iteration
+  int thin;          // thin-matrix path (M <= 16, K <= 8, M <= 8 or K <= 4): one fused pass per iteration
+  int64_t thin_grid; // thin path: blocks per launch (one wave of resident blocks)
 };
 
 // Number of bf16 entries of one packed-operand buffer (E-operand or H-operand) of B:
@@ -94,9 +95,13 @@ hipError_t thin_pass(const Shape& s, const float* X, const float* B, const doubl
 // W (KP x Mpad), V (KP x KP) and *fout = scale * f from the block partials (with_wv = 0: f only)
 hipError_t thin_reduce(const Shape& s, const double* part, double* W, double* V, double* fout, double scale,
                        int with_wv, hipStream_t st);
-// one DBCD column update b_i (a pass over X and a reduction)
-hipError_t dbcd_b_step(const Shape& s, const float* X, float* B, const float* C, double* part, int i, hipStream_t st);
+// one DBCD column update b_i (a pass over X and a reduction); yz holds M + 1 doubles of
+// scratch (at least 17)
+hipError_t dbcd_b_step(const Shape& s, const float* X, float* B, const float* C, double* part, double* yz, int i,
+                       hipStream_t st);
 int64_t thin_blocks(const Shape& s);
+// blocks for the thin kernels on the current device (< 0: the runtime query failed)
+int64_t thin_grid_for(const Shape& s);
 int thin_slots(int MM, int KK);
 
 }  // namespace didk

@@ -320,9 +320,11 @@ def test_bf16_storage_rejects_bad_x_and_borrow_is_ignored():
         did.did_free(h)
 
 
-@pytest.mark.parametrize("M,N,K", [(5, 4000, 3), (16, 700, 8), (9, 333, 5), (1, 100, 1), (8, 257, 4)])
+@pytest.mark.parametrize("M,N,K", [(5, 4000, 3), (16, 700, 4), (8, 700, 8), (7, 333, 5), (1, 100, 1), (8, 257, 4),
+                                   (5, 100_003, 3), (16, 700, 8)])
 def test_thin_path_parity(M, N, K):
-    """M <= 16, K <= 8 runs the fused single-pass thin-matrix path."""
+    """M <= 16, K <= 8 (M <= 8 or K <= 4) runs the fused single-pass thin-matrix path;
+    (16, 700, 8) lies just outside it and runs the MFMA passes."""
     torch = require_gpu()
     rng = np.random.default_rng(M * 31 + N + K)
     X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
@@ -340,19 +342,19 @@ def test_thin_path_parity(M, N, K):
     assert np.max(np.abs(fg - fo) / np.maximum(fo, 1e-8 * fo[0])) <= TOL_OBJ
 
 
-def test_dbcd_ablation_follows_the_same_iterates():
+@pytest.mark.parametrize("M,N,K", [(5, 3000, 3), (12, 2000, 4)])
+def test_dbcd_ablation_follows_the_same_iterates(M, N, K):
     """Alg. 2 (DBCD, K reductions per iteration) and Alg. 3 (DID, one) give the same
     iterates; the GPU's DBCD also matches the oracle's DBCD."""
     from oracle import bcd
 
     torch = require_gpu()
     rng = np.random.default_rng(77)
-    M, N, K = 5, 3000, 3
     X = rng.random((M, K)) @ rng.random((K, N))
     X32 = to_f32_colmajor(X)
     o = did.did_default_opts()
     o.algorithm = did.DID_ALG_DBCD
-    announce("DBCD vs DID")
+    announce(f"DBCD vs DID M={M} N={N} K={K}")
     dbcd_run = run_gpu(torch, X32, K, iters=(1, 10), opts=o)
     did_run = run_gpu(torch, X32, K, iters=(1, 10))
     for n in (1, 10):

@@ -36,6 +36,7 @@ __all__ = [
     "large_halfnormal",
     "large_halfnormal_device",
     "paper_synthetic",
+    "paper_synthetic_device",
     "identifiable_plant",
     "to_f32_colmajor",
     "as_oracle_input",
@@ -122,6 +123,24 @@ def paper_synthetic(N, M=5, K=3, seed=4):
     B0 = rng.random((M, K))
     C0 = rng.random((K, N))
     return B0 @ C0, B0, C0
+
+
+def paper_synthetic_device(torch, N, M=5, K=3, seed=4, device="cuda"):
+    """Device-side generator with ``paper_synthetic``'s recipe (U[0,1] factors, X = B0 C0)
+    for sizes up to N = 10^8; draws from torch's device generator, so the values differ
+    from the host generator's.  Returns X in column-major storage as an (N, M) float32
+    tensor."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    B0t = torch.rand((K, M), generator=g, device=device, dtype=torch.float32)
+    Xt = torch.empty((N, M), device=device, dtype=torch.float32)
+    step = 1 << 24
+    for a in range(0, N, step):
+        b = min(N, a + step)
+        C0t = torch.rand((b - a, K), generator=g, device=device, dtype=torch.float32)
+        torch.matmul(C0t, B0t, out=Xt[a:b])
+        del C0t
+    return Xt
 
 
 def identifiable_plant(M, N, K, seed):
