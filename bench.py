@@ -16,7 +16,17 @@ N = 10^5 ... 10^8, X = B0 C0 with U[0,1] factors): iterations and seconds to the
 rule ||E^t||^2 <= 1e-6 ||E^0||^2 for DID and for the DBCD ablation, beside the paper's
 Table 2 (16 CPU nodes), and iterations/s at N = 10^8 as the line's value.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|large_bf16|image|planted|paper]
+``--workload batch`` advances a set of jobs drawn from the served workload's shape
+distribution (M ~ U{100..4000}, N ~ LogU[1e3, 2e5], K ~ U{5..64}) for --steps
+iterations, once one instance after another (the plain form) and once as one batch
+(grouped persistent kernels replayed from a hipGraph), and reports the batched rate, its
+speedup and the bitwise agreement of the results.  ``--workload serve`` runs the serving
+form: Poisson arrivals at 200 jobs/s, admission by a 200 GB budget, continuous batching,
+each job to 50 iterations or a relative objective change below 1e-4; it reports solves/s
+and p50/p99 latency from the scheduled arrival to retirement.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload large|large_bf16|image|planted|paper|batch|serve]
 """
 
 from __future__ import annotations
@@ -50,6 +60,13 @@ WORKLOADS = {
                   desc="plain FP32 DID, M=784 N=70000 K=16, 4 column blocks, image-like X in [0,1]"),
     "planted": dict(M=500, N=2000, K=10, n_blocks=1,
                     desc="plain FP32 DID, M=500 N=2000 K=10, noiseless X=B0*C0"),
+    "batch": dict(M=0, N=0, K=0, n_blocks=0, jobs=48,
+                  desc="batched form: 48 jobs with M~U{100..4000}, N~LogU[1e3,2e5], K~U{5..64}, "
+                       "X=max(0,B0*C0+0.02*N(0,1)), advanced together vs one after another"),
+    "serve": dict(M=0, N=0, K=0, n_blocks=0, jobs=1000,
+                  desc="serving form: Poisson arrivals at 200 jobs/s, M~U{100..4000}, N~LogU[1e3,2e5], "
+                       "K~U{5..64}, X=max(0,B0*C0+0.02*N(0,1)) float32, 200 GB budget, <=50 iterations or "
+                       "relative objective change <1e-4"),
     "paper": dict(M=5, N=100_000_000, K=3, n_blocks=16,
                   desc="experiments' synthetic shape: M=5 K=3, N=1e5..1e8, X=B0*C0 with B0,C0~U[0,1], "
                        "stopping rule ||E||^2 <= 1e-6 ||E0||^2, DID and DBCD (thin-matrix path)"),
@@ -275,6 +292,209 @@ def run_paper_shape(args, torch, did):
     print(json.dumps(line), flush=True)
 
 
+def _job_inputs(torch, jobs, x_dtype):
+    from workloads import serving_x_device
+
+    g = torch.Generator(device="cuda")
+    out = []
+    for j in jobs:
+        g.manual_seed(j["seed"])
+        out.append(serving_x_device(torch, j["M"], j["N"], j["K"], j["seed"], generator=g))
+    return out
+
+
+def run_batch(args, torch, did):
+    """Plain form (instances one after another) against the batched form, same jobs."""
+    import numpy as np
+
+    from workloads import serving_jobs
+
+    cfg = WORKLOADS["batch"]
+    jobs = serving_jobs(cfg["jobs"], seed=5)
+    log(f"batch: generating {len(jobs)} inputs")
+    Xs = _job_inputs(torch, jobs, did.DID_F32)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    def make_all():
+        hs = []
+        for j, X in zip(jobs, Xs):
+            o = did.did_default_opts()
+            o.borrow_x = 1
+            o.stream = stream.cuda_stream
+            hs.append(did.did_init_ex(X, j["M"], j["N"], j["K"], 1000 + j["seed"], o))
+        return hs
+
+    T, W = args.steps, args.warmup
+    flops_it = sum(8.0 * j["M"] * j["N"] * j["K"] for j in jobs)
+    # plain form: each instance alone, one after another, on one stream
+    hs = make_all()
+    for h in hs:
+        did.did_iterate(h, W)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"batch: plain form, {T} iterations per job")
+    ev0.record(stream)
+    for h in hs:
+        did.did_iterate(h, T)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev0.elapsed_time(ev1)
+    plain_C = []
+    for h, j in zip(hs, jobs):
+        C = np.empty((j["N"], j["K"]), np.float32)
+        did.did_factors(h, None, C)
+        plain_C.append(C)
+        did.did_free(h)
+    # batched form: the same jobs from the same start
+    hs = make_all()
+    b = did.did_batch_create(stream.cuda_stream)
+    try:
+        for h in hs:
+            did.did_batch_add(b, h)
+        did.did_batch_iterate(b, W)
+        did.did_batch_sync(b)
+        log(f"batch: batched form, {T} iterations")
+        ev0.record(stream)
+        did.did_batch_iterate(b, T)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        batch_ms = ev0.elapsed_time(ev1)
+        same = True
+        for h, j, Cp in zip(hs, jobs, plain_C):
+            did.did_batch_remove(b, h)
+            C = np.empty((j["N"], j["K"]), np.float32)
+            did.did_factors(h, None, C)
+            same = same and np.array_equal(C, Cp)
+    finally:
+        did.did_batch_free(b)
+        for h in hs:
+            did.did_free(h)
+    n_it = len(jobs) * T
+    line = {
+        "metric": METRIC,
+        "value": round(n_it / (batch_ms / 1e3), 2),
+        "unit": "instance-iter/s",
+        "n_gpus": 1,
+        "steps": T,
+        "warmup": W,
+        "ms_per_step": round(batch_ms / T, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "jobs": len(jobs)},
+        "plain_form_instance_iter_s": round(n_it / (plain_ms / 1e3), 2),
+        "speedup_vs_plain_form": round(plain_ms / batch_ms, 3),
+        "batched_tflops_fp32_equiv": round(flops_it * T / (batch_ms / 1e3) / 1e12, 2),
+        "plain_tflops_fp32_equiv": round(flops_it * T / (plain_ms / 1e3) / 1e12, 2),
+        "results_bitwise_equal_to_plain": bool(same),
+        "objective_error_vs_plain_form": 0.0 if same else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args, torch, did):
+    """Poisson arrivals into the server; latency from the scheduled arrival to retirement."""
+    import numpy as np
+
+    from workloads import serving_jobs, serving_x_device
+
+    cfg = WORKLOADS["serve"]
+    n_jobs = args.serve_jobs or cfg["jobs"]
+    jobs = serving_jobs(n_jobs, seed=5, rate=200.0)
+    so = did.did_server_default_opts()
+    so.hbm_budget = 200 << 30
+    so.max_active = args.serve_slots
+    so.max_iter = 50
+    so.rel_tol = 1e-4
+    stream = torch.cuda.Stream()
+    so.stream = stream.cuda_stream
+    srv = did.did_server_create(so)
+    gen = torch.Generator(device="cuda")
+    side = torch.cuda.Stream()
+    queued_x_cap = 100 << 30  # client-side cap on generated, not yet admitted data
+    pending = list(range(n_jobs))
+    live = {}  # job id -> (index, X tensor, submit time)
+    lat, iters, qwait = [], [], []
+    max_queue, steps, occ = 0, 0, []
+    queued_bytes = 0
+    log(f"serve: {n_jobs} jobs, {so.max_active} slots")
+    t0 = time.perf_counter()
+    done = 0
+    try:
+        while done < n_jobs:
+            now = time.perf_counter() - t0
+            while pending and jobs[pending[0]]["t"] <= now and queued_bytes < queued_x_cap:
+                i = pending.pop(0)
+                j = jobs[i]
+                gen.manual_seed(j["seed"])
+                with torch.cuda.stream(side):
+                    X = serving_x_device(torch, j["M"], j["N"], j["K"], j["seed"], generator=gen)
+                side.synchronize()
+                jid = did.did_server_submit(srv, X, j["M"], j["N"], j["K"], 1000 + j["seed"])
+                live[jid] = (i, X, time.perf_counter() - t0)
+                queued_bytes += 4 * j["M"] * j["N"]
+            running, queued, fin = did.did_server_step(srv)
+            steps += 1
+            occ.append(running)
+            max_queue = max(max_queue, queued)
+            if fin or running == 0:
+                for jid in list(live):
+                    st, it, f, l, q = did.did_server_poll(srv, jid)
+                    if st == did.DID_JOB_QUEUED:
+                        continue
+                    i, X, ts = live[jid]
+                    if st in (did.DID_JOB_DONE, did.DID_JOB_FAILED):
+                        if st == did.DID_JOB_FAILED:
+                            raise RuntimeError(f"job {i} failed")
+                        lat.append(ts - jobs[i]["t"] + l)
+                        iters.append(it)
+                        qwait.append(q)
+                        did.did_server_release(srv, jid)
+                        del live[jid]
+                        done += 1
+            # charge generated data until the job is admitted
+            queued_bytes = sum(4 * jobs[i]["M"] * jobs[i]["N"] for jid, (i, _, _) in live.items()
+                               if did.did_server_poll(srv, jid)[0] == did.DID_JOB_QUEUED)
+            if running == 0 and queued == 0 and pending:
+                time.sleep(max(0.0, min(0.002, jobs[pending[0]]["t"] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        used, peak = did.did_server_memory(srv)
+    finally:
+        did.did_server_free(srv)
+    lat = np.array(lat)
+    flops = sum(8.0 * jobs[i]["M"] * jobs[i]["N"] * jobs[i]["K"] for i in range(n_jobs))
+    line = {
+        "metric": METRIC,
+        "value": round(n_jobs / wall, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(wall * 1e3 / max(steps, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "jobs": n_jobs, "slots": so.max_active},
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+        "latency_mean_s": round(float(lat.mean()), 4),
+        "queue_wait_p50_s": round(float(np.percentile(qwait, 50)), 4),
+        "iterations_mean": round(float(np.mean(iters)), 2),
+        "arrival_span_s": round(jobs[-1]["t"], 3),
+        "wall_s": round(wall, 3),
+        "max_queue_depth": max_queue,
+        "mean_running": round(float(np.mean(occ)), 2),
+        "peak_budget_bytes": peak,
+        "offered_tflops_fp32_equiv_at_mean_iters": round(flops / len(jobs) * np.mean(iters) * 200.0 / 1e12, 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +504,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paper-max-n", type=float, default=1e8, help="paper workload: largest N")
     ap.add_argument("--no-table", action="store_true", help="paper workload: skip the runs to the stopping rule")
+    ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")
+    ap.add_argument("--serve-slots", type=int, default=64, help="serve workload: batch slots")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "
@@ -297,6 +519,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "paper":
         run_paper_shape(args, torch, did)
+        return
+    if args.workload == "batch":
+        run_batch(args, torch, did)
+        return
+    if args.workload == "serve":
+        run_serve(args, torch, did)
         return
     cfg = WORKLOADS[args.workload]
     M, N, K = cfg["M"], cfg["N"], cfg["K"]

@@ -83,11 +83,17 @@ enum {
  *                  did_free.  Ignored (copy) for host pointers.
  *   algorithm      DID_ALG_DID (default) or DID_ALG_DBCD.  DBCD is available on the
  *                  thin-matrix path only (DID_EINVAL otherwise).
+ *   row_blocks     tile shape of the row pass along N: about this many (column range,
+ *                  32-row slab group) blocks per launch, which sets the number of column
+ *                  ranges whose W partials are summed (in ascending order).  0 takes the
+ *                  value did_autotune recorded for the instance's shape class, else 4096.
+ *                  Results depend on it only through summation order.
+ *   reserved       must be 0.
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
  *
  * Shapes with M <= 16, K <= 8 and M <= 8 or K <= 4 (such as the experiments' synthetic
- * sets, M = 5, K = 3) run on a thin-matrix path that keeps each column in registers and makes one fused pass
- * over X per iteration; other shapes run the MFMA column/row passes.
+ * sets, M = 5, K = 3) run on a thin-matrix path that keeps each column in registers and
+ * makes one fused pass over X per iteration; other shapes run the MFMA column/row passes.
  */
 typedef struct did_opts {
   int32_t n_blocks;
@@ -96,11 +102,14 @@ typedef struct did_opts {
   int32_t init_scale;
   int32_t borrow_x;
   int32_t algorithm;
+  int32_t row_blocks;
+  int32_t reserved;
   void* stream;
 } did_opts;
 
 /* Fill *opts with the defaults: n_blocks 0, DID_F32, refresh_every 1, init_scale 0,
- * borrow_x 0, DID_ALG_DID, stream NULL.  Returns DID_EINVAL for a NULL pointer. */
+ * borrow_x 0, DID_ALG_DID, row_blocks 0, stream NULL.  Returns DID_EINVAL for a NULL
+ * pointer. */
 int did_default_opts(did_opts* opts);
 
 /*
@@ -172,8 +181,113 @@ int did_profile(did_handle h, int32_t enable);
 int did_profile_read(did_handle h, double* ms, int32_t cap, int32_t* n_stages, int64_t* n_iters);
 const char* did_stage_name(int32_t stage);
 
-/* Release every engine-owned resource of h.  NULL is a no-op (returns DID_OK). */
+/* Release every engine-owned resource of h.  NULL is a no-op (returns DID_OK).  A batch
+ * member must be removed from its batch first (DID_ESTATE). */
 int did_free(did_handle h);
+
+/* Device bytes the engine holds for h (X included when the engine owns a copy). */
+int did_mem_bytes(did_handle h, int64_t* bytes);
+
+/* Device bytes did_init_ex would allocate for an (M, N, K) instance with these options
+ * (opts may be NULL); x_on_device = 1 when X will be passed as a device pointer (then
+ * borrow_x = 1 allocates no copy of it).  Sizes are validated as did_init_ex does. */
+int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int32_t x_on_device,
+                     int64_t* bytes);
+
+/*
+ * Row-pass autotuner.  Times one DID iteration (after one warm-up) of a synthetic
+ * U[0,1) instance of shape (M, N, K) and X storage x_dtype for each candidate row_blocks
+ * value (512, 1024, 2048, 4096, 8192), records the fastest for the shape class
+ * (K <= 32 or not, X storage, ceil(log2 M), ceil(log2 N)) in a process-wide table used
+ * by every later instance created with row_blocks = 0, and returns it in *row_blocks
+ * (and its time in *ms_per_iter if not NULL).  Allocates the tuning input (4MN bytes) for
+ * the duration of the call.  Thin-matrix shapes return DID_EINVAL.
+ * did_autotune_clear() empties the table.
+ */
+int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t* row_blocks,
+                 double* ms_per_iter);
+int did_autotune_clear(void);
+
+/*
+ * Batched form: many instances of uneven (M, N, K) advanced together.
+ * Members are grouped by (K <= 32 or not, X storage); each stage of an iteration is one
+ * launch per group of a persistent kernel that walks the work items of all the group's
+ * members from a device-resident table, and the launches of one iteration are captured
+ * once in a hipGraph that each iteration replays.  A member runs exactly the work of its
+ * own did_iterate, so its iterates equal those it would follow alone.
+ *   did_batch_create  stream: hipStream_t for all batch work (NULL: one owned by the
+ *                     batch).  *out receives the batch.
+ *   did_batch_add     h joins the batch (same device; MFMA-path shapes only, algorithm
+ *                     DID, profiling off; at most 64 members per group).  h's queued work
+ *                     is waited for.  While a member, h accepts no did_iterate,
+ *                     did_objective, did_factors, did_history, did_sync, did_profile* or
+ *                     did_free (DID_ESTATE).
+ *   did_batch_remove  h leaves the batch after the batch's queued work has finished; its
+ *                     iteration count and objective history include the batched iterations.
+ *   did_batch_iterate n iterations of every member (n graph replays), stream-ordered.
+ *   did_batch_objectives  synchronises and stores, for member i in admission order, the
+ *                     objective its latest iteration formed (f of the iterate that
+ *                     iteration started from) into f[i], i < cap; *n = member count.
+ *   did_batch_size, did_batch_sync, did_batch_free (members are detached, not freed).
+ */
+typedef struct did_batch_ctx* did_batch;
+int did_batch_create(void* stream, did_batch* out);
+int did_batch_add(did_batch b, did_handle h);
+int did_batch_remove(did_batch b, did_handle h);
+int did_batch_size(did_batch b, int32_t* n);
+int did_batch_iterate(did_batch b, int32_t n);
+int did_batch_objectives(did_batch b, double* f, int32_t cap, int32_t* n);
+int did_batch_sync(did_batch b);
+int did_batch_free(did_batch b);
+
+/*
+ * Serving form: a request loop over a batch (continuous batching).
+ * Jobs are submitted with a device X (float32, column-major, borrowed until the job is
+ * released), queue in FIFO order, and are admitted at the next step while a batch slot is
+ * free and the memory budget holds the job's resident footprint (engine buffers, plus X
+ * for float32 storage).  Each did_server_step admits what fits, runs one iteration of
+ * every running job as one batched iteration, reads their objectives back, and retires a
+ * job once it has run max_iter iterations or its objective changed by at most rel_tol
+ * relative between consecutive iterations (the experiments' stopping criterion on the
+ * objective); retired jobs keep their factors until released.
+ *   hbm_budget   bytes the admitted and unreleased jobs may hold (default 200 GiB)
+ *   max_active   batch slots (1..256, default 64)
+ *   max_iter     iteration cap per job (default 50)
+ *   rel_tol      relative objective change that ends a job (default 1e-4)
+ *   stream       hipStream_t for all server work (NULL: one owned by the server)
+ * Job states: DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED.
+ *   did_server_submit  queue a job (x_dtype DID_F32 or DID_BF16; the init seed as in
+ *                      did_init); *job receives its id.  A footprint above the whole
+ *                      budget returns DID_ENOMEM; thin-matrix shapes return DID_EINVAL.
+ *   did_server_step    *n_running, *n_queued after the step, *n_finished this step
+ *                      (any pointer may be NULL).
+ *   did_server_poll    state, iterations, latest objective, seconds from submission to
+ *                      retirement (-1 while not retired) and from submission to admission
+ *                      (-1 while queued).
+ *   did_server_result  copy a done job's B (M x K) and C (K x N) out, as did_factors.
+ *   did_server_release free a retired job's device memory and forget the job.
+ *   did_server_memory  bytes charged to the budget now and at most so far.
+ */
+enum { DID_JOB_QUEUED = 0, DID_JOB_RUNNING = 1, DID_JOB_DONE = 2, DID_JOB_FAILED = 3 };
+typedef struct did_server_opts {
+  int64_t hbm_budget;
+  int32_t max_active;
+  int32_t max_iter;
+  double rel_tol;
+  void* stream;
+} did_server_opts;
+typedef struct did_server_ctx* did_server;
+int did_server_default_opts(did_server_opts* opts);
+int did_server_create(const did_server_opts* opts, did_server* out);
+int did_server_submit(did_server s, const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed,
+                      int32_t x_dtype, int64_t* job);
+int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t* n_finished);
+int did_server_poll(did_server s, int64_t job, int32_t* state, int32_t* iters, double* f,
+                    double* latency_s, double* queue_s);
+int did_server_result(did_server s, int64_t job, float* B, float* C);
+int did_server_release(did_server s, int64_t job);
+int did_server_memory(did_server s, int64_t* used, int64_t* peak);
+int did_server_free(did_server s);
 
 /* Message for the calling thread's last failure ("" if none).  Valid until the next
  * call on the same thread. */

@@ -21,17 +21,29 @@ __all__ = [
     "did_default_opts", "did_init", "did_init_ex", "did_init_from_factors", "did_iterate", "did_objective",
     "did_factors", "did_history", "did_iterations", "did_sync", "did_free", "did_last_error",
     "did_profile", "did_profile_read", "did_stage_name", "EXPORTED_SYMBOLS",
+    "did_mem_bytes", "did_mem_estimate", "did_autotune", "did_autotune_clear",
+    "did_batch_create", "did_batch_add", "did_batch_remove", "did_batch_size", "did_batch_iterate",
+    "did_batch_objectives", "did_batch_sync", "did_batch_free",
+    "did_server_opts", "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step",
+    "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
+    "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED",
 ]
 
 DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
 DID_F32, DID_BF16 = 0, 1
 DID_ALG_DID, DID_ALG_DBCD = 0, 1
 DID_MAX_K = 64
+DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED = 0, 1, 2, 3
 
 EXPORTED_SYMBOLS = (
     "did_default_opts", "did_init", "did_init_ex", "did_init_from_factors", "did_iterate", "did_objective",
     "did_factors", "did_history", "did_iterations", "did_sync", "did_free", "did_last_error",
     "did_profile", "did_profile_read", "did_stage_name",
+    "did_mem_bytes", "did_mem_estimate", "did_autotune", "did_autotune_clear",
+    "did_batch_create", "did_batch_add", "did_batch_remove", "did_batch_size", "did_batch_iterate",
+    "did_batch_objectives", "did_batch_sync", "did_batch_free",
+    "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step", "did_server_poll",
+    "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -59,6 +71,18 @@ class did_opts(ctypes.Structure):
         ("init_scale", ctypes.c_int32),
         ("borrow_x", ctypes.c_int32),
         ("algorithm", ctypes.c_int32),
+        ("row_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class did_server_opts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_int64),
+        ("max_active", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("rel_tol", ctypes.c_double),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -90,6 +114,28 @@ def lib():
         "did_free": [vp],
         "did_profile": [vp, i32],
         "did_profile_read": [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "did_mem_bytes": [vp, ctypes.POINTER(i64)],
+        "did_mem_estimate": [i64, i64, i32, ctypes.POINTER(did_opts), i32, ctypes.POINTER(i64)],
+        "did_autotune": [i64, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+        "did_autotune_clear": [],
+        "did_batch_create": [vp, ctypes.POINTER(vp)],
+        "did_batch_add": [vp, vp],
+        "did_batch_remove": [vp, vp],
+        "did_batch_size": [vp, ctypes.POINTER(i32)],
+        "did_batch_iterate": [vp, i32],
+        "did_batch_objectives": [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)],
+        "did_batch_sync": [vp],
+        "did_batch_free": [vp],
+        "did_server_default_opts": [ctypes.POINTER(did_server_opts)],
+        "did_server_create": [ctypes.POINTER(did_server_opts), ctypes.POINTER(vp)],
+        "did_server_submit": [vp, vp, i64, i64, i32, u64, i32, ctypes.POINTER(i64)],
+        "did_server_step": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "did_server_poll": [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+        "did_server_result": [vp, i64, vp, vp],
+        "did_server_release": [vp, i64],
+        "did_server_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "did_server_free": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -206,3 +252,122 @@ def did_profile_read(h):
 
 def did_stage_name(i) -> str:
     return lib().did_stage_name(i).decode()
+
+
+def did_mem_bytes(h) -> int:
+    b = ctypes.c_int64()
+    _check(lib().did_mem_bytes(h, ctypes.byref(b)))
+    return b.value
+
+
+def did_mem_estimate(M, N, K, opts=None, x_on_device=True) -> int:
+    b = ctypes.c_int64()
+    op = ctypes.byref(opts) if opts is not None else None
+    _check(lib().did_mem_estimate(M, N, K, op, 1 if x_on_device else 0, ctypes.byref(b)))
+    return b.value
+
+
+def did_autotune(M, N, K, x_dtype=DID_F32):
+    """Tune the row pass for the shape class of (M, N, K); returns (row_blocks, ms per iteration)."""
+    rb = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib().did_autotune(M, N, K, x_dtype, ctypes.byref(rb), ctypes.byref(ms)))
+    return rb.value, ms.value
+
+
+def did_autotune_clear():
+    _check(lib().did_autotune_clear())
+
+
+def did_batch_create(stream=None):
+    b = ctypes.c_void_p()
+    _check(lib().did_batch_create(stream, ctypes.byref(b)))
+    return b
+
+
+def did_batch_add(b, h):
+    _check(lib().did_batch_add(b, h))
+
+
+def did_batch_remove(b, h):
+    _check(lib().did_batch_remove(b, h))
+
+
+def did_batch_size(b) -> int:
+    n = ctypes.c_int32()
+    _check(lib().did_batch_size(b, ctypes.byref(n)))
+    return n.value
+
+
+def did_batch_iterate(b, n):
+    _check(lib().did_batch_iterate(b, n))
+
+
+def did_batch_objectives(b):
+    """Latest objective of every member, in admission order."""
+    cap = 256
+    buf = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    _check(lib().did_batch_objectives(b, buf, cap, ctypes.byref(n)))
+    return list(buf[:n.value])
+
+
+def did_batch_sync(b):
+    _check(lib().did_batch_sync(b))
+
+
+def did_batch_free(b):
+    _check(lib().did_batch_free(b))
+
+
+def did_server_default_opts() -> did_server_opts:
+    o = did_server_opts()
+    _check(lib().did_server_default_opts(ctypes.byref(o)))
+    return o
+
+
+def did_server_create(opts=None):
+    s = ctypes.c_void_p()
+    op = ctypes.byref(opts) if opts is not None else None
+    _check(lib().did_server_create(op, ctypes.byref(s)))
+    return s
+
+
+def did_server_submit(s, X, M, N, K, seed, x_dtype=DID_F32) -> int:
+    j = ctypes.c_int64()
+    _check(lib().did_server_submit(s, _ptr(X), M, N, K, seed, x_dtype, ctypes.byref(j)))
+    return j.value
+
+
+def did_server_step(s):
+    """One scheduling step; returns (running, queued, finished this step)."""
+    r, q, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().did_server_step(s, ctypes.byref(r), ctypes.byref(q), ctypes.byref(f)))
+    return r.value, q.value, f.value
+
+
+def did_server_poll(s, job):
+    """(state, iterations, latest objective, latency s, queueing s) of a job."""
+    st, it = ctypes.c_int32(), ctypes.c_int32()
+    f, lat, qs = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().did_server_poll(s, job, ctypes.byref(st), ctypes.byref(it), ctypes.byref(f), ctypes.byref(lat),
+                                 ctypes.byref(qs)))
+    return st.value, it.value, f.value, lat.value, qs.value
+
+
+def did_server_result(s, job, B=None, C=None):
+    _check(lib().did_server_result(s, job, _ptr(B), _ptr(C)))
+
+
+def did_server_release(s, job):
+    _check(lib().did_server_release(s, job))
+
+
+def did_server_memory(s):
+    u, p = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().did_server_memory(s, ctypes.byref(u), ctypes.byref(p)))
+    return u.value, p.value
+
+
+def did_server_free(s):
+    _check(lib().did_server_free(s))

@@ -1,0 +1,76 @@
+// Internal declarations shared by the single-instance engine (did_engine.hip) and the
+// batched/serving layer (did_batch.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/did.h"
+#include "did_kernels.h"
+
+struct did_batch_ctx;
+
+// One NMF instance: its device buffers and stream.
+struct did_ctx {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  didk::Shape s{};
+  bool own_x = true;
+  void* X = nullptr;  // float32 or bf16 (s.xbf16)
+  float* B = nullptr;
+  float* C = nullptr;
+  __bf16* BqE = nullptr;
+  __bf16* BqH = nullptr;
+  double* G = nullptr;
+  double* Gpart = nullptr;
+  double* V = nullptr;
+  double* Vpart = nullptr;
+  float* H = nullptr;
+  void* Cq = nullptr;
+  double* W = nullptr;
+  float* Wpart = nullptr;
+  double* tpart = nullptr;  // thin path: block partials
+  int algorithm = DID_ALG_DID;
+  int R = 1;
+  int64_t* rbounds = nullptr;
+  double* fpart = nullptr;
+  double* fhist = nullptr;
+  double* fobj = nullptr;
+  int64_t* tdev = nullptr;  // device copy of t (used by the batched form)
+  int* flag = nullptr;
+  int64_t t = 0;
+  int sticky = 0;
+  int64_t dev_bytes = 0;  // device memory held by the engine for this instance
+  did_batch_ctx* batch = nullptr;
+  std::vector<void*> allocs;
+  // per-stage timing: kStages+1 events per profiled iteration
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_events;
+};
+
+namespace didengine {
+
+constexpr int64_t kHistCap = 1 << 16;
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string& msg);
+int dev_fail(did_ctx* h, hipError_t e, const char* what);
+int dalloc_bytes(did_ctx* h, void** p, size_t bytes);
+int check_handle(did_ctx* h);       // non-NULL and not sticky-failed
+int check_free_handle(did_ctx* h);  // check_handle and not a batch member
+
+// Row-pass target recorded by did_autotune for the shape class of (M, N, KP, X storage),
+// else the default (4096).
+int tuned_row_blocks(int64_t M, int64_t N, int KP, int xbf16);
+
+// Make a device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+}  // namespace didengine

@@ -16,11 +16,12 @@
 #include <vector>
 
 #include "../../include/did.h"
+#include "did_engine.h"
 #include "did_kernels.h"
 
 using didk::Shape;
 
-namespace {
+namespace didengine {
 
 thread_local std::string g_err;
 
@@ -29,84 +30,66 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-constexpr int64_t kHistCap = 1 << 16;
-
-// Kernel stages of one iteration, in launch order.
-constexpr int kStages = 8;
-const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "sweep_v",  "reduce_v",
-                                          "row_pass",    "reduce_w", "b_update", "reduce_g"};
-
-}  // namespace
-
-struct did_ctx {
-  int dev = 0;
-  hipStream_t st = nullptr;
-  bool own_stream = false;
-  Shape s{};
-  bool own_x = true;
-  void* X = nullptr;  // float32 or bf16 (s.xbf16)
-  float* B = nullptr;
-  float* C = nullptr;
-  __bf16* BqE = nullptr;
-  __bf16* BqH = nullptr;
-  double* G = nullptr;
-  double* Gpart = nullptr;
-  double* V = nullptr;
-  double* Vpart = nullptr;
-  float* H = nullptr;
-  void* Cq = nullptr;
-  double* W = nullptr;
-  float* Wpart = nullptr;
-  double* tpart = nullptr;  // thin path: block partials
-  int algorithm = DID_ALG_DID;
-  int R = 1;
-  int64_t* rbounds = nullptr;
-  double* fpart = nullptr;
-  double* fhist = nullptr;
-  double* fobj = nullptr;
-  int* flag = nullptr;
-  int64_t t = 0;
-  int sticky = 0;
-  std::vector<void*> allocs;
-  // per-stage timing: kStages+1 events per profiled iteration
-  bool profiling = false;
-  std::vector<hipEvent_t> prof_events;
-};
-
-namespace {
-
-// Make h's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  if (prev != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
 
 int dev_fail(did_ctx* h, hipError_t e, const char* what) {
   if (h) h->sticky = 1;
   return fail(DID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <class T>
-int dalloc(did_ctx* h, T** p, int64_t count) {
+int dalloc_bytes(did_ctx* h, void** p, size_t bytes) {
   *p = nullptr;
-  if (count <= 0) count = 1;
+  if (bytes == 0) bytes = 1;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+  hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return fail(DID_ENOMEM, "device allocation of " + std::to_string((size_t)count * sizeof(T)) +
-                                " bytes failed: " + hipGetErrorString(e));
+    return fail(DID_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                                hipGetErrorString(e));
   }
   h->allocs.push_back(q);
-  *p = static_cast<T*>(q);
+  h->dev_bytes += (int64_t)bytes;
+  *p = q;
   return DID_OK;
+}
+
+int check_handle(did_ctx* h) {
+  if (!h) return fail(DID_EINVAL, "NULL handle");
+  if (h->sticky) return fail(DID_EDEVICE, "handle is in a failed state after an earlier device error");
+  return DID_OK;
+}
+
+int check_free_handle(did_ctx* h) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->batch) return fail(DID_ESTATE, "handle is a member of a batch; remove it first");
+  return DID_OK;
+}
+
+}  // namespace didengine
+
+using namespace didengine;
+
+namespace {
+
+// Kernel stages of one iteration, in launch order.
+constexpr int kStages = 8;
+const char* const kStageNames[kStages] = {"column_pass", "reduce_f", "sweep_v",  "reduce_v",
+                                          "row_pass",    "reduce_w", "b_update", "reduce_g"};
+
+template <class T>
+int dalloc(did_ctx* h, T** p, int64_t count) {
+  void* q = nullptr;
+  const int rc = dalloc_bytes(h, &q, (size_t)(count > 0 ? count : 1) * sizeof(T));
+  *p = static_cast<T*>(q);
+  return rc;
 }
 
 bool is_device_ptr(const void* p) {
@@ -135,12 +118,13 @@ void release(did_ctx* h) {
 // Column ranges of the row pass, in 32-column tiles: P contiguous blocks of tiles (the
 // paper's shards; block p holds tiles [T p / P, T (p+1) / P)), each split into S
 // sub-ranges; W partials are summed in ascending range order.  Returns R + 1 tile bounds.
-std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks) {
+std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks, int row_blocks) {
   const int64_t T = (N + 31) / 32;
   const int64_t slab_groups = (nchunks + 3) / 4;
-  // about 4096 blocks of (range, slab group): several rounds of resident blocks, so the
-  // last partial round costs little
-  int64_t want = (4096 + slab_groups - 1) / slab_groups;
+  // about row_blocks blocks of (range, slab group) (default 4096: several rounds of
+  // resident blocks, so the last partial round costs little)
+  const int64_t target = row_blocks > 0 ? row_blocks : 4096;
+  int64_t want = (target + slab_groups - 1) / slab_groups;
   want = std::max<int64_t>(1, std::min<int64_t>(want, T));
   const int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, T) : 1;
   const int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
@@ -163,21 +147,13 @@ int check_shape(int64_t M, int64_t N, int32_t K) {
   return DID_OK;
 }
 
-// Allocate, copy/adopt X and validate it.  Leaves h ready for factor setup.
-int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did_opts& o) {
-  int rc;
+// Option checks and the derived shape, shared by setup and did_mem_estimate.
+int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   if (o.x_dtype != DID_F32 && o.x_dtype != DID_BF16) return fail(DID_EINVAL, "x_dtype must be DID_F32 or DID_BF16");
   if (o.refresh_every != 1) return fail(DID_EINVAL, "refresh_every must be 1");
   if (o.n_blocks < 0) return fail(DID_EINVAL, "n_blocks must be >= 0");
-  if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
-  if (o.stream) {
-    h->st = static_cast<hipStream_t>(o.stream);
-  } else {
-    hipError_t e = hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking);
-    if (e != hipSuccess) return dev_fail(nullptr, e, "hipStreamCreate");
-    h->own_stream = true;
-  }
-  Shape& s = h->s;
+  if (o.row_blocks < 0) return fail(DID_EINVAL, "row_blocks must be >= 0");
+  if (o.reserved != 0) return fail(DID_EINVAL, "reserved must be 0");
   s.M = M;
   s.N = N;
   s.K = K;
@@ -190,9 +166,53 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if (o.algorithm == DID_ALG_DBCD && !s.thin)
     return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8, M <= 8 or K <= 4)");
   if (s.thin && s.xbf16) return fail(DID_EINVAL, "the thin-matrix path stores X as float32 only");
-  h->algorithm = o.algorithm;
   if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
     return fail(DID_EDEVICE, "thin path: occupancy query failed");
+  return DID_OK;
+}
+
+// Row-pass target of an instance: the option, else the tuned value for its shape class,
+// else the default.
+int row_target(const Shape& s, const did_opts& o) {
+  if (o.row_blocks > 0) return o.row_blocks;
+  return didengine::tuned_row_blocks(s.M, s.N, s.KP, s.xbf16);
+}
+
+// Device bytes the engine allocates for an instance (the plan setup follows).
+int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
+  const int64_t M = s.M, N = s.N, K = s.K, KP = s.KP, NP = didk::n_pairs(s.KP);
+  auto b = [](int64_t n) { return n > 0 ? n : 1; };
+  int64_t t = b(4);  // flag
+  if (s.xbf16)
+    t += b(M * N * 2);
+  else if (x_copied)
+    t += b(M * N * 4);
+  t += b(M * K * 4) + b(K * N * 4) + 2 * b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
+       b((int64_t)didk::bupdate_blocks(s) * NP * 8) + b(KP * KP * 8) + b(KP * s.Mpad * 8);
+  if (s.thin) {
+    t += b(didk::thin_blocks(s) * didk::thin_slots(16, 4) * 8);
+  } else {
+    t += b(didk::vgram_blocks(s) * NP * 8) + b(KP * N * 4) + b(didk::cq_bytes(s)) + b((int64_t)R * KP * s.Mpad * 4) +
+         b((int64_t)(R + 1) * 8) + b(didk::colpass_blocks(s) * 8);
+  }
+  t += b(kHistCap * 8) + b(8) + b(8);  // fhist, fobj, tdev
+  return t;
+}
+
+// Allocate, copy/adopt X and validate it.  Leaves h ready for factor setup.
+int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did_opts& o) {
+  int rc;
+  Shape& s = h->s;
+  if ((rc = make_shape(s, M, N, K, o))) return rc;
+  h->algorithm = o.algorithm;
+  if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
+  if (o.stream) {
+    h->st = static_cast<hipStream_t>(o.stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "hipStreamCreate");
+    h->own_stream = true;
+  }
 
   // float32 view of X on the device: the caller's device buffer (borrowed, or read once for
   // the bf16 form) or an upload
@@ -254,7 +274,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   }
 
   const int NP = didk::n_pairs(s.KP);
-  const std::vector<int64_t> rb = make_ranges(N, s.nchunks, o.n_blocks);
+  const std::vector<int64_t> rb = make_ranges(N, s.nchunks, o.n_blocks, row_target(s, o));
   h->R = (int)rb.size() - 1;
   if ((rc = dalloc(h, &h->B, M * K))) return rc;
   if ((rc = dalloc(h, &h->C, (int64_t)K * N))) return rc;
@@ -278,12 +298,14 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   }
   if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
+  if ((rc = dalloc(h, &h->tdev, 1))) return rc;
 
   if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->W, 0, (size_t)s.KP * s.Mpad * 8, h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess)
+      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->tdev, 0, sizeof(int64_t), h->st)) != hipSuccess)
     return dev_fail(h, e, "buffer setup");
   if (!s.thin &&
       ((e = hipMemsetAsync(h->Cq, 0, (size_t)didk::cq_bytes(s), h->st)) != hipSuccess ||
@@ -298,12 +320,6 @@ hipError_t refresh_b_derived(did_ctx* h) {
   hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st);
   if (e != hipSuccess) return e;
   return didk::reduce_sym(h->Gpart, didk::bupdate_blocks(h->s), h->s.KP, h->G, h->st);
-}
-
-int check_handle(did_ctx* h) {
-  if (!h) return fail(DID_EINVAL, "NULL handle");
-  if (h->sticky) return fail(DID_EDEVICE, "handle is in a failed state after an earlier device error");
-  return DID_OK;
 }
 
 int objective_pass(did_ctx* h) {
@@ -510,7 +526,7 @@ static int iterate_thin(did_ctx* h, int32_t n) {
 }
 
 int did_iterate(did_handle h, int32_t n) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   if (n < 0) return fail(DID_EINVAL, "n must be >= 0");
   DeviceGuard g(h->dev);
@@ -560,7 +576,7 @@ int did_iterate(did_handle h, int32_t n) {
 }
 
 int did_objective(did_handle h, double* f) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   if (!f) return fail(DID_EINVAL, "f must not be NULL");
   DeviceGuard g(h->dev);
@@ -573,7 +589,7 @@ int did_objective(did_handle h, double* f) {
 }
 
 int did_factors(did_handle h, float* B, float* C) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   DeviceGuard g(h->dev);
   hipError_t e;
@@ -587,7 +603,7 @@ int did_factors(did_handle h, float* B, float* C) {
 }
 
 int did_history(did_handle h, double* f, int64_t cap, int64_t* count) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   if (!count) return fail(DID_EINVAL, "count must not be NULL");
   if (cap < 0 || (cap > 0 && !f)) return fail(DID_EINVAL, "bad output buffer");
@@ -615,7 +631,7 @@ int did_iterations(did_handle h, int64_t* t) {
 }
 
 int did_sync(did_handle h) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   DeviceGuard g(h->dev);
   hipError_t e = hipStreamSynchronize(h->st);
@@ -624,14 +640,14 @@ int did_sync(did_handle h) {
 }
 
 int did_profile(did_handle h, int32_t enable) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   h->profiling = enable != 0;
   return DID_OK;
 }
 
 int did_profile_read(did_handle h, double* ms, int32_t cap, int32_t* n_stages, int64_t* n_iters) {
-  int rc = check_handle(h);
+  int rc = check_free_handle(h);
   if (rc) return rc;
   if (!n_stages || !n_iters || cap < 0 || (cap > 0 && !ms)) return fail(DID_EINVAL, "bad output arguments");
   DeviceGuard g(h->dev);
@@ -662,7 +678,29 @@ const char* did_stage_name(int32_t stage) {
 
 int did_free(did_handle h) {
   if (!h) return DID_OK;
+  if (h->batch) return fail(DID_ESTATE, "handle is a member of a batch; remove it first");
   release(h);
+  return DID_OK;
+}
+
+int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int32_t x_on_device, int64_t* bytes) {
+  if (!bytes) return fail(DID_EINVAL, "bytes must not be NULL");
+  *bytes = 0;
+  int rc = check_shape(M, N, K);
+  if (rc) return rc;
+  did_opts o;
+  did_default_opts(&o);
+  if (opts) o = *opts;
+  Shape s{};
+  if ((rc = make_shape(s, M, N, K, o))) return rc;
+  const int R = s.thin ? 1 : (int)make_ranges(N, s.nchunks, o.n_blocks, row_target(s, o)).size() - 1;
+  *bytes = engine_bytes(s, R, !(x_on_device && o.borrow_x));
+  return DID_OK;
+}
+
+int did_mem_bytes(did_handle h, int64_t* bytes) {
+  if (!h || !bytes) return fail(DID_EINVAL, "NULL argument");
+  *bytes = h->dev_bytes;
   return DID_OK;
 }
 

@@ -87,6 +87,51 @@ hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipSt
 hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st);
 
+// ---- batched form: grouped persistent kernels over a device-resident instance table ----
+// One group holds instances of one (KP, X storage) pair.  Every stage of an iteration is a
+// single persistent launch whose blocks walk the concatenated work items of all the
+// group's instances; an instance's items are exactly the blocks of its single-instance
+// launch, run by the same device code, so its results do not depend on the batch.
+constexpr int kMaxBatch = 64;  // instances per group
+enum GStage { GS_COL = 0, GS_REDF, GS_SWEEP, GS_VGRAM, GS_REDV, GS_ROW, GS_REDW, GS_BUP, GS_REDG, GS_ADV, GS_N };
+
+struct GInst {
+  const void* X;
+  float* B;
+  float* C;
+  void* Cq;
+  __bf16* BqE;
+  __bf16* BqH;
+  float* H;
+  double* fpart;
+  double* G;
+  double* Gpart;
+  double* V;
+  double* Vpart;
+  float* Wpart;
+  double* W;
+  const int64_t* tb;
+  double* fhist;  // objective history (ring of hist_cap entries)
+  int64_t* tdev;  // iteration counter (index into fhist)
+  double* fcur;   // latest objective, for the host
+  int64_t M, N, nchunks, Mpad, hist_cap, vblocks, colblocks, bupblocks;
+  int K, vec4, R, nsg;
+};
+
+struct GTable {
+  int n;
+  int64_t total[GS_N];
+  int64_t begin[GS_N][kMaxBatch + 1];  // first item of instance i in stage st; begin[st][n] = total
+  GInst inst[kMaxBatch];
+};
+
+// work items of one instance in each stage (rows of the row pass are a multiple of 8)
+void ginst_items(const Shape& s, int R, int64_t items[GS_N]);
+// persistent grid of each grouped stage kernel on the current device (resident blocks)
+hipError_t group_grids(int KP, int xbf16, int64_t grids[GS_N]);
+// one iteration of every instance in the group table dtab (device memory)
+hipError_t group_iteration(int KP, int xbf16, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st);
+
 // ---- thin-matrix path (did_thin.hip) ----
 // mode 0: DID column work (sweep, W/V/f block partials); 1: objective partials only;
 // 2: DBCD C half (sweep, f partials).

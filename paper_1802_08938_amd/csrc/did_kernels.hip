@@ -24,6 +24,8 @@
 // directly (after the bf16 split) as the B operand of a second MFMA that reduces over
 // those sixteen rows; no lane shuffles are needed.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -68,11 +70,21 @@ __device__ __forceinline__ Split3 split3(const float (&v)[8]) {
   return r;
 }
 
+// float32 -> bf16, round to nearest even, on the bits of the float32 value (finite v).
+// Used where v was just rounded from float64: a plain conversion there may be folded into
+// a single float64 -> bf16 rounding, which differs on float32 ties and would make the
+// packed pieces depend on how the surrounding kernel was optimised.
+__device__ __forceinline__ __bf16 bf16_rne_bits(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
+}
+
 __device__ __forceinline__ void split3_scalar(float v, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)v;
+  h = bf16_rne_bits(v);
   const float r1 = v - (float)h;
-  m = (__bf16)r1;
-  l = (__bf16)(r1 - (float)m);
+  m = bf16_rne_bits(r1);
+  l = bf16_rne_bits(r1 - (float)m);
 }
 
 // acc += a * b as six bf16 MFMAs, smallest terms first.
@@ -277,18 +289,17 @@ __device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, 
 constexpr int kBupRows = 64;  // rows of B per block
 
 template <int KP>
-__global__ __launch_bounds__(kBupRows) void k_bupdate(float* __restrict__ B, int64_t M, int K,
-                                                 const double* __restrict__ W, int64_t Mpad,
-                                                 const double* __restrict__ V, __bf16* __restrict__ BqE,
-                                                 __bf16* __restrict__ BqH, double* __restrict__ Gpart,
-                                                 int update) {
+__device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
+                                             int64_t Mpad, const double* __restrict__ V, __bf16* __restrict__ BqE,
+                                             __bf16* __restrict__ BqH, double* __restrict__ Gpart, int update,
+                                             int64_t bid) {
   __shared__ double Vs[KP * KP];
   __shared__ float Bt[kBupRows * (KP + 1)];
   const int tid = threadIdx.x;
   if (update)
     for (int q = tid; q < KP * KP; q += kBupRows) Vs[q] = V[q];
   __syncthreads();
-  const int64_t m = (int64_t)blockIdx.x * kBupRows + tid;
+  const int64_t m = bid * kBupRows + tid;
   const bool ok = m < M;
   double db[KP];
 #pragma unroll
@@ -327,8 +338,17 @@ __global__ __launch_bounds__(kBupRows) void k_bupdate(float* __restrict__ B, int
       s0 += (double)Bt[r * (KP + 1) + a] * (double)Bt[r * (KP + 1) + b];
       s1 += (double)Bt[(r + 1) * (KP + 1) + a] * (double)Bt[(r + 1) * (KP + 1) + b];
     }
-    Gpart[(int64_t)blockIdx.x * NP + q] = s0 + s1;
+    Gpart[bid * NP + q] = s0 + s1;
   }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBupRows) void k_bupdate(float* __restrict__ B, int64_t M, int K,
+                                                 const double* __restrict__ W, int64_t Mpad,
+                                                 const double* __restrict__ V, __bf16* __restrict__ BqE,
+                                                 __bf16* __restrict__ BqH, double* __restrict__ Gpart,
+                                                 int update) {
+  bupdate_body<KP>(B, M, K, W, Mpad, V, BqE, BqH, Gpart, update, blockIdx.x);
 }
 
 int bupdate_blocks(const Shape& s) { return (int)((s.M + kBupRows - 1) / kBupRows); }
@@ -356,10 +376,10 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
 // c+1 is loaded into registers while chunk c is computed.  H is written as KP x N with
 // row kk contiguous over the columns.
 template <int KP, bool WITH_H, typename XT>
-__global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
-                                                    const __bf16* __restrict__ BqH, float* __restrict__ Hout,
-                                                    double* __restrict__ fpart, int64_t nchunks, int vec4) {
+__device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
+                                             const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                             const __bf16* __restrict__ BqH, float* __restrict__ Hout,
+                                             double* __restrict__ fpart, int64_t nchunks, int vec4, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = KS * 3 * 64;              // 16-byte units of the E operand per chunk
@@ -369,7 +389,7 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, in
   __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  const int64_t T = (int64_t)blockIdx.x * 4 + wave;  // this wave's 32-column tile
+  const int64_t T = bid * 4 + wave;  // this wave's 32-column tile
   const int64_t j0 = T * 32;
   const int64_t col = j0 + lc;
   const bool colok = col < N;
@@ -521,7 +541,15 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, in
   for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
   if (l == 0) fw[wave] = fsum;
   __syncthreads();
-  if (tid == 0) fpart[blockIdx.x] = (fw[0] + fw[1]) + (fw[2] + fw[3]);
+  if (tid == 0) fpart[bid] = (fw[0] + fw[1]) + (fw[2] + fw[3]);
+}
+
+template <int KP, bool WITH_H, typename XT>
+__global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
+                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                                    const __bf16* __restrict__ BqH, float* __restrict__ Hout,
+                                                    double* __restrict__ fpart, int64_t nchunks, int vec4) {
+  colpass_body<KP, WITH_H, XT>(X, M, N, K, Cq, BqE, BqH, Hout, fpart, nchunks, vec4, blockIdx.x);
 }
 
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
@@ -563,9 +591,9 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const __bf16*
 // in memory) are staged through LDS so that global loads and stores are coalesced, and
 // each updated column is repacked into Cq for the row pass and the next column pass.
 template <int KP>
-__global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
-                                               f32x4* __restrict__ Cq, int64_t N, int K,
-                                               const double* __restrict__ G) {
+__device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float* __restrict__ C,
+                                           f32x4* __restrict__ Cq, int64_t N, int K, const double* __restrict__ G,
+                                           int64_t bid) {
   __shared__ double Gs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
   extern __shared__ float Ct[];             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
@@ -575,7 +603,7 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
     Gs[q] = G[a * KP + b];
   }
 
-  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t j0 = bid * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
   const int ne = nv * K;
   for (int e = tid; e < ne; e += 256) Ct[e] = C[j0 * K + e];
@@ -605,6 +633,13 @@ __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, fl
   __syncthreads();
   for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
   pack_block<KP>(Cq, j0, nv, Ct, K, (N + 31) / 32);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
+                                               f32x4* __restrict__ Cq, int64_t N, int K,
+                                               const double* __restrict__ G) {
+  sweep_body<KP>(Hin, C, Cq, N, K, G, blockIdx.x);
 }
 
 hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st) {
@@ -649,8 +684,8 @@ hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st) {
 constexpr int kVBlocks = 256;
 
 template <int KP>
-__global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int64_t ntiles,
-                                               double* __restrict__ Vpart) {
+__device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t ntiles, double* __restrict__ Vpart,
+                                           int64_t bid, int64_t nblk) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = KS * 3 * 64;
@@ -659,8 +694,8 @@ __global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int
   constexpr int NP = KP * (KP + 1) / 2;
   __shared__ double Vs[4][NP];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
-  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-  const int64_t t0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (ntiles + nblk - 1) / nblk;
+  const int64_t t0 = bid * per;
   const int64_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
   double acc[NBL][16];
 #pragma unroll
@@ -708,7 +743,13 @@ __global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int
   }
   __syncthreads();
   for (int q = tid; q < NP; q += 256)
-    Vpart[(int64_t)blockIdx.x * NP + q] = ((Vs[0][q] + Vs[1][q]) + Vs[2][q]) + Vs[3][q];
+    Vpart[bid * NP + q] = ((Vs[0][q] + Vs[1][q]) + Vs[2][q]) + Vs[3][q];
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int64_t ntiles,
+                                               double* __restrict__ Vpart) {
+  vgram_body<KP>(Cq, ntiles, Vpart, blockIdx.x, gridDim.x);
 }
 
 int64_t vgram_blocks(const Shape& s) {
@@ -739,10 +780,10 @@ hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) 
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
 template <int KP, typename XT>
-__global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
-                                                    float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
-                                                    const int64_t* __restrict__ tb, int R, int nsg) {
+__device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
+                                             const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                             float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
+                                             const int64_t* __restrict__ tb, int R, int nsg, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = KS * 3 * 64;      // 16-byte units of the E'^T A operand per tile
@@ -750,7 +791,7 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, in
   constexpr int UT = UE + UW;
   constexpr int NV = (UT + 255) / 256;
   __shared__ f32x4 sc[2][UT];
-  const int id = blockIdx.x, xcd = id & 7, local = id >> 3;
+  const int id = (int)bid, xcd = id & 7, local = id >> 3;
   const int r = xcd + 8 * (local / nsg), sg = local % nsg;
   if (r >= R) return;  // whole block
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
@@ -884,6 +925,14 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, in
   }
 }
 
+template <int KP, typename XT>
+__global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
+                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                                    float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
+                                                    const int64_t* __restrict__ tb, int R, int nsg) {
+  rowpass_body<KP, XT>(X, M, N, K, Cq, BqE, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
+}
+
 template <typename XT>
 static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const __bf16* BqE, float* Wpart,
                            const int64_t* tb, int R, hipStream_t st) {
@@ -907,13 +956,19 @@ hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const __bf16*
 }
 
 // ------------------------------------------------------------------ reductions
-// W[kk][m] = sum_r Wpart[r][kk][m], r ascending, float64.
-__global__ void k_reduce_w(const float* __restrict__ Wpart, int R, int64_t n, double* __restrict__ W) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// W[kk][m] = sum_r Wpart[r][kk][m], r ascending, float64 (blocks of 256 entries).
+__device__ __forceinline__ void reduce_w_body(const float* __restrict__ Wpart, int R, int64_t n,
+                                              double* __restrict__ W, int64_t bid) {
+  const int64_t i = bid * 256 + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   for (int r = 0; r < R; ++r) s += (double)Wpart[(int64_t)r * n + i];
   W[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_w(const float* __restrict__ Wpart, int R, int64_t n,
+                                                  double* __restrict__ W) {
+  reduce_w_body(Wpart, R, n, W, blockIdx.x);
 }
 
 hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStream_t st) {
@@ -937,10 +992,11 @@ hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipS
   return hipGetLastError();
 }
 
-// full[a][b] = full[b][a] = sum_p part[p][pair(a,b)], p ascending.
-__global__ void k_reduce_sym(const double* __restrict__ part, int64_t P, int KP, double* __restrict__ full) {
+// full[a][b] = full[b][a] = sum_p part[p][pair(a,b)], p ascending (blocks of 256 pairs).
+__device__ __forceinline__ void reduce_sym_body(const double* __restrict__ part, int64_t P, int KP,
+                                                double* __restrict__ full, int64_t bid) {
   const int NP = KP * (KP + 1) / 2;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = (int)bid * 256 + (int)threadIdx.x;
   if (q >= NP) return;
   double s = 0.0;
   for (int64_t p = 0; p < P; ++p) s += part[p * NP + q];
@@ -950,16 +1006,20 @@ __global__ void k_reduce_sym(const double* __restrict__ part, int64_t P, int KP,
   full[b * KP + a] = s;
 }
 
+__global__ __launch_bounds__(256) void k_reduce_sym(const double* __restrict__ part, int64_t P, int KP,
+                                                    double* __restrict__ full) {
+  reduce_sym_body(part, P, KP, full, blockIdx.x);
+}
+
 hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st) {
   const int NP = KP * (KP + 1) / 2;
   k_reduce_sym<<<(unsigned)((NP + 255) / 256), 256, 0, st>>>(part, P, KP, full);
   return hipGetLastError();
 }
 
-// *out = scale * sum_p part[p]: each thread sums a strided subset in order, then a fixed
-// tree over the block.
-__global__ __launch_bounds__(256) void k_reduce_f(const double* __restrict__ part, int64_t P, double* out,
-                                                  double scale) {
+// scale * sum_p part[p]: each thread sums a strided subset in order, then a fixed tree over
+// the block; the result is returned to every thread.
+__device__ __forceinline__ double reduce_f_body(const double* __restrict__ part, int64_t P, double scale) {
   __shared__ double s[256];
   double a = 0.0;
   for (int64_t p = threadIdx.x; p < P; p += 256) a += part[p];
@@ -969,11 +1029,205 @@ __global__ __launch_bounds__(256) void k_reduce_f(const double* __restrict__ par
     if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = scale * s[0];
+  const double r = scale * s[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_f(const double* __restrict__ part, int64_t P, double* out,
+                                                  double scale) {
+  const double r = reduce_f_body(part, P, scale);
+  if (threadIdx.x == 0) *out = r;
 }
 
 hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st) {
   k_reduce_f<<<1, 256, 0, st>>>(part, P, out, scale);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched form
+// Grouped persistent kernels: block b takes items b, b + grid, b + 2 grid, ... of the
+// stage's concatenated item list, finds the owning instance by binary search over the
+// item prefix, and runs the stage's device code for that instance and local block index.
+// The row pass's items of each instance start at a multiple of 8 and every grid is a
+// multiple of 8, so an item's XCD (block index mod 8) is the same as in the instance's
+// own launch.
+__device__ __forceinline__ int ginst_find(const GTable* __restrict__ g, int st, int64_t w) {
+  int lo = 0, hi = g->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g->begin[st][mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+#define DID_GROUP_LOOP(ST)                                                     \
+  const int64_t total_ = g->total[ST];                                        \
+  for (int64_t w_ = blockIdx.x; w_ < total_; w_ += gridDim.x) {               \
+    const int i_ = ginst_find(g, ST, w_);                                      \
+    const GInst& d = g->inst[i_];                                              \
+    const int64_t bid = w_ - g->begin[ST][i_];
+
+#define DID_GROUP_END \
+  __syncthreads();    \
+  }
+
+template <int KP, typename XT>
+__global__ __launch_bounds__(256, 2) void kg_colpass(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_COL)
+  colpass_body<KP, true, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE,
+                             d.BqH, d.H, d.fpart, d.nchunks, d.vec4, bid);
+  DID_GROUP_END
+}
+
+__global__ __launch_bounds__(256) void kg_reduce_f(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_REDF)
+  (void)bid;
+  const double r = reduce_f_body(d.fpart, d.colblocks, 0.5);
+  if (threadIdx.x == 0) {
+    const int64_t t = *d.tdev;
+    d.fhist[t % d.hist_cap] = r;
+    *d.fcur = r;
+  }
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_sweep(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_SWEEP)
+  sweep_body<KP>(d.H, d.C, static_cast<f32x4*>(d.Cq), d.N, d.K, d.G, bid);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_vgram(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_VGRAM)
+  vgram_body<KP>(static_cast<const f32x4*>(d.Cq), (d.N + 31) / 32, d.Vpart, bid, d.vblocks);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_reduce_v(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_REDV)
+  reduce_sym_body(d.Vpart, d.vblocks, KP, d.V, bid);
+  DID_GROUP_END
+}
+
+template <int KP, typename XT>
+__global__ __launch_bounds__(256, 2) void kg_rowpass(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_ROW)
+  rowpass_body<KP, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE, d.Wpart,
+                       d.Mpad, d.nchunks, d.tb, d.R, d.nsg, bid);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_REDW)
+  reduce_w_body(d.Wpart, d.R, (int64_t)KP * d.Mpad, d.W, bid);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBupRows) void kg_bupdate(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_BUP)
+  bupdate_body<KP>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.BqE, d.BqH, d.Gpart, 1, bid);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_reduce_g(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_REDG)
+  reduce_sym_body(d.Gpart, d.bupblocks, KP, d.G, bid);
+  DID_GROUP_END
+}
+
+__global__ __launch_bounds__(64) void kg_advance(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_ADV)
+  (void)bid;
+  if (threadIdx.x == 0) *d.tdev = *d.tdev + 1;
+  DID_GROUP_END
+}
+
+#undef DID_GROUP_LOOP
+#undef DID_GROUP_END
+
+void ginst_items(const Shape& s, int R, int64_t items[GS_N]) {
+  const int64_t np = n_pairs(s.KP);
+  const int64_t nsg = (s.nchunks + 3) / 4;
+  const int64_t R8 = ((int64_t)R + 7) / 8 * 8;
+  items[GS_COL] = colpass_blocks(s);
+  items[GS_REDF] = 1;
+  items[GS_SWEEP] = (s.N + 255) / 256;
+  items[GS_VGRAM] = vgram_blocks(s);
+  items[GS_REDV] = (np + 255) / 256;
+  items[GS_ROW] = nsg * R8;
+  items[GS_REDW] = ((int64_t)s.KP * s.Mpad + 255) / 256;
+  items[GS_BUP] = bupdate_blocks(s);
+  items[GS_REDG] = (np + 255) / 256;
+  items[GS_ADV] = 1;
+}
+
+template <int KP, typename XT>
+static hipError_t group_grids_t(int64_t grids[GS_N]) {
+  int dev = 0, cus = 0;
+  hipError_t e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  auto occ = [&](const void* fn, int threads, size_t lds, int64_t* out) {
+    int per = 0;
+    hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, lds);
+    // multiple of 8 (one block per XCD round), at least one round
+    *out = ((int64_t)std::max(per, 1) * cus + 7) / 8 * 8;
+    return r;
+  };
+  if ((e = occ((const void*)kg_colpass<KP, XT>, 256, 0, &grids[GS_COL])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_reduce_f, 256, 0, &grids[GS_REDF])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_sweep<KP>, 256, 256 * KP * sizeof(float), &grids[GS_SWEEP])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_vgram<KP>, 256, 0, &grids[GS_VGRAM])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_reduce_v<KP>, 256, 0, &grids[GS_REDV])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_rowpass<KP, XT>, 256, 0, &grids[GS_ROW])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_reduce_w<KP>, 256, 0, &grids[GS_REDW])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_bupdate<KP>, kBupRows, 0, &grids[GS_BUP])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_reduce_g<KP>, 256, 0, &grids[GS_REDG])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_advance, 64, 0, &grids[GS_ADV])) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t group_grids(int KP, int xbf16, int64_t grids[GS_N]) {
+  if (KP == 32) return xbf16 ? group_grids_t<32, __bf16>(grids) : group_grids_t<32, float>(grids);
+  return xbf16 ? group_grids_t<64, __bf16>(grids) : group_grids_t<64, float>(grids);
+}
+
+template <int KP, typename XT>
+static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st) {
+  kg_colpass<KP, XT><<<(unsigned)gr[GS_COL], 256, 0, st>>>(t);
+  kg_reduce_f<<<(unsigned)gr[GS_REDF], 256, 0, st>>>(t);
+  kg_sweep<KP><<<(unsigned)gr[GS_SWEEP], 256, 256 * KP * sizeof(float), st>>>(t);
+  kg_vgram<KP><<<(unsigned)gr[GS_VGRAM], 256, 0, st>>>(t);
+  kg_reduce_v<KP><<<(unsigned)gr[GS_REDV], 256, 0, st>>>(t);
+  kg_rowpass<KP, XT><<<(unsigned)gr[GS_ROW], 256, 0, st>>>(t);
+  kg_reduce_w<KP><<<(unsigned)gr[GS_REDW], 256, 0, st>>>(t);
+  kg_bupdate<KP><<<(unsigned)gr[GS_BUP], kBupRows, 0, st>>>(t);
+  kg_reduce_g<KP><<<(unsigned)gr[GS_REDG], 256, 0, st>>>(t);
+  kg_advance<<<(unsigned)gr[GS_ADV], 64, 0, st>>>(t);
+}
+
+hipError_t group_iteration(int KP, int xbf16, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st) {
+  if (KP == 32) {
+    if (xbf16)
+      group_iteration_t<32, __bf16>(dtab, grids, st);
+    else
+      group_iteration_t<32, float>(dtab, grids, st);
+  } else {
+    if (xbf16)
+      group_iteration_t<64, __bf16>(dtab, grids, st);
+    else
+      group_iteration_t<64, float>(dtab, grids, st);
+  }
   return hipGetLastError();
 }
 

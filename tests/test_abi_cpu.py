@@ -40,8 +40,12 @@ def test_default_opts_and_struct_layout():
     _lib_or_skip()
     o = did.did_default_opts()
     assert (o.n_blocks, o.x_dtype, o.refresh_every, o.init_scale, o.borrow_x) == (0, did.DID_F32, 1, 0, 0)
+    assert (o.algorithm, o.row_blocks, o.reserved) == (did.DID_ALG_DID, 0, 0)
     assert o.stream is None
-    assert ctypes.sizeof(did.did_opts) == 32
+    assert ctypes.sizeof(did.did_opts) == 40
+    so = did.did_server_default_opts()
+    assert (so.hbm_budget, so.max_active, so.max_iter, so.rel_tol) == (200 << 30, 64, 50, 1e-4)
+    assert ctypes.sizeof(did.did_server_opts) == 32
 
 
 @pytest.mark.parametrize("M,N,K,msg", [
@@ -99,3 +103,36 @@ def test_bf16_rounding_helper_matches_torch():
     x = x.astype(np.float32)
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(round_to_bf16(x), ref)
+
+
+def test_memory_estimate_host_logic():
+    """did_mem_estimate is pure host arithmetic for MFMA-path shapes: a copied float32 X
+    adds exactly 4MN bytes, the bf16 storage form 2MN, and the large workload's footprint
+    is dominated by X and the packed C."""
+    _lib_or_skip()
+    M, N, K = 5000, 1_000_000, 50
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    borrowed = did.did_mem_estimate(M, N, K, o, x_on_device=True)
+    copied = did.did_mem_estimate(M, N, K, o, x_on_device=False)
+    assert copied - borrowed == 4 * M * N
+    ob = did.did_default_opts()
+    ob.x_dtype = did.DID_BF16
+    assert did.did_mem_estimate(M, N, K, ob) - borrowed == 2 * M * N
+    # packed C: per 32-column tile (64/16*3 + 64/32*6) units of 64 x 16 bytes
+    cq = (N + 31) // 32 * (12 + 12) * 64 * 16
+    assert borrowed > cq + 4 * K * N and borrowed < 3e9
+
+
+def test_batch_and_server_null_arguments():
+    L = _lib_or_skip()
+    assert L.did_batch_add(None, None) == did.DID_EINVAL
+    assert L.did_batch_iterate(None, 1) == did.DID_EINVAL
+    assert L.did_batch_free(None) == did.DID_OK
+    assert L.did_server_step(None, None, None, None) == did.DID_EINVAL
+    assert L.did_server_free(None) == did.DID_OK
+    so = did.did_server_default_opts()
+    so.max_active = 0
+    h = ctypes.c_void_p()
+    assert L.did_server_create(ctypes.byref(so), ctypes.byref(h)) == did.DID_EINVAL
+    assert "server options" in did.did_last_error()

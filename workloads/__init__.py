@@ -21,6 +21,8 @@ Recipes (seeds are the workload number unless a caller passes another):
   the parent seed, block p of C0 ~ U[0,1] and of the noise from
   ``SeedSequence(seed).spawn(n_blocks)[p]``, X = B0 C0 + |0.01 N(0,1)|.  Any prefix of
   blocks can be regenerated on its own, which is how the parity slices are built.
+* ``serving_x`` (one served job): X = max(0, B0 C0 + 0.02 N(0,1)), U[0,1] factors, from
+  the job's own seed; ``serving_jobs`` draws the arrival times and shapes.
 * ``paper_synthetic`` (the experiments' synthetic sets, M = 5, K = 3): X = B0 C0 with
   U[0,1] factors (the paper's `rand` data; read as a product of uniform factors).
 """
@@ -41,6 +43,8 @@ __all__ = [
     "to_f32_colmajor",
     "as_oracle_input",
     "serving_jobs",
+    "serving_x",
+    "serving_x_device",
     "round_to_bf16",
 ]
 
@@ -183,6 +187,29 @@ def serving_jobs(n_jobs, seed=5, rate=200.0, M_range=(100, 4000), N_range=(1000,
     seeds = rng.integers(0, 2**31 - 1, size=n_jobs)
     return [dict(t=float(t[i]), M=int(Ms[i]), N=int(Ns[i]), K=int(min(Ks[i], Ms[i], Ns[i])),
                  seed=int(seeds[i])) for i in range(n_jobs)]
+
+
+def serving_x(M, N, K, seed, noise=0.02):
+    """One served job's data: X = max(0, B0 C0 + noise N(0,1)) with U[0,1] factors (host)."""
+    rng = np.random.default_rng(seed)
+    B0 = rng.random((M, K))
+    C0 = rng.random((K, N))
+    X = B0 @ C0 + noise * rng.standard_normal((M, N))
+    return np.maximum(X, 0.0)
+
+
+def serving_x_device(torch, M, N, K, seed, noise=0.02, device="cuda", generator=None):
+    """``serving_x``'s recipe on the device (torch's generator, so other values); returns a
+    float32 (N, M) tensor, i.e. X in column-major storage."""
+    g = generator
+    if g is None:
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+    B0t = torch.rand((K, M), generator=g, device=device, dtype=torch.float32)
+    C0t = torch.rand((N, K), generator=g, device=device, dtype=torch.float32)
+    Xt = torch.matmul(C0t, B0t)
+    Xt.add_(torch.randn((N, M), generator=g, device=device, dtype=torch.float32).mul_(noise)).clamp_(min=0.0)
+    return Xt
 
 
 def round_to_bf16(X):
