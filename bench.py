@@ -433,7 +433,8 @@ def run_serve(args, torch, did):
                 with torch.cuda.stream(side):
                     X = serving_x_device(torch, j["M"], j["N"], j["K"], j["seed"], generator=gen)
                 side.synchronize()
-                jid = did.did_server_submit(srv, X, j["M"], j["N"], j["K"], 1000 + j["seed"])
+                jid = did.did_server_submit(srv, X, j["M"], j["N"], j["K"], 1000 + j["seed"],
+                                            did.DID_BF16 if args.serve_bf16 else did.DID_F32)
                 live[jid] = (i, X, time.perf_counter() - t0)
                 queued_bytes += 4 * j["M"] * j["N"]
             running, queued, fin = did.did_server_step(srv)
@@ -479,7 +480,8 @@ def run_serve(args, torch, did):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "jobs": n_jobs, "slots": so.max_active},
+        "config": {"workload": cfg["desc"] + ("; X stored as bf16" if args.serve_bf16 else ""), "jobs": n_jobs,
+                   "slots": so.max_active, "x_storage": "bf16" if args.serve_bf16 else "f32"},
         "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "latency_mean_s": round(float(lat.mean()), 4),
@@ -506,6 +508,7 @@ def main():
     ap.add_argument("--no-table", action="store_true", help="paper workload: skip the runs to the stopping rule")
     ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")
     ap.add_argument("--serve-slots", type=int, default=64, help="serve workload: batch slots")
+    ap.add_argument("--serve-bf16", action="store_true", help="serve workload: store each job's X as bf16")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "

@@ -267,6 +267,9 @@ int did_batch_free(did_batch b);
  *   did_server_result  copy a done job's B (M x K) and C (K x N) out, as did_factors.
  *   did_server_release free a retired job's device memory and forget the job.
  *   did_server_memory  bytes charged to the budget now and at most so far.
+ * A server, like a handle, is driven from one thread.  Admission is strictly first-in
+ * first-out: a head job that does not fit yet (budget, slots, or 64 running jobs of its
+ * K class and X storage) holds back the jobs behind it.
  */
 enum { DID_JOB_QUEUED = 0, DID_JOB_RUNNING = 1, DID_JOB_DONE = 2, DID_JOB_FAILED = 3 };
 typedef struct did_server_opts {

@@ -556,10 +556,17 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
   int rc = check_server(s);
   if (rc) return rc;
   int32_t finished = 0;
-  // admission: FIFO while a slot is free and the budget holds the head of the queue
+  // admission: FIFO while a slot is free, the head's batch group has room and the budget
+  // holds the head of the queue
   while (!s->queue.empty() && (int)s->running.size() < s->o.max_active) {
     Job& j = s->jobs[s->queue.front()];
     if (s->used + j.bytes > s->o.hbm_budget) break;
+    int same_group = 0;
+    for (int64_t id : s->running) {
+      const Job& r = s->jobs[id];
+      same_group += ((r.K > 32) == (j.K > 32)) && (r.x_dtype == j.x_dtype);
+    }
+    if (same_group >= kMaxBatch) break;
     did_opts o;
     did_default_opts(&o);
     o.x_dtype = j.x_dtype;

@@ -125,7 +125,9 @@ std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks, int r
   // resident blocks, so the last partial round costs little)
   const int64_t target = row_blocks > 0 ? row_blocks : 4096;
   int64_t want = (target + slab_groups - 1) / slab_groups;
-  want = std::max<int64_t>(1, std::min<int64_t>(want, T));
+  // at least 16 tiles (512 columns) per range: the W partials (R x KP x M floats) then
+  // stay below a sixteenth of X for K <= 64
+  want = std::max<int64_t>(1, std::min<int64_t>(want, std::max<int64_t>(1, T / 16)));
   const int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, T) : 1;
   const int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
   std::vector<int64_t> b;

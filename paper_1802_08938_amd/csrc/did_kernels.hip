@@ -45,46 +45,52 @@ __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// Exact three-way split of float32 values into bf16 pieces: x = hi + mid + lo with
-// hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid) (round to nearest even; the
-// two differences are exact in float32), so hi + mid + lo carries x to within 2^-24
-// relative.  A float32 product a*b is then formed to float32 accuracy by the six bf16
-// products whose weight is above 2^-24: hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi
-// (each exact in float32 and accumulated in float32 by the MFMA).
+// Exact three-way split of float32 values into bf16 pieces by truncation: hi keeps the
+// leading 8 significant bits of x (x with its low 16 bits cleared), mid the leading 8 of
+// r1 = x - hi, and lo = r1 - mid; both differences are exact in float32 and lo has at
+// most 8 significant bits, so x = hi + mid + lo exactly, and each piece is the upper half
+// of a float32 (a bf16).  A float32 product a*b is then formed to float32 accuracy by the
+// six bf16 products whose weight is above 2^-24: hi*hi, hi*mid, mid*hi, hi*lo, mid*mid,
+// lo*hi (each exact in float32 and accumulated in float32 by the MFMA).
 struct Split3 {
   bf16x8 p[3];
 };
 
+__device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ float u2f(uint32_t x) { return __builtin_bit_cast(float, x); }
+// bf16 pair from the upper halves of two float32 bit patterns (element 0 = a)
+__device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xFFFF0000u); }
+
 __device__ __forceinline__ Split3 split3(const float (&v)[8]) {
-  Split3 r;
+  uint32_t h[8], m[8], lo[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const __bf16 h = (__bf16)v[t];
-    const float r1 = v[t] - (float)h;
-    const __bf16 m = (__bf16)r1;
-    const float r2 = r1 - (float)m;
-    r.p[0][t] = h;
-    r.p[1][t] = m;
-    r.p[2][t] = (__bf16)r2;
+    h[t] = f2u(v[t]);
+    const float r1 = v[t] - u2f(h[t] & 0xFFFF0000u);
+    m[t] = f2u(r1);
+    lo[t] = f2u(r1 - u2f(m[t] & 0xFFFF0000u));
   }
+  uint32_t ph[4], pm[4], pl[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ph[q] = hi_pair(h[2 * q], h[2 * q + 1]);
+    pm[q] = hi_pair(m[2 * q], m[2 * q + 1]);
+    pl[q] = hi_pair(lo[2 * q], lo[2 * q + 1]);
+  }
+  Split3 r;
+  r.p[0] = __builtin_bit_cast(bf16x8, ph);
+  r.p[1] = __builtin_bit_cast(bf16x8, pm);
+  r.p[2] = __builtin_bit_cast(bf16x8, pl);
   return r;
 }
 
-// float32 -> bf16, round to nearest even, on the bits of the float32 value (finite v).
-// Used where v was just rounded from float64: a plain conversion there may be folded into
-// a single float64 -> bf16 rounding, which differs on float32 ties and would make the
-// packed pieces depend on how the surrounding kernel was optimised.
-__device__ __forceinline__ __bf16 bf16_rne_bits(float v) {
-  uint32_t u = __builtin_bit_cast(uint32_t, v);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
-}
-
 __device__ __forceinline__ void split3_scalar(float v, __bf16& h, __bf16& m, __bf16& l) {
-  h = bf16_rne_bits(v);
-  const float r1 = v - (float)h;
-  m = bf16_rne_bits(r1);
-  l = bf16_rne_bits(r1 - (float)m);
+  const uint32_t u = f2u(v);
+  const float r1 = v - u2f(u & 0xFFFF0000u);
+  const float r2 = r1 - u2f(f2u(r1) & 0xFFFF0000u);
+  h = __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
+  m = __builtin_bit_cast(__bf16, (uint16_t)(f2u(r1) >> 16));
+  l = __builtin_bit_cast(__bf16, (uint16_t)(f2u(r2) >> 16));
 }
 
 // acc += a * b as six bf16 MFMAs, smallest terms first.
