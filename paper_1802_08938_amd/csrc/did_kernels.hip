@@ -464,12 +464,13 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   // One chunk: compute chunk c from the X tile in xr (loaded one chunk earlier) and the
   // staged B operands in LDS buffer c & 1; meanwhile stage chunk c+1's B operands and load
   // its X tile into xr.
-  auto step = [&](int64_t c, f32x16& xr) {
+  // acc holds the X tile of chunk c and accumulates in place; xn receives chunk c+1's
+  // (the two tiles alternate roles from one chunk to the next, so nothing is copied)
+  auto step = [&](int64_t c, f32x16& acc, f32x16& xn) {
     const int buf = (int)(c & 1);
-    f32x16 acc = xr;
     const int64_t cn = c + 1 < nchunks ? c + 1 : c;
     gload(cn);
-    xr = xload(cn);
+    xn = xload(cn);
       // E = X - B C: KS steps of six MFMAs, operands of step s+1 read from LDS during step s
       const f32x4* ue = &sb[buf][0] + l;
       bf16x8 a[3], an[3];
@@ -533,7 +534,11 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   gload(0);
   sstore(0);
   __syncthreads();
-  for (int64_t c = 0; c < nchunks; ++c) step(c, x0);
+  f32x16 x1;
+  for (int64_t c = 0; c < nchunks; c += 2) {
+    step(c, x0, x1);
+    if (c + 1 < nchunks) step(c + 1, x1, x0);
+  }
 
   if (WITH_H && colok) {  // row kk of H contiguous over columns: coalesced stores
 #pragma unroll
@@ -858,11 +863,11 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
 
   // One tile: compute tile T from the X tile in xr (loaded one tile earlier) and the
   // staged C' operands in LDS buffer buf; meanwhile stage tile T+1 and load its X tile.
-  auto step = [&](int64_t T, int buf, f32x16& xr) {
-    f32x16 acc = xr;
+  // acc holds the X tile of tile T and accumulates in place; xn receives tile T+1's
+  auto step = [&](int64_t T, int buf, f32x16& acc, f32x16& xn) {
     const int64_t Tn = T + 1 < thi ? T + 1 : T;
     cload(Tn);
-    xr = xload(Tn);
+    xn = xload(Tn);
       if (active) {
         const f32x4* ue = &sc[buf][0] + l;
         bf16x8 a[3], an[3];
@@ -916,10 +921,10 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     cload(tlo);
     cstore(0);
     __syncthreads();
-    int buf = 0;
-    for (int64_t T = tlo; T < thi; ++T) {
-      step(T, buf, x0);
-      buf ^= 1;
+    f32x16 x1;
+    for (int64_t T = tlo; T < thi; T += 2) {
+      step(T, 0, x0, x1);
+      if (T + 1 < thi) step(T + 1, 1, x1, x0);
     }
   }
   if (active) {
