@@ -189,7 +189,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
     t += b(M * N * 2);
   else if (x_copied)
     t += b(M * N * 4);
-  t += b(M * K * 4) + b(K * N * 4) + 2 * b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
+  t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
        b((int64_t)didk::bupdate_blocks(s) * NP * 8) + b(KP * KP * 8) + b(KP * s.Mpad * 8);
   if (s.thin) {
     t += b(didk::thin_blocks(s) * didk::thin_slots(16, 4) * 8);
@@ -281,7 +281,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->B, M * K))) return rc;
   if ((rc = dalloc(h, &h->C, (int64_t)K * N))) return rc;
   if ((rc = dalloc(h, &h->BqE, didk::packed_b_elems(s)))) return rc;
-  if ((rc = dalloc(h, &h->BqH, didk::packed_b_elems(s)))) return rc;
+  h->BqH = h->BqE + (int64_t)didk::bq_units_e(s.KP) * 8;  // H-order units of chunk 0
   if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
@@ -303,7 +303,6 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->tdev, 1))) return rc;
 
   if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->BqH, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->W, 0, (size_t)s.KP * s.Mpad * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||

@@ -19,9 +19,13 @@ struct Shape {
   int64_t thin_grid; // thin path: blocks per launch (one wave of resident blocks)
 };
 
-// Number of bf16 entries of one packed-operand buffer (E-operand or H-operand) of B:
-// per 32-row chunk, KP x 32 values in three pieces.
-inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)s.KP * 32 * 3; }
+// Packed B: per 32-row chunk, the bf16 pieces of B in the two MFMA operand orders as
+// 16-byte units, E order (KP/16 * 3 * 64 units) then H order (KP/32 * 2 * 3 * 64 units, the
+// same count), so that one chunk's operands are one contiguous run of 2 * bq_units_e units.
+inline int bq_units_e(int KP) { return (KP / 16) * 3 * 64; }
+inline int bq_units_chunk(int KP) { return 2 * bq_units_e(KP); }
+// bf16 entries of the packed B buffer
+inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)bq_units_chunk(s.KP) * 8; }
 inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
 
 // Packed C: per 32-column tile, the bf16 pieces of C in the two MFMA operand orders, as
@@ -51,7 +55,9 @@ hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t 
 hipError_t to_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
-// Pack B (three bf16 pieces per entry) into MFMA operand order, optionally applying the incremental B update from the
+// Pack B (three bf16 pieces per entry) into MFMA operand order (Bq: the E-order units of
+// each chunk at BqE, its H-order units at BqH = BqE + bq_units_e units, chunk stride
+// bq_units_chunk units), optionally applying the incremental B update from the
 // reduced messages W (KP x Mpad, float64) and V (KP x KP, float64); writes per-block
 // partials of B^T B into Gpart (n_pairs(KP) doubles per block).  Grid: ceil(M/256).
 hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, __bf16* BqE,

@@ -264,15 +264,18 @@ hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t 
 }
 
 // ------------------------------------------------------------------ B update + packing
-// Packed operand buffers of B, each entry split into its three bf16 pieces p = 0, 1, 2
+// Packed operand buffer of B, each entry split into its three bf16 pieces p = 0, 1, 2
 // (rows >= M and columns >= K stay zero from allocation).  A 16-byte unit holds the eight
-// bf16 values lane l feeds to one MFMA:
-//   BqE unit ((c*(KP/16) + s)*3 + p)*64 + l, element t: piece p of -B[32c + l%32][16s + 8(l/32) + t]
+// bf16 values lane l feeds to one MFMA; chunk c's units form one contiguous run of
+// UC = 2 * (KP/16) * 3 * 64 units, its E-order units first (at BqE) and then its H-order
+// units (at BqH = BqE + UC / 2 units):
+//   BqE unit c*UC + (s*3 + p)*64 + l, element t: piece p of -B[32c + l%32][16s + 8(l/32) + t]
 //       (A operand of E = X - B C in the column pass; B operand of E'^T in the row pass)
-//   BqH unit (((c*(KP/32) + b)*2 + q)*3 + p)*64 + l, element t:
+//   BqH unit c*UC + ((b*2 + q)*3 + p)*64 + l, element t:
 //       piece p of B[32c + row32(8q + t, l/32)][32b + l%32]   (A operand of H = B^T E)
 template <int KP>
 __device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, int kk, float v) {
+  constexpr int64_t UC = 2 * (KP / 16) * 3 * 64;  // units per chunk (E then H order)
   constexpr int NB = KP / 32;
   const int64_t c = m >> 5;
   const int r = (int)(m & 31);
@@ -282,13 +285,13 @@ __device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, 
   {
     const int s = kk >> 4, h = (kk >> 3) & 1, t = kk & 7, l = r + 32 * h;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) BqE[(((c * (KP / 16) + s) * 3 + p) * 64 + l) * 8 + t] = nc[p];
+    for (int p = 0; p < 3; ++p) BqE[(c * UC + (s * 3 + p) * 64 + l) * 8 + t] = nc[p];
   }
   {
     const int i = 4 * (r >> 3) + (r & 3), h = (r >> 2) & 1, q = i >> 3, t = i & 7;
     const int b = kk >> 5, l = (kk & 31) + 32 * h;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) BqH[((((c * NB + b) * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
+    for (int p = 0; p < 3; ++p) BqH[(c * UC + ((b * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
   }
 }
 
@@ -423,8 +426,8 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
       const int uu = u < U ? u : U - 1;  // threads past the end reload the last unit
-      const f32x4* src = (uu < UE) ? reinterpret_cast<const f32x4*>(BqE) + c * UE + uu
-                                   : reinterpret_cast<const f32x4*>(BqH) + c * UH + (uu - UE);
+      // the chunk's E-order units followed by its H-order units (BqH = BqE + UE units)
+      const f32x4* src = reinterpret_cast<const f32x4*>(BqE) + c * (UE + UH) + uu;
       stg[v] = *src;
     }
   };
@@ -815,7 +818,7 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
 
   bf16x8 bP[KS][3];  // pieces of -B[m0 + l%32][16s + 8*half + t]
   {
-    const f32x4* pe = reinterpret_cast<const f32x4*>(BqE) + (active ? c : 0) * UE + l;
+    const f32x4* pe = reinterpret_cast<const f32x4*>(BqE) + (active ? c : 0) * (2 * UE) + l;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
