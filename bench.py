@@ -87,7 +87,7 @@ def log(msg):
 
 
 def algorithmic_counts(M, N, K):
-    """Algorithmic work of one iteration and of the dominant kernel (see DESIGN.md).
+    """Algorithmic work of one iteration and of the dominant kernel.
 
     Iteration bytes: X read once (4MN), C read and written (8KN), B read (4MK).
     Column-pass launch: flops 4MNK (E = X - BC and H = B^T E, 2MNK each); bytes 4MN + 8KN.

@@ -19,7 +19,7 @@ in its order and notation:
     4. for i = 1..K: b_i := [b_i + w_i/v_ii - sum_{k<i} (v_ik/v_ii) delta b_k]_+ and
        delta b_i := b_i^{t+1} - b_i^t (Section "Incremental Update for b_i").
 
-Readings taken where the paper is silent (each one is listed in the design doc):
+Readings taken where the paper is silent:
 
 * the residual is carried across iterations and updated explicitly by
   E := E - delta b_i c_i^r (Section "Incremental Update for b_i"); Alg. 3 recomputes

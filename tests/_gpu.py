@@ -16,7 +16,7 @@ def require_gpu():
         pytest.skip("no GPU")
     try:
         did.lib()
-    except did.DidLibraryMissing as e:  # a GPU machine without the library is a failure, not a skip
+    except did.DidLibraryMissing as e:  # a GPU without the library is a failure, not a skip
         raise AssertionError(str(e))
     return torch
 
