@@ -243,13 +243,16 @@ int did_batch_free(did_batch b);
 /*
  * Serving form: a request loop over a batch (continuous batching).
  * Jobs are submitted with a device X (float32, column-major, borrowed until the job is
- * released), queue in FIFO order, and are admitted at the next step while a batch slot is
- * free and the memory budget holds the job's resident footprint (engine buffers, plus X
- * for float32 storage).  Each did_server_step admits what fits, runs one iteration of
- * every running job as one batched iteration, reads their objectives back, and retires a
- * job once it has run max_iter iterations or its objective changed by at most rel_tol
- * relative between consecutive iterations (the experiments' stopping criterion on the
- * objective); retired jobs keep their factors until released.
+ * released), queue in FIFO order, and are admitted while a batch slot is free and the
+ * memory budget holds the job's resident footprint (engine buffers, plus X for float32
+ * storage).  Each did_server_step (1) collects the batched iteration the previous step
+ * launched: it reads every running job's objective and retires a job once it has run
+ * max_iter iterations or its objective changed by at most rel_tol relative between
+ * consecutive iterations (the experiments' stopping criterion on the objective); (2) adds
+ * the jobs admitted by the previous step to the batch; (3) launches the next iteration of
+ * all running jobs and returns without waiting for it; (4) admits queued jobs and
+ * initialises them on a second stream while that iteration runs.  Retired jobs keep their
+ * factors until released.
  *   hbm_budget   bytes the admitted and unreleased jobs may hold (default 200 GiB)
  *   max_active   batch slots (1..256, default 64)
  *   max_iter     iteration cap per job (default 50)
@@ -259,8 +262,8 @@ int did_batch_free(did_batch b);
  *   did_server_submit  queue a job (x_dtype DID_F32 or DID_BF16; the init seed as in
  *                      did_init); *job receives its id.  A footprint above the whole
  *                      budget returns DID_ENOMEM; thin-matrix shapes return DID_EINVAL.
- *   did_server_step    *n_running, *n_queued after the step, *n_finished this step
- *                      (any pointer may be NULL).
+ *   did_server_step    *n_running (jobs running or admitted), *n_queued after the step,
+ *                      *n_finished this step (any pointer may be NULL).
  *   did_server_poll    state, iterations, latest objective, seconds from submission to
  *                      retirement (-1 while not retired) and from submission to admission
  *                      (-1 while queued).

@@ -455,14 +455,17 @@ struct Job {
 
 struct did_server_ctx {
   did_server_opts o{};
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;      // batch iterations
+  hipStream_t adm_st = nullptr;  // initialisation of admitted jobs, beside the iterations
   bool own_stream = false;
   did_batch b = nullptr;
   int64_t next_id = 1;
   std::deque<int64_t> queue;
   std::map<int64_t, Job> jobs;
-  std::vector<int64_t> running;  // batch member order
-  int64_t used = 0;              // bytes charged by admitted, unreleased jobs
+  std::vector<int64_t> running;   // batch member order
+  std::vector<int64_t> admitted;  // initialised, joining the batch at the next step
+  bool inflight = false;          // an iteration of the running jobs has been launched
+  int64_t used = 0;               // bytes charged by admitted, unreleased jobs
   int64_t peak_used = 0;
 };
 
@@ -511,8 +514,14 @@ int did_server_create(const did_server_opts* opts, did_server* out) {
     }
     s->own_stream = true;
   }
+  if ((e = hipStreamCreateWithFlags(&s->adm_st, hipStreamNonBlocking)) != hipSuccess) {
+    if (s->own_stream) (void)hipStreamDestroy(s->st);
+    delete s;
+    return fail(DID_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  }
   int rc = did_batch_create(s->st, &s->b);
   if (rc) {
+    (void)hipStreamDestroy(s->adm_st);
     if (s->own_stream) (void)hipStreamDestroy(s->st);
     delete s;
     return rc;
@@ -552,46 +561,20 @@ int did_server_submit(did_server s, const void* X, int64_t M, int64_t N, int32_t
   return DID_OK;
 }
 
+// One scheduling step, pipelined so that host work overlaps an iteration on the device:
+//   1. collect the iteration launched by the previous step (objectives of every running
+//      job), retire the jobs that met their stopping rule;
+//   2. the jobs initialised by the previous step join the batch;
+//   3. launch the next iteration of all running jobs (asynchronous);
+//   4. admit queued jobs first-in first-out while a slot is free, their batch group has
+//      room and the budget holds them, and initialise them on the admission stream while
+//      the iteration runs; they join at the next step.
 int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t* n_finished) {
   int rc = check_server(s);
   if (rc) return rc;
   int32_t finished = 0;
-  // admission: FIFO while a slot is free, the head's batch group has room and the budget
-  // holds the head of the queue
-  while (!s->queue.empty() && (int)s->running.size() < s->o.max_active) {
-    Job& j = s->jobs[s->queue.front()];
-    if (s->used + j.bytes > s->o.hbm_budget) break;
-    int same_group = 0;
-    for (int64_t id : s->running) {
-      const Job& r = s->jobs[id];
-      same_group += ((r.K > 32) == (j.K > 32)) && (r.x_dtype == j.x_dtype);
-    }
-    if (same_group >= kMaxBatch) break;
-    did_opts o;
-    did_default_opts(&o);
-    o.x_dtype = j.x_dtype;
-    o.borrow_x = 1;
-    o.stream = s->st;
-    s->queue.pop_front();
-    j.t_start = std::chrono::steady_clock::now();
-    if ((rc = did_init_ex(j.X, j.M, j.N, j.K, j.seed, &o, &j.h)) == DID_OK) rc = did_batch_add(s->b, j.h);
-    if (rc) {
-      j.state = DID_JOB_FAILED;
-      j.error = g_err;
-      if (j.h) did_free(j.h);
-      j.h = nullptr;
-      j.t_done = std::chrono::steady_clock::now();
-      ++finished;
-      if (rc == DID_EDEVICE) return rc;
-      continue;
-    }
-    j.state = DID_JOB_RUNNING;
-    s->used += j.bytes;
-    s->peak_used = std::max(s->peak_used, s->used);
-    s->running.push_back(j.id);
-  }
-  if (!s->running.empty()) {
-    if ((rc = did_batch_iterate(s->b, 1))) return rc;
+  if (s->inflight) {
+    s->inflight = false;
     std::vector<double> f(s->running.size());
     int32_t n = 0;
     if ((rc = did_batch_objectives(s->b, f.data(), (int32_t)f.size(), &n))) return rc;
@@ -614,7 +597,58 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
     }
     s->running.swap(keep);
   }
-  if (n_running) *n_running = (int32_t)s->running.size();
+  for (int64_t id : s->admitted) {
+    Job& j = s->jobs[id];
+    if ((rc = did_batch_add(s->b, j.h))) {
+      j.state = DID_JOB_FAILED;
+      j.error = g_err;
+      did_free(j.h);
+      j.h = nullptr;
+      s->used -= j.bytes;
+      j.t_done = std::chrono::steady_clock::now();
+      ++finished;
+      if (rc == DID_EDEVICE) return rc;
+      continue;
+    }
+    s->running.push_back(id);
+  }
+  s->admitted.clear();
+  if (!s->running.empty()) {
+    if ((rc = did_batch_iterate(s->b, 1))) return rc;
+    s->inflight = true;
+  }
+  while (!s->queue.empty() && (int)(s->running.size() + s->admitted.size()) < s->o.max_active) {
+    Job& j = s->jobs[s->queue.front()];
+    if (s->used + j.bytes > s->o.hbm_budget) break;
+    int same_group = 0;
+    for (const auto* list : {&s->running, &s->admitted})
+      for (int64_t id : *list) {
+        const Job& r = s->jobs[id];
+        same_group += ((r.K > 32) == (j.K > 32)) && (r.x_dtype == j.x_dtype);
+      }
+    if (same_group >= kMaxBatch) break;
+    did_opts o;
+    did_default_opts(&o);
+    o.x_dtype = j.x_dtype;
+    o.borrow_x = 1;
+    o.stream = s->adm_st;
+    s->queue.pop_front();
+    j.t_start = std::chrono::steady_clock::now();
+    if ((rc = did_init_ex(j.X, j.M, j.N, j.K, j.seed, &o, &j.h))) {
+      j.state = DID_JOB_FAILED;
+      j.error = g_err;
+      j.h = nullptr;
+      j.t_done = std::chrono::steady_clock::now();
+      ++finished;
+      if (rc == DID_EDEVICE) return rc;
+      continue;
+    }
+    j.state = DID_JOB_RUNNING;
+    s->used += j.bytes;
+    s->peak_used = std::max(s->peak_used, s->used);
+    s->admitted.push_back(j.id);
+  }
+  if (n_running) *n_running = (int32_t)(s->running.size() + s->admitted.size());
   if (n_queued) *n_queued = (int32_t)s->queue.size();
   if (n_finished) *n_finished = finished;
   return DID_OK;
@@ -674,12 +708,12 @@ int did_server_free(did_server s) {
   if (!s) return DID_OK;
   if (s->b) {
     (void)did_batch_sync(s->b);
-    for (auto& kv : s->jobs)
-      if (kv.second.h && kv.second.state == DID_JOB_RUNNING) (void)did_batch_remove(s->b, kv.second.h);
+    for (int64_t id : s->running) (void)did_batch_remove(s->b, s->jobs[id].h);
   }
   for (auto& kv : s->jobs)
     if (kv.second.h) did_free(kv.second.h);
   did_batch_free(s->b);
+  if (s->adm_st) (void)hipStreamDestroy(s->adm_st);
   if (s->own_stream) (void)hipStreamDestroy(s->st);
   delete s;
   return DID_OK;
