@@ -23,10 +23,12 @@ iterations, once one instance after another (the plain form) and once as one bat
 speedup and the bitwise agreement of the results.  ``--workload serve`` runs the serving
 form: Poisson arrivals at 200 jobs/s, admission by a 200 GB budget, continuous batching,
 each job to 50 iterations or a relative objective change below 1e-4; it reports solves/s
-and p50/p99 latency from the scheduled arrival to retirement.
+and p50/p99 latency from the scheduled arrival to retirement.  ``--workload nsweep`` times
+the large workload's recipe at N = 1.25e5 ... 1e6 (the method's cost per iteration is
+linear in N) and reports the time per iteration and per 10^5 columns at each size.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload large|large_bf16|image|planted|paper|batch|serve]
+                       [--workload large|large_bf16|image|planted|nsweep|paper|batch|serve]
 """
 
 from __future__ import annotations
@@ -67,6 +69,9 @@ WORKLOADS = {
                   desc="serving form: Poisson arrivals at 200 jobs/s, M~U{100..4000}, N~LogU[1e3,2e5], "
                        "K~U{5..64}, X=max(0,B0*C0+0.02*N(0,1)) float32, 200 GB budget, <=50 iterations or "
                        "relative objective change <1e-4"),
+    "nsweep": dict(M=5000, N=1_000_000, K=50, n_blocks=64, sizes=(125_000, 250_000, 500_000, 1_000_000),
+                   desc="linear-in-N sweep of the large workload's recipe: M=5000 K=50, 64 column blocks, "
+                        "N=125000..1000000, X=B0*C0+|0.01*N(0,1)|, X resident in HBM"),
     "paper": dict(M=5, N=100_000_000, K=3, n_blocks=16,
                   desc="experiments' synthetic shape: M=5 K=3, N=1e5..1e8, X=B0*C0 with B0,C0~U[0,1], "
                        "stopping rule ||E||^2 <= 1e-6 ||E0||^2, DID and DBCD (thin-matrix path)"),
@@ -288,6 +293,69 @@ def run_paper_shape(args, torch, did):
         "table2": table,
         "table2_note": "GPU seconds = time of exactly t_eps iterations from the same start; paper's seconds are "
                        "its Table 2 on 16 CPU nodes (one core each), other random data of the same recipe",
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_nsweep(args, torch, did):
+    from workloads import large_halfnormal_device
+
+    cfg = WORKLOADS["nsweep"]
+    M, K = cfg["M"], cfg["K"]
+    stream = torch.cuda.Stream()
+    rows = []
+    X = None
+    for N in cfg["sizes"]:
+        del X
+        torch.cuda.empty_cache()
+        log(f"nsweep N={N}: generating")
+        X = large_halfnormal_device(torch, M=M, N=N, K=K, seed=3, n_blocks=cfg["n_blocks"])
+        torch.cuda.synchronize()
+        opts = did.did_default_opts()
+        opts.n_blocks = cfg["n_blocks"]
+        opts.borrow_x = 1
+        opts.stream = stream.cuda_stream
+        h = did.did_init_ex(X, M, N, K, 12345, opts)
+        try:
+            did.did_iterate(h, args.warmup)
+            did.did_profile(h, True)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            log(f"nsweep N={N}: timing {args.steps} steps")
+            ev0.record(stream)
+            did.did_iterate(h, args.steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.steps
+            stages, n_it = did.did_profile_read(h)
+            did.did_profile(h, False)
+        finally:
+            did.did_free(h)
+        n_it = max(n_it, 1)
+        rows.append({"N": N, "ms_per_iter": round(ms, 4), "ms_per_1e5_columns": round(ms * 1e5 / N, 4),
+                     "column_pass_ms": round(stages["column_pass"] / n_it, 4),
+                     "row_pass_ms": round(stages["row_pass"] / n_it, 4),
+                     "other_ms": round(sum(v for k, v in stages.items() if k not in ("column_pass", "row_pass")) / n_it, 4)})
+    del X
+    per = [r["ms_per_1e5_columns"] for r in rows]
+    last = rows[-1]
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / last["ms_per_iter"], 4),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": last["ms_per_iter"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "M": M, "N": last["N"], "K": K, "n_blocks": cfg["n_blocks"]},
+        "sweep": rows,
+        "per_column_cost_spread": round(max(per) / min(per), 4),
     }
     print(json.dumps(line), flush=True)
 
@@ -522,6 +590,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "paper":
         run_paper_shape(args, torch, did)
+        return
+    if args.workload == "nsweep":
+        run_nsweep(args, torch, did)
         return
     if args.workload == "batch":
         run_batch(args, torch, did)
