@@ -175,9 +175,41 @@ def cpu_baseline(name, cfg):
     oracle.did_run(X, B0, C0, reps, P=1, history=False)
     dt = (time.perf_counter() - t0) / reps
     it_s = frac / dt  # iterations/s of the full workload
+    # the same sample on one core (the paper's nodes ran one core each)
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.did_run(X, B0, C0, reps, P=1, history=False)
+        dt1 = (time.perf_counter() - t0) / reps
     return {"value": it_s, "unit": "iter/s", "cores": threads, "kind": "oracle",
             "sample": sample + f"; {dt:.2f} s per sampled iteration; numpy float64, BLAS threads={threads}, "
-                               f"host cpu_count={os.cpu_count()}"}
+                               f"host cpu_count={os.cpu_count()}",
+            "single_core": {"value": frac / dt1, "unit": "iter/s", "cores": 1,
+                            "seconds_per_sampled_iteration": round(dt1, 3)}}
+
+
+def device_env(torch):
+    """The device and software the numbers were taken on."""
+    p = torch.cuda.get_device_properties(0)
+    env = {"device": p.name, "gcn_arch": getattr(p, "gcnArchName", None),
+           "compute_units": p.multi_processor_count, "hbm_bytes": p.total_memory,
+           "hip": torch.version.hip, "torch": torch.__version__}
+    try:
+        from ctypes import byref, c_int, cdll
+
+        hip = cdll.LoadLibrary("libamdhip64.so")
+        clk = c_int(0)
+        # hipDeviceAttributeClockRate (kHz): the peak engine clock
+        attr = 5
+        if hip.hipDeviceGetAttribute(byref(clk), attr, 0) == 0:
+            env["max_engine_clock_mhz"] = clk.value // 1000
+    except OSError:
+        pass
+    return env
+
+
+def emit(torch, line):
+    line["env"] = device_env(torch)
+    print(json.dumps(line), flush=True)
 
 
 def _solve_to_eps(torch, did, X, M, N, K, alg, stream, eps, cap, n_blocks):
@@ -294,7 +326,7 @@ def run_paper_shape(args, torch, did):
         "table2_note": "GPU seconds = time of exactly t_eps iterations from the same start; paper's seconds are "
                        "its Table 2 on 16 CPU nodes (one core each), other random data of the same recipe",
     }
-    print(json.dumps(line), flush=True)
+    emit(torch, line)
 
 
 def run_nsweep(args, torch, did):
@@ -357,7 +389,7 @@ def run_nsweep(args, torch, did):
         "sweep": rows,
         "per_column_cost_spread": round(max(per) / min(per), 4),
     }
-    print(json.dumps(line), flush=True)
+    emit(torch, line)
 
 
 def _job_inputs(torch, jobs, x_dtype):
@@ -460,7 +492,7 @@ def run_batch(args, torch, did):
         "results_bitwise_equal_to_plain": bool(same),
         "objective_error_vs_plain_form": 0.0 if same else None,
     }
-    print(json.dumps(line), flush=True)
+    emit(torch, line)
 
 
 def run_serve(args, torch, did):
@@ -562,7 +594,7 @@ def run_serve(args, torch, did):
         "peak_budget_bytes": peak,
         "offered_tflops_fp32_equiv_at_mean_iters": round(flops / len(jobs) * np.mean(iters) * 200.0 / 1e12, 1),
     }
-    print(json.dumps(line), flush=True)
+    emit(torch, line)
 
 
 def main():
@@ -702,7 +734,7 @@ def main():
         del X
         torch.cuda.empty_cache()
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg)
-    print(json.dumps(line), flush=True)
+    emit(torch, line)
 
 
 if __name__ == "__main__":
