@@ -67,7 +67,10 @@ enum {
  *                  engine choose; results depend on P only through summation order.
  *   x_dtype        DID_F32: X is used as given.  DID_BF16: X (still passed as float32)
  *                  is rounded to bf16 (round to nearest even) on the device and stored in
- *                  that form, halving the bytes streamed per iteration; B, C, the residual
+ *                  that form, as two copies in 32 x 32 tile order (one per pass over X,
+ *                  each zero-padded to multiples of 32 rows and columns: together about
+ *                  the size of the float32 X), halving the bytes each pass streams and
+ *                  letting both passes load whole tiles with full-width loads; B, C, the residual
  *                  and every product stay float32-accurate and the objective is reduced in
  *                  float64, so the engine solves the problem for the rounded data exactly
  *                  as DID_F32 would.  borrow_x does not apply to DID_BF16.

@@ -112,6 +112,7 @@ int check_batch(did_batch_ctx* b) {
 void fill_inst(GInst& d, did_ctx* h, double* fcur) {
   const didk::Shape& s = h->s;
   d.X = h->X;
+  d.XR = h->XR;
   d.B = h->B;
   d.C = h->C;
   d.Cq = h->Cq;

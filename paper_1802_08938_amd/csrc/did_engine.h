@@ -19,7 +19,8 @@ struct did_ctx {
   bool own_stream = false;
   didk::Shape s{};
   bool own_x = true;
-  void* X = nullptr;  // float32 or bf16 (s.xbf16)
+  void* X = nullptr;   // float32 (column-major), or the column-pass tiled bf16 copy (s.xbf16)
+  void* XR = nullptr;  // X as the row pass reads it: X itself, or the row-pass tiled bf16 copy
   float* B = nullptr;
   float* C = nullptr;
   __bf16* BqE = nullptr;

@@ -186,7 +186,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
   auto b = [](int64_t n) { return n > 0 ? n : 1; };
   int64_t t = b(4);  // flag
   if (s.xbf16)
-    t += b(M * N * 2);
+    t += b(2 * didk::tiled_x_elems(s) * 2);
   else if (x_copied)
     t += b(M * N * 4);
   t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
@@ -258,20 +258,23 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       return fail(DID_EINVAL, "X must be finite and nonnegative");
     }
   }
-  if (s.xbf16) {
+  if (s.xbf16) {  // the two tiled copies (one per pass) in one allocation
     __bf16* xb = nullptr;
-    if ((rc = dalloc(h, &xb, M * N))) {
+    const int64_t te = didk::tiled_x_elems(s);
+    if ((rc = dalloc(h, &xb, 2 * te))) {
       if (xtmp) (void)hipFree(xtmp);
       return rc;
     }
-    e = didk::to_bf16(xin, xb, M * N, h->st);
+    e = didk::tile_bf16(s, xin, xb, xb + te, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (xtmp) (void)hipFree(xtmp);
     if (e != hipSuccess) return dev_fail(h, e, "bf16 storage of X");
     h->X = xb;
-    s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xb) & 7) == 0);
+    h->XR = xb + te;
+    s.vec4 = 0;  // the tiled copies are read with their own full-width loads
   } else {
     h->X = const_cast<float*>(xin);
+    h->XR = h->X;
     s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xin) & 15) == 0);
   }
 
@@ -559,7 +562,7 @@ int did_iterate(did_handle h, int32_t n) {
     if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->X, h->Cq, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->XR, h->Cq, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");

@@ -51,8 +51,18 @@ inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
 // ---- launchers (all asynchronous on `st`; they return the launch status) ----
 hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
 hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
-// dst = bf16(src), round to nearest even
-hipError_t to_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
+// bf16 storage form of X: two copies in 32 x 32 tile order, one per pass, zero-padded to
+// Mpad x (32 * ntiles).  A tile holds 1024 bf16 as 2 x 64 units of eight: unit q*64 + l,
+// element t is value i = 8q + t of lane l's MFMA accumulator tile, for l = 32h + r:
+//   column-pass copy XC, tile (T, c) at (T * nchunks + c) * 1024:
+//       X[32c + 8(i/4) + 4h + i%4][32T + r]      (the accumulator layout of X)
+//   row-pass copy XR, tile (c, T) at (c * ntiles + T) * 1024:
+//       X[32c + r][32T + 8(i/4) + 4h + i%4]      (the accumulator layout of X^T)
+// so that a pass loads a lane's 16 values with two 16-byte loads and a wave's tile in two
+// fully used 1 kB runs.  Values are rounded to nearest even.
+inline int64_t n_tiles(const Shape& s) { return (s.N + 31) / 32; }
+inline int64_t tiled_x_elems(const Shape& s) { return s.nchunks * n_tiles(s) * 1024; }
+hipError_t tile_bf16(const Shape& s, const float* src, __bf16* xc, __bf16* xr, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
 // Pack B (three bf16 pieces per entry) into MFMA operand order (Bq: the E-order units of
@@ -102,7 +112,8 @@ constexpr int kMaxBatch = 64;  // instances per group
 enum GStage { GS_COL = 0, GS_REDF, GS_SWEEP, GS_VGRAM, GS_REDV, GS_ROW, GS_REDW, GS_BUP, GS_REDG, GS_ADV, GS_N };
 
 struct GInst {
-  const void* X;
+  const void* X;   // X as the column pass reads it
+  const void* XR;  // X as the row pass reads it
   float* B;
   float* C;
   void* Cq;

@@ -29,6 +29,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "did_kernels.h"
 
 namespace didk {
@@ -220,18 +222,64 @@ hipError_t scale(float* p, int64_t n, float a, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ bf16 storage of X
-// dst[i] = bf16(src[i]), round to nearest even (the reduced-precision storage form of X).
-__global__ void k_to_bf16(const float* __restrict__ src, __bf16* __restrict__ dst, int64_t n) {
+// Both tiled bf16 copies of X (layout in did_kernels.h); one thread per 16-byte unit of
+// each copy, values rounded to nearest even, zero outside M x N.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_tile_bf16(const float* __restrict__ src, int64_t M, int64_t N, int64_t nchunks, int64_t ntiles,
+                            __bf16* __restrict__ xc, __bf16* __restrict__ xr) {
+  const int64_t units = nchunks * ntiles * 128;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (__bf16)src[i];
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += stride) {
+    const int64_t tile = u >> 7;  // the same index in both copies' own tile order
+    const int q = (int)(u >> 6) & 1, l = (int)u & 63, h = l >> 5, r = l & 31;
+    {  // column-pass copy: tile (T, c)
+      const int64_t T = tile / nchunks, c = tile - T * nchunks;
+      const int64_t j = T * 32 + r;
+      __bf16 v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = 8 * q + t;
+        const int64_t m = c * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+        v[t] = (__bf16)((m < M && j < N) ? src[j * M + m] : 0.0f);
+      }
+      *reinterpret_cast<u32x4*>(xc + tile * 1024 + (int64_t)(q * 64 + l) * 8) = __builtin_bit_cast(u32x4, v);
+    }
+    {  // row-pass copy: tile (c, T)
+      const int64_t c = tile / ntiles, T = tile - c * ntiles;
+      const int64_t m = c * 32 + r;
+      __bf16 v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = 8 * q + t;
+        const int64_t j = T * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+        v[t] = (__bf16)((m < M && j < N) ? src[j * M + m] : 0.0f);
+      }
+      *reinterpret_cast<u32x4*>(xr + tile * 1024 + (int64_t)(q * 64 + l) * 8) = __builtin_bit_cast(u32x4, v);
+    }
+  }
 }
 
-hipError_t to_bf16(const float* src, void* dst, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
+hipError_t tile_bf16(const Shape& s, const float* src, __bf16* xc, __bf16* xr, hipStream_t st) {
+  const int64_t units = s.nchunks * n_tiles(s) * 128;
+  int64_t blocks = (units + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(src, static_cast<__bf16*>(dst), n);
+  k_tile_bf16<<<(unsigned)blocks, 256, 0, st>>>(src, s.M, s.N, s.nchunks, n_tiles(s), xc, xr);
   return hipGetLastError();
+}
+
+// The 16 values of one lane's accumulator tile from a tiled bf16 copy of X.
+__device__ __forceinline__ f32x16 ld_tile_bf16(const __bf16* tile, int l) {
+  f32x16 v;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const u32x4 w = *reinterpret_cast<const u32x4*>(tile + (q * 64 + l) * 8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[8 * q + 2 * k] = __builtin_bit_cast(float, w[k] << 16);
+      v[8 * q + 2 * k + 1] = __builtin_bit_cast(float, w[k] & 0xffff0000u);
+    }
+  }
+  return v;
 }
 
 // ------------------------------------------------------------------ validation
@@ -441,6 +489,14 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   const bool tilefull = vec4 && (j0 + 32 <= N);  // wave-uniform
   auto xload = [&](int64_t c) {
     f32x16 v;
+    if constexpr (std::is_same<XT, __bf16>::value) {  // tiled copy XC
+      if (!tileok) {  // a wave past the last tile: E = 0, so it adds nothing to f
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = 0.0f;
+        return v;
+      }
+      return ld_tile_bf16(X + (T * nchunks + c) * 1024, l);
+    }
     const int64_t m0 = c * 32;
     if (tilefull && m0 + 32 <= M) {
 #pragma unroll
@@ -849,6 +905,9 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   const bool rowsfull = active && m0 + 32 <= M;            // wave-uniform
   auto xload = [&](int64_t T) {
     f32x16 v;
+    if constexpr (std::is_same<XT, __bf16>::value) {  // tiled copy XR
+      return ld_tile_bf16(X + ((active ? c : 0) * ((N + 31) / 32) + T) * 1024, l);
+    }
     const int64_t j0 = T * 32;
     const XT* xt = X + j0 * M;  // wave-uniform
     if (rowsfull && j0 + 32 <= hi) {  // wave-uniform
@@ -1133,7 +1192,7 @@ __global__ __launch_bounds__(256) void kg_reduce_v(const GTable* __restrict__ g)
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void kg_rowpass(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_ROW)
-  rowpass_body<KP, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE, d.Wpart,
+  rowpass_body<KP, XT>(static_cast<const XT*>(d.XR), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE, d.Wpart,
                        d.Mpad, d.nchunks, d.tb, d.R, d.nsg, bid);
   DID_GROUP_END
 }

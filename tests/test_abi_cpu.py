@@ -107,7 +107,8 @@ def test_bf16_rounding_helper_matches_torch():
 
 def test_memory_estimate_host_logic():
     """did_mem_estimate is pure host arithmetic for MFMA-path shapes: a copied float32 X
-    adds exactly 4MN bytes, the bf16 storage form 2MN, and the large workload's footprint
+    adds exactly 4MN bytes, the bf16 storage form two tiled copies of 2 bytes per entry of
+    X zero-padded to multiples of 32 rows and columns, and the large workload's footprint
     is dominated by X and the packed C."""
     _lib_or_skip()
     M, N, K = 5000, 1_000_000, 50
@@ -118,7 +119,8 @@ def test_memory_estimate_host_logic():
     assert copied - borrowed == 4 * M * N
     ob = did.did_default_opts()
     ob.x_dtype = did.DID_BF16
-    assert did.did_mem_estimate(M, N, K, ob) - borrowed == 2 * M * N
+    Mp, Np = (M + 31) // 32 * 32, (N + 31) // 32 * 32
+    assert did.did_mem_estimate(M, N, K, ob) - borrowed == 2 * 2 * Mp * Np
     # packed C: per 32-column tile (64/16*3 + 64/32*6) units of 64 x 16 bytes
     cq = (N + 31) // 32 * (12 + 12) * 64 * 16
     assert borrowed > cq + 4 * K * N and borrowed < 3e9

@@ -298,6 +298,29 @@ def test_bf16_storage_form_matches_oracle_on_rounded_x(M, N, K):
     assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
 
 
+@pytest.mark.parametrize("M,N,K", [(500, 2000, 10), (130, 777, 64), (97, 1234, 33), (64, 4001, 7)])
+def test_bf16_storage_equals_float32_form_on_rounded_x_bitwise(M, N, K):
+    """The bf16 form reads X from two tiled copies (one per pass) and the float32 form
+    reads the column-major X, but both feed the same values to the same arithmetic: run
+    on X and on bf16(X) respectively, their iterates agree bit for bit.  Ragged M and N
+    (zero padding of the tiles) and a column-pass wave past the last tile (N = 777, 4001)
+    are covered."""
+    torch = require_gpu()
+    rng = np.random.default_rng(7 * M + N + K)
+    X32 = to_f32_colmajor(rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N))))
+    Xr = to_f32_colmajor(round_to_bf16(X32))
+    ob = did.did_default_opts()
+    ob.x_dtype = did.DID_BF16
+    announce(f"bf16 tiled vs float32 on rounded X, M={M} N={N} K={K}")
+    a = run_gpu(torch, X32, K, iters=(1, 6), opts=ob)
+    b = run_gpu(torch, Xr, K, iters=(1, 6), opts=did.did_default_opts())
+    for n in (1, 6):
+        np.testing.assert_array_equal(a[n][0], b[n][0])
+        np.testing.assert_array_equal(a[n][1], b[n][1])
+    np.testing.assert_array_equal(a["hist"], b["hist"])
+    assert a["f"] == b["f"]
+
+
 def test_bf16_storage_rejects_bad_x_and_borrow_is_ignored():
     torch = require_gpu()
     X = np.ones((40, 40), dtype=np.float32)
