@@ -91,7 +91,13 @@ enum {
  *                  ranges whose W partials are summed (in ascending order).  0 takes the
  *                  value did_autotune recorded for the instance's shape class, else 4096.
  *                  Results depend on it only through summation order.
- *   reserved       must be 0.
+ *   x_tiled        float32 form only.  0: the passes read X as given (column-major).
+ *                  1: the engine keeps X as two float32 copies in 32 x 32 tile order, one
+ *                  per pass over X (the layout DID_BF16 uses), zero-padded to multiples of
+ *                  32 rows and columns, so that both passes load whole tiles with
+ *                  full-width loads.  Costs 8 * Mpad * Npad bytes of device memory and one
+ *                  conversion pass at init; borrow_x does not apply.  Results are the same
+ *                  bit for bit.  Not accepted on the thin-matrix path, nor in batches.
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
  *
  * Shapes with M <= 16, K <= 8 and M <= 8 or K <= 4 (such as the experiments' synthetic
@@ -106,7 +112,7 @@ typedef struct did_opts {
   int32_t borrow_x;
   int32_t algorithm;
   int32_t row_blocks;
-  int32_t reserved;
+  int32_t x_tiled;
   void* stream;
 } did_opts;
 

@@ -72,7 +72,7 @@ class did_opts(ctypes.Structure):
         ("borrow_x", ctypes.c_int32),
         ("algorithm", ctypes.c_int32),
         ("row_blocks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("x_tiled", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

@@ -155,7 +155,7 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   if (o.refresh_every != 1) return fail(DID_EINVAL, "refresh_every must be 1");
   if (o.n_blocks < 0) return fail(DID_EINVAL, "n_blocks must be >= 0");
   if (o.row_blocks < 0) return fail(DID_EINVAL, "row_blocks must be >= 0");
-  if (o.reserved != 0) return fail(DID_EINVAL, "reserved must be 0");
+  if (o.x_tiled != 0 && o.x_tiled != 1) return fail(DID_EINVAL, "x_tiled must be 0 or 1");
   s.M = M;
   s.N = N;
   s.K = K;
@@ -163,11 +163,13 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   s.nchunks = (M + 31) / 32;
   s.Mpad = s.nchunks * 32;
   s.xbf16 = o.x_dtype == DID_BF16;
+  s.xtiled = s.xbf16 || o.x_tiled;
   s.thin = (M <= 16 && K <= 8 && (M <= 8 || K <= 4)) ? 1 : 0;
   if (o.algorithm != DID_ALG_DID && o.algorithm != DID_ALG_DBCD) return fail(DID_EINVAL, "unknown algorithm");
   if (o.algorithm == DID_ALG_DBCD && !s.thin)
     return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8, M <= 8 or K <= 4)");
   if (s.thin && s.xbf16) return fail(DID_EINVAL, "the thin-matrix path stores X as float32 only");
+  if (s.thin && o.x_tiled) return fail(DID_EINVAL, "the thin-matrix path reads X as given (x_tiled must be 0)");
   if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
     return fail(DID_EDEVICE, "thin path: occupancy query failed");
   return DID_OK;
@@ -185,8 +187,8 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
   const int64_t M = s.M, N = s.N, K = s.K, KP = s.KP, NP = didk::n_pairs(s.KP);
   auto b = [](int64_t n) { return n > 0 ? n : 1; };
   int64_t t = b(4);  // flag
-  if (s.xbf16)
-    t += b(2 * didk::tiled_x_elems(s) * 2);
+  if (s.xtiled)
+    t += b(2 * didk::tiled_x_elems(s) * (s.xbf16 ? 2 : 4));
   else if (x_copied)
     t += b(M * N * 4);
   t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
@@ -222,11 +224,11 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   hipError_t e;
   const bool xdev = is_device_ptr(Xv);
   const float* xin = nullptr;
-  float* xtmp = nullptr;  // temporary upload for the bf16 form, freed below
-  if (xdev && (o.borrow_x || s.xbf16)) {
+  float* xtmp = nullptr;  // temporary upload for the tiled forms, freed below
+  if (xdev && (o.borrow_x || s.xtiled)) {
     xin = static_cast<const float*>(Xv);
-    h->own_x = !s.xbf16 ? false : true;
-  } else if (!s.xbf16) {
+    h->own_x = !s.xtiled ? false : true;
+  } else if (!s.xtiled) {
     float* xc = nullptr;
     if ((rc = dalloc(h, &xc, M * N))) return rc;
     if ((e = hipMemcpyAsync(xc, Xv, (size_t)(M * N) * sizeof(float), hipMemcpyDefault, h->st)) != hipSuccess)
@@ -258,19 +260,19 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       return fail(DID_EINVAL, "X must be finite and nonnegative");
     }
   }
-  if (s.xbf16) {  // the two tiled copies (one per pass) in one allocation
-    __bf16* xb = nullptr;
-    const int64_t te = didk::tiled_x_elems(s);
-    if ((rc = dalloc(h, &xb, 2 * te))) {
+  if (s.xtiled) {  // the two tiled copies (one per pass) in one allocation
+    unsigned char* xb = nullptr;
+    const int64_t te = didk::tiled_x_elems(s), esz = s.xbf16 ? 2 : 4;
+    if ((rc = dalloc(h, &xb, 2 * te * esz))) {
       if (xtmp) (void)hipFree(xtmp);
       return rc;
     }
-    e = didk::tile_bf16(s, xin, xb, xb + te, h->st);
+    e = didk::tile_x(s, xin, xb, xb + te * esz, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (xtmp) (void)hipFree(xtmp);
-    if (e != hipSuccess) return dev_fail(h, e, "bf16 storage of X");
+    if (e != hipSuccess) return dev_fail(h, e, "tiled storage of X");
     h->X = xb;
-    h->XR = xb + te;
+    h->XR = xb + te * esz;
     s.vec4 = 0;  // the tiled copies are read with their own full-width loads
   } else {
     h->X = const_cast<float*>(xin);

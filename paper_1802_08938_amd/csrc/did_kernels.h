@@ -15,6 +15,7 @@ struct Shape {
   int64_t Mpad;      // nchunks * 32
   int vec4;          // vector loads of X are aligned (M % 4 == 0 and X aligned)
   int xbf16;         // X is stored as bf16 (reduced-precision storage form), else float32
+  int xtiled;        // X is stored in tile order (always for bf16; float32 on request)
   int thin;          // thin-matrix path (M <= 16, K <= 8, M <= 8 or K <= 4): one fused pass per iteration
   int64_t thin_grid; // thin path: blocks per launch (one wave of resident blocks)
 };
@@ -51,18 +52,21 @@ inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
 // ---- launchers (all asynchronous on `st`; they return the launch status) ----
 hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
 hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
-// bf16 storage form of X: two copies in 32 x 32 tile order, one per pass, zero-padded to
-// Mpad x (32 * ntiles).  A tile holds 1024 bf16 as 2 x 64 units of eight: unit q*64 + l,
-// element t is value i = 8q + t of lane l's MFMA accumulator tile, for l = 32h + r:
+// Tiled storage of X (the bf16 form, and the float32 form on request): two copies in
+// 32 x 32 tile order, one per pass, zero-padded to
+// Mpad x (32 * ntiles).  A tile holds 1024 values as 16-byte units, E = 8 (bf16) or 4
+// (float32) values per unit, 16 / E units per lane: unit q*64 + l, element t is value
+// i = E q + t of lane l's MFMA accumulator tile, for l = 32h + r:
 //   column-pass copy XC, tile (T, c) at (T * nchunks + c) * 1024:
 //       X[32c + 8(i/4) + 4h + i%4][32T + r]      (the accumulator layout of X)
 //   row-pass copy XR, tile (c, T) at (c * ntiles + T) * 1024:
 //       X[32c + r][32T + 8(i/4) + 4h + i%4]      (the accumulator layout of X^T)
 // so that a pass loads a lane's 16 values with two 16-byte loads and a wave's tile in two
-// fully used 1 kB runs.  Values are rounded to nearest even.
+// fully used 1 kB runs.  bf16 values are rounded to nearest even.
 inline int64_t n_tiles(const Shape& s) { return (s.N + 31) / 32; }
 inline int64_t tiled_x_elems(const Shape& s) { return s.nchunks * n_tiles(s) * 1024; }
-hipError_t tile_bf16(const Shape& s, const float* src, __bf16* xc, __bf16* xr, hipStream_t st);
+// xc and xr each hold tiled_x_elems(s) values of the storage type (s.xbf16)
+hipError_t tile_x(const Shape& s, const float* src, void* xc, void* xr, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
 // Pack B (three bf16 pieces per entry) into MFMA operand order (Bq: the E-order units of

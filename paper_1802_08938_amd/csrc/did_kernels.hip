@@ -125,6 +125,18 @@ __device__ __forceinline__ f32x4 ldx4(const __bf16* p) {
   return r;
 }
 __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
+// float32 X in tile order (the x_tiled option): a distinct element type selects the tiled
+// loads in the passes at compile time.  Its column-major loads exist only so that the
+// untaken branches compile.
+struct xtf32 {
+  float v;
+};
+__device__ __forceinline__ float ldx(const xtf32* p) { return p->v; }
+__device__ __forceinline__ f32x4 ldx4(const xtf32* p) { return *reinterpret_cast<const f32x4*>(p); }
+template <typename XT>
+struct x_is_tiled {
+  static constexpr bool value = std::is_same<XT, __bf16>::value || std::is_same<XT, xtf32>::value;
+};
 
 // Packed C (Cq), per 32-column tile T, in 16-byte units of eight bf16:
 //   E order, unit (s*3 + p)*64 + l, element t: piece p of C[16s + 8(l/32) + t][32T + l%32]
@@ -221,54 +233,63 @@ hipError_t scale(float* p, int64_t n, float a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ bf16 storage of X
-// Both tiled bf16 copies of X (layout in did_kernels.h); one thread per 16-byte unit of
-// each copy, values rounded to nearest even, zero outside M x N.
+// ------------------------------------------------------------------ tiled storage of X
+// Both tiled copies of X (layout in did_kernels.h), elements of type T (bf16 rounded to
+// nearest even, or float32); one thread per 16-byte unit of each copy, zero outside M x N.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__global__ void k_tile_bf16(const float* __restrict__ src, int64_t M, int64_t N, int64_t nchunks, int64_t ntiles,
-                            __bf16* __restrict__ xc, __bf16* __restrict__ xr) {
-  const int64_t units = nchunks * ntiles * 128;
+template <typename ET>
+__global__ void k_tile_x(const float* __restrict__ src, int64_t M, int64_t N, int64_t nchunks, int64_t ntiles,
+                         ET* __restrict__ xc, ET* __restrict__ xr) {
+  constexpr int E = 16 / (int)sizeof(ET);  // values per unit
+  constexpr int Q = 16 / E;               // units per lane
+  const int64_t units = nchunks * ntiles * 64 * Q;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += stride) {
-    const int64_t tile = u >> 7;  // the same index in both copies' own tile order
-    const int q = (int)(u >> 6) & 1, l = (int)u & 63, h = l >> 5, r = l & 31;
+    const int64_t tile = u / (64 * Q);  // the same index in both copies' own tile order
+    const int q = (int)(u / 64 % Q), l = (int)u & 63, h = l >> 5, r = l & 31;
+    const int64_t at = tile * 1024 + (int64_t)(q * 64 + l) * E;
     {  // column-pass copy: tile (T, c)
       const int64_t T = tile / nchunks, c = tile - T * nchunks;
       const int64_t j = T * 32 + r;
-      __bf16 v[8];
+      ET v[E];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int i = 8 * q + t;
+      for (int t = 0; t < E; ++t) {
+        const int i = E * q + t;
         const int64_t m = c * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-        v[t] = (__bf16)((m < M && j < N) ? src[j * M + m] : 0.0f);
+        v[t] = (ET)((m < M && j < N) ? src[j * M + m] : 0.0f);
       }
-      *reinterpret_cast<u32x4*>(xc + tile * 1024 + (int64_t)(q * 64 + l) * 8) = __builtin_bit_cast(u32x4, v);
+      *reinterpret_cast<u32x4*>(xc + at) = __builtin_bit_cast(u32x4, v);
     }
     {  // row-pass copy: tile (c, T)
       const int64_t c = tile / ntiles, T = tile - c * ntiles;
       const int64_t m = c * 32 + r;
-      __bf16 v[8];
+      ET v[E];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int i = 8 * q + t;
+      for (int t = 0; t < E; ++t) {
+        const int i = E * q + t;
         const int64_t j = T * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-        v[t] = (__bf16)((m < M && j < N) ? src[j * M + m] : 0.0f);
+        v[t] = (ET)((m < M && j < N) ? src[j * M + m] : 0.0f);
       }
-      *reinterpret_cast<u32x4*>(xr + tile * 1024 + (int64_t)(q * 64 + l) * 8) = __builtin_bit_cast(u32x4, v);
+      *reinterpret_cast<u32x4*>(xr + at) = __builtin_bit_cast(u32x4, v);
     }
   }
 }
 
-hipError_t tile_bf16(const Shape& s, const float* src, __bf16* xc, __bf16* xr, hipStream_t st) {
-  const int64_t units = s.nchunks * n_tiles(s) * 128;
+hipError_t tile_x(const Shape& s, const float* src, void* xc, void* xr, hipStream_t st) {
+  const int64_t units = s.nchunks * n_tiles(s) * 64 * (s.xbf16 ? 2 : 4);
   int64_t blocks = (units + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  k_tile_bf16<<<(unsigned)blocks, 256, 0, st>>>(src, s.M, s.N, s.nchunks, n_tiles(s), xc, xr);
+  if (s.xbf16)
+    k_tile_x<__bf16><<<(unsigned)blocks, 256, 0, st>>>(src, s.M, s.N, s.nchunks, n_tiles(s),
+                                                        static_cast<__bf16*>(xc), static_cast<__bf16*>(xr));
+  else
+    k_tile_x<float><<<(unsigned)blocks, 256, 0, st>>>(src, s.M, s.N, s.nchunks, n_tiles(s), static_cast<float*>(xc),
+                                                       static_cast<float*>(xr));
   return hipGetLastError();
 }
 
-// The 16 values of one lane's accumulator tile from a tiled bf16 copy of X.
-__device__ __forceinline__ f32x16 ld_tile_bf16(const __bf16* tile, int l) {
+// The 16 values of one lane's accumulator tile from a tiled copy of X.
+__device__ __forceinline__ f32x16 ld_tile(const __bf16* tile, int l) {
   f32x16 v;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -278,6 +299,16 @@ __device__ __forceinline__ f32x16 ld_tile_bf16(const __bf16* tile, int l) {
       v[8 * q + 2 * k] = __builtin_bit_cast(float, w[k] << 16);
       v[8 * q + 2 * k + 1] = __builtin_bit_cast(float, w[k] & 0xffff0000u);
     }
+  }
+  return v;
+}
+__device__ __forceinline__ f32x16 ld_tile(const xtf32* tile, int l) {
+  f32x16 v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x4 w = *reinterpret_cast<const f32x4*>(tile + (q * 64 + l) * 4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[4 * q + k] = w[k];
   }
   return v;
 }
@@ -489,13 +520,13 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   const bool tilefull = vec4 && (j0 + 32 <= N);  // wave-uniform
   auto xload = [&](int64_t c) {
     f32x16 v;
-    if constexpr (std::is_same<XT, __bf16>::value) {  // tiled copy XC
+    if constexpr (x_is_tiled<XT>::value) {  // tiled copy XC
       if (!tileok) {  // a wave past the last tile: E = 0, so it adds nothing to f
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = 0.0f;
         return v;
       }
-      return ld_tile_bf16(X + (T * nchunks + c) * 1024, l);
+      return ld_tile(X + (T * nchunks + c) * 1024, l);
     }
     const int64_t m0 = c * 32;
     if (tilefull && m0 + 32 <= M) {
@@ -646,6 +677,8 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const __bf16*
   const f32x4* C = static_cast<const f32x4*>(Cqv);
   if (s.xbf16)
     colpass_launch(s, static_cast<const __bf16*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
+  else if (s.xtiled)
+    colpass_launch(s, static_cast<const xtf32*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
   else
     colpass_launch(s, static_cast<const float*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
   return hipGetLastError();
@@ -905,8 +938,8 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   const bool rowsfull = active && m0 + 32 <= M;            // wave-uniform
   auto xload = [&](int64_t T) {
     f32x16 v;
-    if constexpr (std::is_same<XT, __bf16>::value) {  // tiled copy XR
-      return ld_tile_bf16(X + ((active ? c : 0) * ((N + 31) / 32) + T) * 1024, l);
+    if constexpr (x_is_tiled<XT>::value) {  // tiled copy XR
+      return ld_tile(X + ((active ? c : 0) * ((N + 31) / 32) + T) * 1024, l);
     }
     const int64_t j0 = T * 32;
     const XT* xt = X + j0 * M;  // wave-uniform
@@ -1023,6 +1056,8 @@ hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const __bf16*
   const f32x4* Cq = static_cast<const f32x4*>(Cqv);
   if (s.xbf16)
     rowpass_launch(s, static_cast<const __bf16*>(X), Cq, BqE, Wpart, tb, R, st);
+  else if (s.xtiled)
+    rowpass_launch(s, static_cast<const xtf32*>(X), Cq, BqE, Wpart, tb, R, st);
   else
     rowpass_launch(s, static_cast<const float*>(X), Cq, BqE, Wpart, tb, R, st);
   return hipGetLastError();

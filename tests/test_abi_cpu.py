@@ -40,7 +40,7 @@ def test_default_opts_and_struct_layout():
     _lib_or_skip()
     o = did.did_default_opts()
     assert (o.n_blocks, o.x_dtype, o.refresh_every, o.init_scale, o.borrow_x) == (0, did.DID_F32, 1, 0, 0)
-    assert (o.algorithm, o.row_blocks, o.reserved) == (did.DID_ALG_DID, 0, 0)
+    assert (o.algorithm, o.row_blocks, o.x_tiled) == (did.DID_ALG_DID, 0, 0)
     assert o.stream is None
     assert ctypes.sizeof(did.did_opts) == 40
     so = did.did_server_default_opts()

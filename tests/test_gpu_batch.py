@@ -256,15 +256,16 @@ def test_autotune_records_and_applies():
         did.did_autotune_clear()
 
 
-@pytest.mark.parametrize("M,N,K,xd,borrow", [(300, 2000, 10, did.DID_F32, 1), (300, 2000, 10, did.DID_F32, 0),
-                                             (130, 777, 64, did.DID_BF16, 0), (5, 1000, 3, did.DID_F32, 1),
-                                             (16, 4000, 8, did.DID_F32, 0)])
-def test_memory_estimate_matches_allocation(M, N, K, xd, borrow):
+@pytest.mark.parametrize("M,N,K,xd,borrow,tiled", [(300, 2000, 10, did.DID_F32, 1, 0), (300, 2000, 10, did.DID_F32, 0, 0),
+                                                   (130, 777, 64, did.DID_BF16, 0, 0), (5, 1000, 3, did.DID_F32, 1, 0),
+                                                   (16, 4000, 8, did.DID_F32, 0, 0), (130, 777, 40, did.DID_F32, 1, 1)])
+def test_memory_estimate_matches_allocation(M, N, K, xd, borrow, tiled):
     torch = require_gpu()
     announce(f"memory estimate {M}x{N} K={K}")
     o = did.did_default_opts()
     o.x_dtype = xd
     o.borrow_x = borrow
+    o.x_tiled = tiled
     X = torch.rand((N, M), device="cuda")
     h = did.did_init_ex(X, M, N, K, 5, o)
     try:

@@ -321,6 +321,52 @@ def test_bf16_storage_equals_float32_form_on_rounded_x_bitwise(M, N, K):
     assert a["f"] == b["f"]
 
 
+@pytest.mark.parametrize("M,N,K", [(500, 2000, 10), (130, 777, 64), (97, 1234, 33), (5000, 3001, 50)])
+def test_tiled_float32_x_equals_column_major_bitwise(M, N, K):
+    """x_tiled = 1 keeps X as two float32 copies in tile order; the passes load the same
+    values, so the iterates equal those of the column-major form bit for bit."""
+    torch = require_gpu()
+    rng = np.random.default_rng(3 * M + N + K)
+    X32 = to_f32_colmajor(rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N))))
+    ot = did.did_default_opts()
+    ot.x_tiled = 1
+    announce(f"tiled float32 X vs column-major, M={M} N={N} K={K}")
+    a = run_gpu(torch, X32, K, iters=(1, 6), opts=ot)
+    b = run_gpu(torch, X32, K, iters=(1, 6), opts=did.did_default_opts())
+    for n in (1, 6):
+        np.testing.assert_array_equal(a[n][0], b[n][0])
+        np.testing.assert_array_equal(a[n][1], b[n][1])
+    np.testing.assert_array_equal(a["hist"], b["hist"])
+    assert a["f"] == b["f"]
+
+
+def test_tiled_x_rejected_on_thin_shapes_and_in_batches():
+    torch = require_gpu()
+    announce("x_tiled rejections")
+    ot = did.did_default_opts()
+    ot.x_tiled = 1
+    Xt = torch.rand((1000, 5), device="cuda")
+    with pytest.raises(did.DidError) as ei:
+        did.did_init_ex(Xt, 5, 1000, 3, 1, ot)
+    assert ei.value.code == did.DID_EINVAL
+    ot.x_tiled = 2
+    X = torch.rand((1000, 100), device="cuda")
+    with pytest.raises(did.DidError) as ei:
+        did.did_init_ex(X, 100, 1000, 8, 1, ot)
+    assert ei.value.code == did.DID_EINVAL
+    ot.x_tiled = 1
+    h = did.did_init_ex(X, 100, 1000, 8, 1, ot)
+    b = did.did_batch_create()
+    try:
+        with pytest.raises(did.DidError) as ei:
+            did.did_batch_add(b, h)
+        assert ei.value.code == did.DID_EINVAL
+        did.did_iterate(h, 2)  # still usable alone
+    finally:
+        did.did_batch_free(b)
+        did.did_free(h)
+
+
 def test_bf16_storage_rejects_bad_x_and_borrow_is_ignored():
     torch = require_gpu()
     X = np.ones((40, 40), dtype=np.float32)
