@@ -346,7 +346,7 @@ def run_nsweep(args, torch, did):
         opts = did.did_default_opts()
         opts.n_blocks = cfg["n_blocks"]
         opts.borrow_x = 1
-        opts.x_tiled = 1
+        opts.x_tiled = 0 if args.x_given else 1
         opts.stream = stream.cuda_stream
         h = did.did_init_ex(X, M, N, K, 12345, opts)
         try:
@@ -422,6 +422,7 @@ def run_batch(args, torch, did):
         for j, X in zip(jobs, Xs):
             o = did.did_default_opts()
             o.borrow_x = 1
+            o.x_tiled = 0 if args.x_given else 1
             o.stream = stream.cuda_stream
             hs.append(did.did_init_ex(X, j["M"], j["N"], j["K"], 1000 + j["seed"], o))
         return hs
@@ -485,7 +486,8 @@ def run_batch(args, torch, did):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "jobs": len(jobs)},
+        "config": {"workload": cfg["desc"], "jobs": len(jobs),
+                   "x_layout": "as given (column-major)" if args.x_given else "tile order (x_tiled=1)"},
         "plain_form_instance_iter_s": round(n_it / (plain_ms / 1e3), 2),
         "speedup_vs_plain_form": round(plain_ms / batch_ms, 3),
         "batched_tflops_fp32_equiv": round(flops_it * T / (batch_ms / 1e3) / 1e12, 2),
@@ -510,6 +512,7 @@ def run_serve(args, torch, did):
     so.max_active = args.serve_slots
     so.max_iter = 50
     so.rel_tol = 1e-4
+    so.x_tiled = 0 if args.x_given else 1  # float32 jobs keep X in tile order
     stream = torch.cuda.Stream()
     so.stream = stream.cuda_stream
     srv = did.did_server_create(so)
@@ -582,7 +585,8 @@ def run_serve(args, torch, did):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg["desc"] + ("; X stored as bf16" if args.serve_bf16 else ""), "jobs": n_jobs,
-                   "slots": so.max_active, "x_storage": "bf16" if args.serve_bf16 else "f32"},
+                   "slots": so.max_active, "x_storage": "bf16" if args.serve_bf16 else "f32",
+                   "x_layout": "tile order" if (args.serve_bf16 or not args.x_given) else "as given (column-major)"},
         "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "latency_mean_s": round(float(lat.mean()), 4),
@@ -610,6 +614,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")
     ap.add_argument("--serve-slots", type=int, default=64, help="serve workload: batch slots")
     ap.add_argument("--serve-bf16", action="store_true", help="serve workload: store each job's X as bf16")
+    ap.add_argument("--x-given", action="store_true",
+                    help="float32 X read as given (column-major) instead of kept in tile order")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "
@@ -647,7 +653,7 @@ def main():
     opts.x_dtype = did.DID_BF16 if cfg.get("x_bf16") else did.DID_F32
     # the engine keeps X in 32x32 tile order, one copy per pass (made once at init; the
     # bf16 form always does)
-    opts.x_tiled = 1
+    opts.x_tiled = 0 if args.x_given else 1
     opts.stream = stream.cuda_stream
     t0 = time.perf_counter()
     h = did.did_init_ex(X, M, N, K, 12345, opts)
@@ -722,7 +728,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "M": M, "N": N, "K": K, "n_blocks": cfg["n_blocks"],
-                   "x_layout": "two copies in 32x32 tile order (one per pass), made once at init (x_tiled=1)"},
+                   "x_layout": "as given (column-major)" if args.x_given and not cfg.get("x_bf16") else
+                               "two copies in 32x32 tile order (one per pass), made once at init (x_tiled=1)"},
         "hbm_gbs_algorithmic": round(cnt["iter_bytes"] * it_s / 1e9, 2),
         "stage_ms_per_iter": {k: round(v / max(n_it, 1), 4) for k, v in stages.items()},
         "objective_last": f_last,

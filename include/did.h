@@ -97,7 +97,7 @@ enum {
  *                  32 rows and columns, so that both passes load whole tiles with
  *                  full-width loads.  Costs 8 * Mpad * Npad bytes of device memory and one
  *                  conversion pass at init; borrow_x does not apply.  Results are the same
- *                  bit for bit.  Not accepted on the thin-matrix path, nor in batches.
+ *                  bit for bit.  Not accepted on the thin-matrix path.
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
  *
  * Shapes with M <= 16, K <= 8 and M <= 8 or K <= 4 (such as the experiments' synthetic
@@ -219,7 +219,8 @@ int did_autotune_clear(void);
 
 /*
  * Batched form: many instances of uneven (M, N, K) advanced together.
- * Members are grouped by (K <= 32 or not, X storage); each stage of an iteration is one
+ * Members are grouped by (K <= 32 or not, X storage: float32 as given, float32 tiled or
+ * bf16); each stage of an iteration is one
  * launch per group of a persistent kernel that walks the work items of all the group's
  * members from a device-resident table, and the launches of one iteration are captured
  * once in a hipGraph that each iteration replays.  A member runs exactly the work of its
@@ -266,6 +267,9 @@ int did_batch_free(did_batch b);
  *   max_active   batch slots (1..256, default 64)
  *   max_iter     iteration cap per job (default 50)
  *   rel_tol      relative objective change that ends a job (default 1e-4)
+ *   x_tiled      1: float32 jobs keep X in tile order (did_opts.x_tiled), which makes
+ *                their iterations faster and adds 8 bytes per (padded) entry of X to
+ *                their footprint; 0 (default): float32 jobs read the borrowed X as given
  *   stream       hipStream_t for all server work (NULL: one owned by the server)
  * Job states: DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED.
  *   did_server_submit  queue a job (x_dtype DID_F32 or DID_BF16; the init seed as in
@@ -289,6 +293,7 @@ typedef struct did_server_opts {
   int32_t max_active;
   int32_t max_iter;
   double rel_tol;
+  int32_t x_tiled;
   void* stream;
 } did_server_opts;
 typedef struct did_server_ctx* did_server;

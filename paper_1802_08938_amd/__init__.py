@@ -83,6 +83,7 @@ class did_server_opts(ctypes.Structure):
         ("max_active", ctypes.c_int32),
         ("max_iter", ctypes.c_int32),
         ("rel_tol", ctypes.c_double),
+        ("x_tiled", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

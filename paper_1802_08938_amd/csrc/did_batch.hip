@@ -35,6 +35,7 @@ using didk::GInst;
 using didk::GS_N;
 using didk::GTable;
 using didk::kMaxBatch;
+constexpr int kGroups = 2 * didk::XK_N;  // (K class, X storage kind)
 
 // ------------------------------------------------------------------ autotuned row pass
 namespace {
@@ -83,7 +84,7 @@ struct did_batch_ctx {
     GTable htab;             // host image
     int64_t grids[GS_N] = {0};
     bool have_grids = false;
-  } groups[4];
+  } groups[kGroups];
   double* dfcur = nullptr;  // device: latest objective per slot
   std::vector<int> slot_of;  // parallel to members
   std::vector<double> hf;
@@ -96,7 +97,7 @@ struct did_batch_ctx {
 
 namespace {
 
-int group_of(const did_ctx* h) { return (h->s.KP == 64 ? 2 : 0) + (h->s.xbf16 ? 1 : 0); }
+int group_of(const did_ctx* h) { return (h->s.KP == 64 ? didk::XK_N : 0) + didk::x_kind(h->s); }
 
 int bdev_fail(did_batch_ctx* b, hipError_t e, const char* what) {
   if (b) b->sticky = 1;
@@ -151,7 +152,7 @@ int rebuild(did_batch_ctx* b) {
   unsigned mask = 0;
   // earlier table uploads and replays have finished before the host images change
   if ((e = hipStreamSynchronize(b->st)) != hipSuccess) return bdev_fail(b, e, "batch rebuild");
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < kGroups; ++g) {
     auto& G = b->groups[g];
     G.m.clear();
   }
@@ -159,7 +160,7 @@ int rebuild(did_batch_ctx* b) {
     did_ctx* h = b->members[i];
     b->groups[group_of(h)].m.push_back(h);
   }
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < kGroups; ++g) {
     auto& G = b->groups[g];
     if (G.m.empty()) continue;
     mask |= 1u << g;
@@ -172,7 +173,7 @@ int rebuild(did_batch_ctx* b) {
       G.dtab = static_cast<GTable*>(p);
     }
     if (!G.have_grids) {
-      if ((e = didk::group_grids(g >= 2 ? 64 : 32, g & 1, G.grids)) != hipSuccess)
+      if ((e = didk::group_grids(g >= didk::XK_N ? 64 : 32, g % didk::XK_N, G.grids)) != hipSuccess)
         return bdev_fail(b, e, "occupancy of the grouped kernels");
       G.have_grids = true;
     }
@@ -201,10 +202,10 @@ int rebuild(did_batch_ctx* b) {
       if ((e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return bdev_fail(b, e, "graph capture");
       hipError_t le = hipSuccess;
-      for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < kGroups; ++g) {
         auto& G = b->groups[g];
         if (!(mask & (1u << g))) continue;
-        hipError_t r = didk::group_iteration(g >= 2 ? 64 : 32, g & 1, G.dtab, G.grids, b->st);
+        hipError_t r = didk::group_iteration(g >= didk::XK_N ? 64 : 32, g % didk::XK_N, G.dtab, G.grids, b->st);
         if (r != hipSuccess && le == hipSuccess) le = r;
       }
       if ((e = hipStreamEndCapture(b->st, &b->graph)) != hipSuccess) return bdev_fail(b, e, "graph capture");
@@ -219,7 +220,7 @@ int rebuild(did_batch_ctx* b) {
 }
 
 int free_slot(const did_batch_ctx* b) {
-  for (int s = 0; s < 4 * kMaxBatch; ++s)
+  for (int s = 0; s < kGroups * kMaxBatch; ++s)
     if (std::find(b->slot_of.begin(), b->slot_of.end(), s) == b->slot_of.end()) return s;
   return -1;
 }
@@ -248,7 +249,7 @@ int did_batch_create(void* stream, did_batch* out) {
     b->own_stream = true;
   }
   void* p = nullptr;
-  if ((e = hipMalloc(&p, sizeof(double) * 4 * kMaxBatch)) != hipSuccess) {
+  if ((e = hipMalloc(&p, sizeof(double) * kGroups * kMaxBatch)) != hipSuccess) {
     (void)hipGetLastError();
     if (b->own_stream) (void)hipStreamDestroy(b->st);
     delete b;
@@ -266,7 +267,6 @@ int did_batch_add(did_batch b, did_handle h) {
   if (h->dev != b->dev) return fail(DID_EINVAL, "handle and batch are on different devices");
   if (h->s.thin) return fail(DID_EINVAL, "the batched form runs the MFMA passes; thin-matrix shapes are not accepted");
   if (h->algorithm != DID_ALG_DID) return fail(DID_EINVAL, "the batched form runs DID only");
-  if (h->s.xtiled && !h->s.xbf16) return fail(DID_EINVAL, "x_tiled instances are not accepted in batches");
   if (h->profiling) return fail(DID_ESTATE, "disable profiling before adding a handle to a batch");
   int n_in_group = 0;
   for (did_ctx* m : b->members) n_in_group += group_of(m) == group_of(h);
@@ -326,9 +326,9 @@ int did_batch_objectives(did_batch b, double* f, int32_t cap, int32_t* n) {
   if (rc) return rc;
   if (!n || (cap > 0 && !f) || cap < 0) return fail(DID_EINVAL, "bad output arguments");
   DeviceGuard g(b->dev);
-  b->hf.resize(4 * kMaxBatch);
+  b->hf.resize(kGroups * kMaxBatch);
   hipError_t e;
-  if ((e = hipMemcpyAsync(b->hf.data(), b->dfcur, sizeof(double) * 4 * kMaxBatch, hipMemcpyDeviceToHost, b->st)) !=
+  if ((e = hipMemcpyAsync(b->hf.data(), b->dfcur, sizeof(double) * kGroups * kMaxBatch, hipMemcpyDeviceToHost, b->st)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(b->st)) != hipSuccess)
     return bdev_fail(b, e, "objective readback");
@@ -501,7 +501,8 @@ int did_server_create(const did_server_opts* opts, did_server* out) {
   did_server_opts o;
   did_server_default_opts(&o);
   if (opts) o = *opts;
-  if (o.hbm_budget <= 0 || o.max_active < 1 || o.max_active > 4 * kMaxBatch || o.max_iter < 1 || !(o.rel_tol >= 0.0))
+  if (o.hbm_budget <= 0 || o.max_active < 1 || o.max_active > 4 * kMaxBatch || o.max_iter < 1 ||
+      !(o.rel_tol >= 0.0) || (o.x_tiled != 0 && o.x_tiled != 1))
     return fail(DID_EINVAL, "bad server options");
   did_server_ctx* s = new (std::nothrow) did_server_ctx();
   if (!s) return fail(DID_ENOMEM, "host allocation failed");
@@ -542,6 +543,7 @@ int did_server_submit(did_server s, const void* X, int64_t M, int64_t N, int32_t
   did_default_opts(&o);
   o.x_dtype = x_dtype;
   o.borrow_x = 1;
+  o.x_tiled = s->o.x_tiled;
   int64_t bytes = 0;
   if ((rc = did_mem_estimate(M, N, K, &o, 1, &bytes))) return rc;
   if (M <= 16 && K <= 8 && (M <= 8 || K <= 4)) return fail(DID_EINVAL, "the server runs the MFMA passes; thin shapes are not served");
@@ -633,6 +635,7 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
     did_default_opts(&o);
     o.x_dtype = j.x_dtype;
     o.borrow_x = 1;
+    o.x_tiled = s->o.x_tiled;
     o.stream = s->adm_st;
     s->queue.pop_front();
     j.t_start = std::chrono::steady_clock::now();

@@ -148,10 +148,13 @@ struct GTable {
 
 // work items of one instance in each stage (rows of the row pass are a multiple of 8)
 void ginst_items(const Shape& s, int R, int64_t items[GS_N]);
+// Storage kinds of X in the batched form: float32 column-major, bf16 tiled, float32 tiled.
+enum { XK_F32 = 0, XK_BF16 = 1, XK_F32_TILED = 2, XK_N = 3 };
+inline int x_kind(const Shape& s) { return s.xbf16 ? XK_BF16 : (s.xtiled ? XK_F32_TILED : XK_F32); }
 // persistent grid of each grouped stage kernel on the current device (resident blocks)
-hipError_t group_grids(int KP, int xbf16, int64_t grids[GS_N]);
+hipError_t group_grids(int KP, int xkind, int64_t grids[GS_N]);
 // one iteration of every instance in the group table dtab (device memory)
-hipError_t group_iteration(int KP, int xbf16, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st);
+hipError_t group_iteration(int KP, int xkind, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st);
 
 // ---- thin-matrix path (did_thin.hip) ----
 // mode 0: DID column work (sweep, W/V/f block partials); 1: objective partials only;

@@ -1305,9 +1305,15 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
   return hipSuccess;
 }
 
-hipError_t group_grids(int KP, int xbf16, int64_t grids[GS_N]) {
-  if (KP == 32) return xbf16 ? group_grids_t<32, __bf16>(grids) : group_grids_t<32, float>(grids);
-  return xbf16 ? group_grids_t<64, __bf16>(grids) : group_grids_t<64, float>(grids);
+hipError_t group_grids(int KP, int xkind, int64_t grids[GS_N]) {
+  if (KP == 32) {
+    if (xkind == XK_BF16) return group_grids_t<32, __bf16>(grids);
+    if (xkind == XK_F32_TILED) return group_grids_t<32, xtf32>(grids);
+    return group_grids_t<32, float>(grids);
+  }
+  if (xkind == XK_BF16) return group_grids_t<64, __bf16>(grids);
+  if (xkind == XK_F32_TILED) return group_grids_t<64, xtf32>(grids);
+  return group_grids_t<64, float>(grids);
 }
 
 template <int KP, typename XT>
@@ -1324,15 +1330,19 @@ static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st
   kg_advance<<<(unsigned)gr[GS_ADV], 64, 0, st>>>(t);
 }
 
-hipError_t group_iteration(int KP, int xbf16, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st) {
+hipError_t group_iteration(int KP, int xkind, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st) {
   if (KP == 32) {
-    if (xbf16)
+    if (xkind == XK_BF16)
       group_iteration_t<32, __bf16>(dtab, grids, st);
+    else if (xkind == XK_F32_TILED)
+      group_iteration_t<32, xtf32>(dtab, grids, st);
     else
       group_iteration_t<32, float>(dtab, grids, st);
   } else {
-    if (xbf16)
+    if (xkind == XK_BF16)
       group_iteration_t<64, __bf16>(dtab, grids, st);
+    else if (xkind == XK_F32_TILED)
+      group_iteration_t<64, xtf32>(dtab, grids, st);
     else
       group_iteration_t<64, float>(dtab, grids, st);
   }

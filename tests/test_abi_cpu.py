@@ -45,7 +45,7 @@ def test_default_opts_and_struct_layout():
     assert ctypes.sizeof(did.did_opts) == 40
     so = did.did_server_default_opts()
     assert (so.hbm_budget, so.max_active, so.max_iter, so.rel_tol) == (200 << 30, 64, 50, 1e-4)
-    assert ctypes.sizeof(did.did_server_opts) == 32
+    assert ctypes.sizeof(did.did_server_opts) == 40
 
 
 @pytest.mark.parametrize("M,N,K,msg", [

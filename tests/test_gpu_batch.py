@@ -16,17 +16,21 @@ from workloads import serving_x, to_f32_colmajor
 
 pytestmark = pytest.mark.gpu
 
-# (M, N, K, X storage): both K classes (K <= 32 and K > 32), both storages, ragged sizes
+TILED = "f32-tiled"  # float32 X kept in tile order (x_tiled = 1)
+
+# (M, N, K, X storage): both K classes (K <= 32 and K > 32), all three storages, ragged sizes
 SHAPES = [(300, 2000, 10, did.DID_F32), (777, 1500, 40, did.DID_F32), (130, 5000, 64, did.DID_F32),
           (64, 999, 7, did.DID_F32), (250, 3000, 20, did.DID_BF16), (97, 1234, 33, did.DID_BF16),
-          (3809, 2248, 49, did.DID_F32), (1868, 40000, 60, did.DID_F32)]
+          (3809, 2248, 49, did.DID_F32), (1868, 40000, 60, did.DID_F32), (500, 2500, 12, TILED),
+          (611, 3333, 50, TILED)]
 
 
 def _make(torch, M, N, K, xd, seed):
     X = to_f32_colmajor(serving_x(M, N, K, seed=seed))
     Xd = device_x(torch, X)
     o = did.did_default_opts()
-    o.x_dtype = xd
+    o.x_dtype = did.DID_BF16 if xd == did.DID_BF16 else did.DID_F32
+    o.x_tiled = 1 if xd == TILED else 0
     o.borrow_x = 1 if xd == did.DID_F32 else 0
     h = did.did_init_ex(Xd, M, N, K, 1000 + seed, o)
     return h, Xd
@@ -134,17 +138,21 @@ def test_batch_rejections():
         did.did_free(h)
 
 
-def test_server_results_equal_alone_and_budget_holds():
+@pytest.mark.parametrize("tiled", [0, 1])
+def test_server_results_equal_alone_and_budget_holds(tiled):
     """Jobs of uneven shape arrive over several steps; the budget admits about two at a
     time, so later jobs queue and are admitted as earlier ones retire and are released.
-    Every result equals the same job run alone for the same number of iterations, the
-    charged memory never exceeds the budget, and jobs are admitted first-in first-out."""
+    Every result equals the same job run alone (X column-major) for the same number of
+    iterations, also when the server keeps X in tile order; the charged memory never
+    exceeds the budget, and jobs are admitted first-in first-out."""
     torch = require_gpu()
     jobs = [(300, 2000, 10), (500, 1200, 40), (200, 4000, 64), (640, 900, 5), (128, 3000, 33), (350, 2500, 20)]
     o0 = did.did_default_opts()
     o0.borrow_x = 1
+    o0.x_tiled = tiled
     fp = [did.did_mem_estimate(M, N, K, o0) + 4 * M * N for M, N, K in jobs]
     so = did.did_server_default_opts()
+    so.x_tiled = tiled
     so.hbm_budget = int(max(fp) + sorted(fp)[-2])
     so.max_active = 4
     so.max_iter = 30
