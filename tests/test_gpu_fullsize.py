@@ -24,10 +24,11 @@ pytestmark = pytest.mark.gpu
 TOL_FACTORS = 1e-5
 
 
-def _run_one_iteration(torch, Xt, M, N, K, n_blocks):
+def _run_one_iteration(torch, Xt, M, N, K, n_blocks, tiled=0):
     o = did.did_default_opts()
     o.n_blocks = n_blocks
     o.borrow_x = 1
+    o.x_tiled = tiled
     h = did.did_init_ex(Xt, M, N, K, 12345, o)
     try:
         B0, C0 = read_factors(h, M, N, K)
@@ -67,8 +68,9 @@ def _check_b_rows_chunked(Xt, B0, C1, rows, chunk):
 
 
 def test_large_workload_full_size_sampled():
-    """M = 5000, N = 10^6, K = 50, 64 column blocks, X borrowed from the device: the
-    benchmark's workload and launch configuration."""
+    """M = 5000, N = 10^6, K = 50, 64 column blocks, X kept in tile order: the benchmark's
+    workload and launch configuration.  Sampled columns of C and rows of B against the
+    oracle; the whole of B and C bitwise against the same iteration on X read as given."""
     from workloads import large_halfnormal_device
 
     torch = require_gpu()
@@ -76,7 +78,13 @@ def test_large_workload_full_size_sampled():
     announce("full-size large workload, one iteration")
     Xt = large_halfnormal_device(torch, M=M, N=N, K=K, seed=3, n_blocks=64)
     torch.cuda.synchronize()
-    B0, C0, B1, C1 = _run_one_iteration(torch, Xt, M, N, K, 64)
+    B0, C0, B1, C1 = _run_one_iteration(torch, Xt, M, N, K, 64, tiled=1)
+    B0g, C0g, B1g, C1g = _run_one_iteration(torch, Xt, M, N, K, 64, tiled=0)
+    np.testing.assert_array_equal(B0, B0g)
+    np.testing.assert_array_equal(C0, C0g)
+    np.testing.assert_array_equal(B1, B1g)
+    np.testing.assert_array_equal(C1, C1g)
+    del B0g, C0g, B1g, C1g
     rng = np.random.default_rng(8)
     cols = sorted(set(rng.choice(N, 96, replace=False).tolist()) | {0, 1, 31, 32, 15624, 15625, N - 33, N - 1})
     ec = _check_c_columns(Xt, B0, C0, C1, cols)
