@@ -108,31 +108,13 @@ __device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b
 
 __device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-// X is stored either as float32 or as bf16 (the reduced-precision storage form); both load
-// paths return float32 (bf16 -> float32 is exact).
-__device__ __forceinline__ float ldx(const float* p) { return *p; }
-__device__ __forceinline__ float ldx(const __bf16* p) { return (float)*p; }
-// four consecutive elements; p is 16-byte (float) or 8-byte (bf16) aligned
-__device__ __forceinline__ f32x4 ldx4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
-__device__ __forceinline__ f32x4 ldx4(const __bf16* p) {
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  const u32x2 w = *reinterpret_cast<const u32x2*>(p);
-  f32x4 r;
-  r[0] = __builtin_bit_cast(float, w[0] << 16);
-  r[1] = __builtin_bit_cast(float, w[0] & 0xffff0000u);
-  r[2] = __builtin_bit_cast(float, w[1] << 16);
-  r[3] = __builtin_bit_cast(float, w[1] & 0xffff0000u);
-  return r;
-}
 __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
-// float32 X in tile order (the x_tiled option): a distinct element type selects the tiled
-// loads in the passes at compile time.  Its column-major loads exist only so that the
-// untaken branches compile.
+// Element types of X as the passes read it: float (column-major, as given), or one of the
+// two tiled storages (layout in did_kernels.h), bf16 or float32 (xtf32, a distinct type so
+// that the tiled loads are selected at compile time).
 struct xtf32 {
   float v;
 };
-__device__ __forceinline__ float ldx(const xtf32* p) { return p->v; }
-__device__ __forceinline__ f32x4 ldx4(const xtf32* p) { return *reinterpret_cast<const f32x4*>(p); }
 template <typename XT>
 struct x_is_tiled {
   static constexpr bool value = std::is_same<XT, __bf16>::value || std::is_same<XT, xtf32>::value;
@@ -527,28 +509,29 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
         return v;
       }
       return ld_tile(X + (T * nchunks + c) * 1024, l);
-    }
-    const int64_t m0 = c * 32;
-    if (tilefull && m0 + 32 <= M) {
+    } else {  // column-major float32 X
+      const int64_t m0 = c * 32;
+      if (tilefull && m0 + 32 <= M) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const XT* xb = xtile + m0 + 8 * q;  // wave-uniform base, 32-bit lane offset
-        const f32x4 t = ldx4(xb + loff);
-        v[4 * q + 0] = t[0];
-        v[4 * q + 1] = t[1];
-        v[4 * q + 2] = t[2];
-        v[4 * q + 3] = t[3];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t r = m0 + 8 * q + 4 * half + e;
-          v[4 * q + e] = (colok && r < M) ? ldx(xtile + (int64_t)lc * M + r) : 0.0f;
+        for (int q = 0; q < 4; ++q) {
+          const float* xb = xtile + m0 + 8 * q;  // wave-uniform base, 32-bit lane offset
+          const f32x4 t = *reinterpret_cast<const f32x4*>(xb + loff);
+          v[4 * q + 0] = t[0];
+          v[4 * q + 1] = t[1];
+          v[4 * q + 2] = t[2];
+          v[4 * q + 3] = t[3];
         }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t r = m0 + 8 * q + 4 * half + e;
+            v[4 * q + e] = (colok && r < M) ? xtile[(int64_t)lc * M + r] : 0.0f;
+          }
+      }
+      return v;
     }
-    return v;
   };
 
   // One chunk: compute chunk c from the X tile in xr (loaded one chunk earlier) and the
@@ -940,20 +923,21 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     f32x16 v;
     if constexpr (x_is_tiled<XT>::value) {  // tiled copy XR
       return ld_tile(X + ((active ? c : 0) * ((N + 31) / 32) + T) * 1024, l);
-    }
-    const int64_t j0 = T * 32;
-    const XT* xt = X + j0 * M;  // wave-uniform
-    if (rowsfull && j0 + 32 <= hi) {  // wave-uniform
+    } else {  // column-major float32 X
+      const int64_t j0 = T * 32;
+      const float* xt = X + j0 * M;  // wave-uniform
+      if (rowsfull && j0 + 32 <= hi) {  // wave-uniform
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = ldx(xt + (int64_t)(8 * (i >> 2) + (i & 3)) * M + loff);
-    } else {
+        for (int i = 0; i < 16; ++i) v[i] = xt[(int64_t)(8 * (i >> 2) + (i & 3)) * M + loff];
+      } else {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t j = j0 + row32(i, half);
-        v[i] = (rowok && j < hi) ? ldx(X + j * M + mrow) : 0.0f;
+        for (int i = 0; i < 16; ++i) {
+          const int64_t j = j0 + row32(i, half);
+          v[i] = (rowok && j < hi) ? X[j * M + mrow] : 0.0f;
+        }
       }
+      return v;
     }
-    return v;
   };
 
   // One tile: compute tile T from the X tile in xr (loaded one tile earlier) and the
