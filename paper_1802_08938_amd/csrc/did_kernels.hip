@@ -676,18 +676,32 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const __bf16*
 // with G_kk = 0 (zero column of B) is skipped.  The block's 256 columns of C (contiguous
 // in memory) are staged through LDS so that global loads and stores are coalesced, and
 // each updated column is repacked into Cq for the row pass and the next column pass.
-template <int KP>
+template <int KP, bool G_IN_LDS>
 __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float* __restrict__ C,
                                            f32x4* __restrict__ Cq, int64_t N, int K, const double* __restrict__ G,
                                            int64_t bid) {
-  __shared__ double Gs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
-  extern __shared__ float Ct[];             // the block's columns, stride K (256 * K floats)
+  // G = B^T B (KP x KP, both halves stored) is the same for every lane.  The single-instance
+  // kernel reads it directly: uniform addresses into memory the kernel does not write, which
+  // the compiler serves with scalar loads, so the FMAs below take G from scalar registers.
+  // The grouped kernels (whose pointers come from the descriptor table, after earlier work
+  // items stored to memory) stage its lower triangle in LDS instead.
+  __shared__ double Gs[G_IN_LDS ? KP * (KP + 1) / 2 : 1];  // lower triangle, row-major pairs
+  extern __shared__ float Ct[];                             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
-  for (int q = tid; q < KP * (KP + 1) / 2; q += 256) {
-    int a, b;
-    pair_of(q, a, b);
-    Gs[q] = G[a * KP + b];
+  if constexpr (G_IN_LDS) {
+    for (int q = tid; q < KP * (KP + 1) / 2; q += 256) {
+      int a, b;
+      pair_of(q, a, b);
+      Gs[q] = G[a * KP + b];
+    }
   }
+  // G[r][c] for r >= c
+  auto gl = [&](int r, int c) -> double {
+    if constexpr (G_IN_LDS)
+      return Gs[r * (r + 1) / 2 + c];
+    else
+      return G[c * KP + r];  // row c of the symmetric G: contiguous in r
+  };
 
   const int64_t j0 = bid * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
@@ -703,7 +717,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (k < K) {
-        const double nk = Gs[k * (k + 1) / 2 + k];
+        const double nk = gl(k, k);
         if (nk > 0.0) {
           const double cold = (double)cl[k];
           double cn = cold + h[k] / nk;
@@ -711,7 +725,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
           const double d = cn - cold;
           cl[k] = (float)cn;
 #pragma unroll
-          for (int q = k + 1; q < KP; ++q) h[q] -= Gs[q * (q + 1) / 2 + k] * d;
+          for (int q = k + 1; q < KP; ++q) h[q] -= gl(q, k) * d;
         }
       }
     }
@@ -725,7 +739,7 @@ template <int KP>
 __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
                                                f32x4* __restrict__ Cq, int64_t N, int K,
                                                const double* __restrict__ G) {
-  sweep_body<KP>(Hin, C, Cq, N, K, G, blockIdx.x);
+  sweep_body<KP, false>(Hin, C, Cq, N, K, G, blockIdx.x);
 }
 
 hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st) {
@@ -1190,7 +1204,7 @@ __global__ __launch_bounds__(256) void kg_reduce_f(const GTable* __restrict__ g)
 template <int KP>
 __global__ __launch_bounds__(256) void kg_sweep(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_SWEEP)
-  sweep_body<KP>(d.H, d.C, static_cast<f32x4*>(d.Cq), d.N, d.K, d.G, bid);
+  sweep_body<KP, true>(d.H, d.C, static_cast<f32x4*>(d.Cq), d.N, d.K, d.G, bid);
   DID_GROUP_END
 }
 
