@@ -356,51 +356,65 @@ __device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, 
   }
 }
 
-constexpr int kBupRows = 64;  // rows of B per block
+constexpr int kBupRows = 64;      // rows of B per block (one thread each for the update)
+constexpr int kBupThreads = 256;  // threads per block (all of them form the G partial)
 
-template <int KP>
+template <int KP, bool V_IN_LDS>
 __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
                                              int64_t Mpad, const double* __restrict__ V, __bf16* __restrict__ BqE,
                                              __bf16* __restrict__ BqH, double* __restrict__ Gpart, int update,
                                              int64_t bid) {
-  __shared__ double Vs[KP * KP];
+  // V is the same for every row.  The single-instance kernel reads it with uniform loads,
+  // which the compiler serves from scalar registers; the grouped kernels (pointers from the
+  // descriptor table) stage it in LDS.
+  __shared__ double Vs[V_IN_LDS ? KP * KP : 1];
   __shared__ float Bt[kBupRows * (KP + 1)];
   const int tid = threadIdx.x;
-  if (update)
-    for (int q = tid; q < KP * KP; q += kBupRows) Vs[q] = V[q];
+  if constexpr (V_IN_LDS) {
+    if (update)
+      for (int q = tid; q < KP * KP; q += kBupThreads) Vs[q] = V[q];
+  }
+  auto vv = [&](int a, int b) -> double {
+    if constexpr (V_IN_LDS)
+      return Vs[a * KP + b];
+    else
+      return V[a * KP + b];
+  };
   __syncthreads();
   const int64_t m = bid * kBupRows + tid;
   const bool ok = m < M;
-  double db[KP];
+  if (tid < kBupRows) {  // the row update, one thread per row of B
+    double db[KP];
 #pragma unroll
-  for (int i = 0; i < KP; ++i) {
-    db[i] = 0.0;
-    float bnew = 0.0f;
-    if (i < K && ok) {
-      const double bold = (double)B[(int64_t)i * M + m];
-      double bn = bold;
-      if (update) {
-        const double vii = Vs[i * KP + i];
-        if (vii > 0.0) {
-          double s = W[(int64_t)i * Mpad + m];
+    for (int i = 0; i < KP; ++i) {
+      db[i] = 0.0;
+      float bnew = 0.0f;
+      if (i < K && ok) {
+        const double bold = (double)B[(int64_t)i * M + m];
+        double bn = bold;
+        if (update) {
+          const double vii = vv(i, i);
+          if (vii > 0.0) {
+            double s = W[(int64_t)i * Mpad + m];
 #pragma unroll
-          for (int k = 0; k < KP; ++k)
-            if (k < i) s -= Vs[i * KP + k] * db[k];
-          bn = bold + s / vii;
-          bn = bn > 0.0 ? bn : 0.0;
+            for (int k = 0; k < KP; ++k)
+              if (k < i) s -= vv(i, k) * db[k];
+            bn = bold + s / vii;
+            bn = bn > 0.0 ? bn : 0.0;
+          }
+          db[i] = bn - bold;
         }
-        db[i] = bn - bold;
+        bnew = (float)bn;
+        if (update) B[(int64_t)i * M + m] = bnew;
+        pack_entry<KP>(BqE, BqH, m, i, bnew);
       }
-      bnew = (float)bn;
-      if (update) B[(int64_t)i * M + m] = bnew;
-      pack_entry<KP>(BqE, BqH, m, i, bnew);
+      Bt[tid * (KP + 1) + i] = bnew;
     }
-    Bt[tid * (KP + 1) + i] = bnew;
   }
   __syncthreads();
   // Partial of G = B^T B over this block's rows, float64, pairs (a >= b).
   constexpr int NP = KP * (KP + 1) / 2;
-  for (int q = tid; q < NP; q += kBupRows) {
+  for (int q = tid; q < NP; q += kBupThreads) {
     int a, b;
     pair_of(q, a, b);
     double s0 = 0.0, s1 = 0.0;
@@ -413,12 +427,12 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
 }
 
 template <int KP>
-__global__ __launch_bounds__(kBupRows) void k_bupdate(float* __restrict__ B, int64_t M, int K,
+__global__ __launch_bounds__(kBupThreads) void k_bupdate(float* __restrict__ B, int64_t M, int K,
                                                  const double* __restrict__ W, int64_t Mpad,
                                                  const double* __restrict__ V, __bf16* __restrict__ BqE,
                                                  __bf16* __restrict__ BqH, double* __restrict__ Gpart,
                                                  int update) {
-  bupdate_body<KP>(B, M, K, W, Mpad, V, BqE, BqH, Gpart, update, blockIdx.x);
+  bupdate_body<KP, false>(B, M, K, W, Mpad, V, BqE, BqH, Gpart, update, blockIdx.x);
 }
 
 int bupdate_blocks(const Shape& s) { return (int)((s.M + kBupRows - 1) / kBupRows); }
@@ -427,9 +441,9 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
                    double* Gpart, int update, hipStream_t st) {
   const unsigned g = (unsigned)bupdate_blocks(s);
   if (s.KP == 32)
-    k_bupdate<32><<<g, kBupRows, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
+    k_bupdate<32><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
   else
-    k_bupdate<64><<<g, kBupRows, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
+    k_bupdate<64><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
   return hipGetLastError();
 }
 
@@ -1238,9 +1252,9 @@ __global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g)
 }
 
 template <int KP>
-__global__ __launch_bounds__(kBupRows) void kg_bupdate(const GTable* __restrict__ g) {
+__global__ __launch_bounds__(kBupThreads) void kg_bupdate(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_BUP)
-  bupdate_body<KP>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.BqE, d.BqH, d.Gpart, 1, bid);
+  bupdate_body<KP, true>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.BqE, d.BqH, d.Gpart, 1, bid);
   DID_GROUP_END
 }
 
@@ -1297,7 +1311,7 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
   if ((e = occ((const void*)kg_reduce_v<KP>, 256, 0, &grids[GS_REDV])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_rowpass<KP, XT>, 256, 0, &grids[GS_ROW])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_w<KP>, 256, 0, &grids[GS_REDW])) != hipSuccess) return e;
-  if ((e = occ((const void*)kg_bupdate<KP>, kBupRows, 0, &grids[GS_BUP])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_bupdate<KP>, kBupThreads, 0, &grids[GS_BUP])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_g<KP>, 256, 0, &grids[GS_REDG])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_advance, 64, 0, &grids[GS_ADV])) != hipSuccess) return e;
   return hipSuccess;
@@ -1323,7 +1337,7 @@ static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st
   kg_reduce_v<KP><<<(unsigned)gr[GS_REDV], 256, 0, st>>>(t);
   kg_rowpass<KP, XT><<<(unsigned)gr[GS_ROW], 256, 0, st>>>(t);
   kg_reduce_w<KP><<<(unsigned)gr[GS_REDW], 256, 0, st>>>(t);
-  kg_bupdate<KP><<<(unsigned)gr[GS_BUP], kBupRows, 0, st>>>(t);
+  kg_bupdate<KP><<<(unsigned)gr[GS_BUP], kBupThreads, 0, st>>>(t);
   kg_reduce_g<KP><<<(unsigned)gr[GS_REDG], 256, 0, st>>>(t);
   kg_advance<<<(unsigned)gr[GS_ADV], 64, 0, st>>>(t);
 }
