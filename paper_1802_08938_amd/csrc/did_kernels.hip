@@ -367,16 +367,21 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   // V is the same for every row.  The single-instance kernel reads it with uniform loads,
   // which the compiler serves from scalar registers; the grouped kernels (pointers from the
   // descriptor table) stage it in LDS.
-  __shared__ double Vs[V_IN_LDS ? KP * KP : 1];
+  __shared__ double Vs[V_IN_LDS ? KP * (KP + 1) / 2 : 1];  // lower triangle, row-major pairs
   __shared__ float Bt[kBupRows * (KP + 1)];
+  __shared__ double dbs[KP * kBupRows];  // delta b of the block's rows, [i][row]
   const int tid = threadIdx.x;
   if constexpr (V_IN_LDS) {
     if (update)
-      for (int q = tid; q < KP * KP; q += kBupThreads) Vs[q] = V[q];
+      for (int q = tid; q < KP * (KP + 1) / 2; q += kBupThreads) {
+        int a, b;
+        pair_of(q, a, b);
+        Vs[q] = V[a * KP + b];
+      }
   }
-  auto vv = [&](int a, int b) -> double {
+  auto vv = [&](int a, int b) -> double {  // V[a][b] for a >= b
     if constexpr (V_IN_LDS)
-      return Vs[a * KP + b];
+      return Vs[a * (a + 1) / 2 + b];
     else
       return V[a * KP + b];
   };
@@ -384,10 +389,10 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   const int64_t m = bid * kBupRows + tid;
   const bool ok = m < M;
   if (tid < kBupRows) {  // the row update, one thread per row of B
-    double db[KP];
+    double* db = dbs + tid;  // db[i * kBupRows]: in LDS, as a private array would go to scratch
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
-      db[i] = 0.0;
+      db[i * kBupRows] = 0.0;
       float bnew = 0.0f;
       if (i < K && ok) {
         const double bold = (double)B[(int64_t)i * M + m];
@@ -398,11 +403,11 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
             double s = W[(int64_t)i * Mpad + m];
 #pragma unroll
             for (int k = 0; k < KP; ++k)
-              if (k < i) s -= vv(i, k) * db[k];
+              if (k < i) s -= vv(i, k) * db[k * kBupRows];
             bn = bold + s / vii;
             bn = bn > 0.0 ? bn : 0.0;
           }
-          db[i] = bn - bold;
+          db[i * kBupRows] = bn - bold;
         }
         bnew = (float)bn;
         if (update) B[(int64_t)i * M + m] = bnew;
