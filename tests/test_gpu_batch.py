@@ -220,6 +220,11 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
 
 def test_server_rejects_oversized_and_thin_jobs():
     torch = require_gpu()
+    bad = did.did_server_default_opts()
+    bad.x_tiled = 2
+    with pytest.raises(did.DidError) as ei:
+        did.did_server_create(bad)
+    assert ei.value.code == did.DID_EINVAL
     so = did.did_server_default_opts()
     so.hbm_budget = 1 << 20
     s = did.did_server_create(so)
