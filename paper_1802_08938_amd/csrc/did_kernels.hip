@@ -703,21 +703,22 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
   // kernel reads it directly: uniform addresses into memory the kernel does not write, which
   // the compiler serves with scalar loads, so the FMAs below take G from scalar registers.
   // The grouped kernels (whose pointers come from the descriptor table, after earlier work
-  // items stored to memory) stage its lower triangle in LDS instead.
-  __shared__ double Gs[G_IN_LDS ? KP * (KP + 1) / 2 : 1];  // lower triangle, row-major pairs
+  // items stored to memory) stage its strictly lower triangle in LDS instead and read the
+  // diagonal from memory: without the diagonal, two blocks of the K > 32 class fit per CU.
+  __shared__ double Gs[G_IN_LDS ? KP * (KP - 1) / 2 : 1];  // strictly lower triangle, rows r >= 1
   extern __shared__ float Ct[];                             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
   if constexpr (G_IN_LDS) {
-    for (int q = tid; q < KP * (KP + 1) / 2; q += 256) {
+    for (int q = tid; q < KP * (KP - 1) / 2; q += 256) {
       int a, b;
-      pair_of(q, a, b);
-      Gs[q] = G[a * KP + b];
+      pair_of(q, a, b);  // a >= b; entry (a + 1, b) of G
+      Gs[q] = G[(a + 1) * KP + b];
     }
   }
-  // G[r][c] for r >= c
+  // G[r][c] for r > c
   auto gl = [&](int r, int c) -> double {
     if constexpr (G_IN_LDS)
-      return Gs[r * (r + 1) / 2 + c];
+      return Gs[(r - 1) * r / 2 + c];
     else
       return G[c * KP + r];  // row c of the symmetric G: contiguous in r
   };
@@ -736,7 +737,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (k < K) {
-        const double nk = gl(k, k);
+        const double nk = G[k * KP + k];
         if (nk > 0.0) {
           const double cold = (double)cl[k];
           double cn = cold + h[k] / nk;
