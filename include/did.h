@@ -199,7 +199,8 @@ int did_mem_bytes(did_handle h, int64_t* bytes);
 
 /* Device bytes did_init_ex would allocate for an (M, N, K) instance with these options
  * (opts may be NULL); x_on_device = 1 when X will be passed as a device pointer (then
- * borrow_x = 1 allocates no copy of it).  Sizes are validated as did_init_ex does. */
+ * borrow_x = 1 allocates no copy of it; the tiled storages, DID_BF16 or x_tiled = 1,
+ * always allocate their two copies).  Sizes are validated as did_init_ex does. */
 int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int32_t x_on_device,
                      int64_t* bytes);
 
