@@ -199,14 +199,20 @@ def test_rejects_negative_and_nonfinite_x():
         assert ei.value.code == did.DID_EINVAL
 
 
-def test_host_pointer_x_matches_device_pointer():
+@pytest.mark.parametrize("storage", ["f32", "f32-tiled", "bf16"])
+def test_host_pointer_x_matches_device_pointer(storage):
+    """X in host memory is uploaded (and, for the tiled storages, tiled from a temporary
+    upload); the iterates equal those from the same X on the device."""
     torch = require_gpu()
     rng = np.random.default_rng(4)
     X32 = to_f32_colmajor(rng.random((64, 96)))
-    announce("host vs device X")
-    hd = did.did_init(device_x(torch, X32), 64, 96, 5, 7)
+    o = did.did_default_opts()
+    o.x_tiled = 1 if storage == "f32-tiled" else 0
+    o.x_dtype = did.DID_BF16 if storage == "bf16" else did.DID_F32
+    announce(f"host vs device X ({storage})")
+    hd = did.did_init_ex(device_x(torch, X32), 64, 96, 5, 7, o)
     Xh = np.ascontiguousarray(X32.T)  # host memory, column-major X
-    hh = did.did_init(Xh, 64, 96, 5, 7)
+    hh = did.did_init_ex(Xh, 64, 96, 5, 7, o)
     try:
         did.did_iterate(hd, 3)
         did.did_iterate(hh, 3)
@@ -246,14 +252,17 @@ def test_block_count_only_changes_rounding():
         assert rel_fro(r[5][1], res[0][5][1]) <= 1e-5
 
 
-def test_resume_from_factors_equals_uninterrupted():
+@pytest.mark.parametrize("tiled", [0, 1])
+def test_resume_from_factors_equals_uninterrupted(tiled):
     torch = require_gpu()
     X, _, _ = planted_lowrank(150, 900, 6, seed=17)
     X32 = to_f32_colmajor(X)
-    announce("resume")
-    full = run_gpu(torch, X32, 6, iters=(4, 8))
+    announce(f"resume (x_tiled={tiled})")
+    o = did.did_default_opts()
+    o.x_tiled = tiled
+    full = run_gpu(torch, X32, 6, iters=(4, 8), opts=o)
     B4, C4 = full[4]
-    resumed = run_gpu(torch, X32, 6, iters=(4,), B0=B4.astype(np.float32), C0=C4.astype(np.float32))
+    resumed = run_gpu(torch, X32, 6, iters=(4,), opts=o, B0=B4.astype(np.float32), C0=C4.astype(np.float32))
     np.testing.assert_array_equal(resumed[4][0], full[8][0])
     np.testing.assert_array_equal(resumed[4][1], full[8][1])
 
