@@ -512,7 +512,7 @@ def run_serve(args, torch, did):
     so.max_active = args.serve_slots
     so.max_iter = 50
     so.rel_tol = 1e-4
-    so.x_tiled = 0 if args.x_given else 1  # float32 jobs keep X in tile order
+    so.x_tiled = 1 if args.serve_tiled else 0  # float32 jobs keep X in tile order
     stream = torch.cuda.Stream()
     so.stream = stream.cuda_stream
     srv = did.did_server_create(so)
@@ -586,7 +586,7 @@ def run_serve(args, torch, did):
         "data": "synthetic",
         "config": {"workload": cfg["desc"] + ("; X stored as bf16" if args.serve_bf16 else ""), "jobs": n_jobs,
                    "slots": so.max_active, "x_storage": "bf16" if args.serve_bf16 else "f32",
-                   "x_layout": "tile order" if (args.serve_bf16 or not args.x_given) else "as given (column-major)"},
+                   "x_layout": "tile order" if (args.serve_bf16 or args.serve_tiled) else "as given (column-major)"},
         "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "latency_mean_s": round(float(lat.mean()), 4),
@@ -616,6 +616,8 @@ def main():
     ap.add_argument("--serve-bf16", action="store_true", help="serve workload: store each job's X as bf16")
     ap.add_argument("--x-given", action="store_true",
                     help="float32 X read as given (column-major) instead of kept in tile order")
+    ap.add_argument("--serve-tiled", action="store_true",
+                    help="serve workload: float32 jobs keep X in tile order (more memory per job)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the DID engine here is single-GPU "
