@@ -27,8 +27,13 @@ and p50/p99 latency from the scheduled arrival to retirement.  ``--workload nswe
 the large workload's recipe at N = 1.25e5 ... 1e6 (the method's cost per iteration is
 linear in N) and reports the time per iteration and per 10^5 columns at each size.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+The engine keeps float32 X in 32x32 tile order (one copy per pass, made at init) for the
+MFMA-path workloads and the batch; --x-given reads it as given (column-major) instead.
+The serve workload reads it as given unless --serve-tiled is passed.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--x-given]
                        [--workload large|large_bf16|image|planted|nsweep|paper|batch|serve]
+                       [--serve-jobs J] [--serve-slots S] [--serve-bf16] [--serve-tiled]
 """
 
 from __future__ import annotations
