@@ -522,12 +522,17 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   auto xload = [&](int64_t c) {
     f32x16 v;
     if constexpr (x_is_tiled<XT>::value) {  // tiled copy XC
-      if (!tileok) {  // a wave past the last tile: E = 0, so it adds nothing to f
+      // A wave past the last tile either loads zeros (float32) or reads tile 0, in bounds
+      // (bf16); either way its f partial is dropped and its H stores are masked by
+      // col < N.  Each form is the faster one for its storage (measured).
+      if constexpr (std::is_same<XT, xtf32>::value) {
+        if (!tileok) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = 0.0f;
-        return v;
+          for (int i = 0; i < 16; ++i) v[i] = 0.0f;
+          return v;
+        }
       }
-      return ld_tile(X + (T * nchunks + c) * 1024, l);
+      return ld_tile(X + ((tileok ? T : 0) * nchunks + c) * 1024, l);
     } else {  // column-major float32 X
       const int64_t m0 = c * 32;
       if (tilefull && m0 + 32 <= M) {
@@ -640,6 +645,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   }
 
   double fsum = fs0 + fs1;
+  if (!tileok) fsum = 0.0;  // a wave past the last tile
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
   if (l == 0) fw[wave] = fsum;
