@@ -138,3 +138,16 @@ def test_batch_and_server_null_arguments():
     h = ctypes.c_void_p()
     assert L.did_server_create(ctypes.byref(so), ctypes.byref(h)) == did.DID_EINVAL
     assert "server options" in did.did_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; --gpus N with N > 1 exits with a message (checked
+    before anything touches a device)."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
