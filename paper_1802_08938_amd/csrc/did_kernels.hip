@@ -1124,18 +1124,34 @@ hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipS
   return hipGetLastError();
 }
 
-// full[a][b] = full[b][a] = sum_p part[p][pair(a,b)], p ascending (blocks of 256 pairs).
+// full[a][b] = full[b][a] = sum_p part[p][pair(a,b)] in a fixed order.  A block of 256
+// threads takes kSymPairs consecutive pairs with 32 threads each: thread (t, qi) =
+// (tid / 8, tid % 8) adds the partials p = t, t + 32, t + 64, ... in turn, then the 32
+// sums of a pair are combined by a fixed tree (xor shuffles within each wave, then the
+// four waves in order).  Every thread reaches the barrier.
+constexpr int kSymPairs = 8;
 __device__ __forceinline__ void reduce_sym_body(const double* __restrict__ part, int64_t P, int KP,
                                                 double* __restrict__ full, int64_t bid) {
+  __shared__ double ws[4][kSymPairs];
   const int NP = KP * (KP + 1) / 2;
-  const int q = (int)bid * 256 + (int)threadIdx.x;
-  if (q >= NP) return;
+  const int tid = threadIdx.x, qi = tid & (kSymPairs - 1), t = tid / kSymPairs, wave = tid >> 6;
+  const int q = (int)bid * kSymPairs + qi;
   double s = 0.0;
-  for (int64_t p = 0; p < P; ++p) s += part[p * NP + q];
-  int a, b;
-  pair_of(q, a, b);
-  full[a * KP + b] = s;
-  full[b * KP + a] = s;
+  if (q < NP)
+    for (int64_t p = t; p < P; p += 256 / kSymPairs) s += part[p * NP + q];
+  // lanes qi + 8 t' of a wave (t' = t % 8) hold the same pair
+  s += __shfl_xor(s, 8, 64);
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  if ((tid & 63) < kSymPairs) ws[wave][qi] = s;
+  __syncthreads();
+  if (tid < kSymPairs && q < NP) {
+    const double v = (ws[0][qi] + ws[1][qi]) + (ws[2][qi] + ws[3][qi]);
+    int a, b;
+    pair_of(q, a, b);
+    full[a * KP + b] = v;
+    full[b * KP + a] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_sym(const double* __restrict__ part, int64_t P, int KP,
@@ -1145,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_reduce_sym(const double* __restrict__ p
 
 hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st) {
   const int NP = KP * (KP + 1) / 2;
-  k_reduce_sym<<<(unsigned)((NP + 255) / 256), 256, 0, st>>>(part, P, KP, full);
+  k_reduce_sym<<<(unsigned)((NP + kSymPairs - 1) / kSymPairs), 256, 0, st>>>(part, P, KP, full);
   return hipGetLastError();
 }
 
@@ -1295,11 +1311,11 @@ void ginst_items(const Shape& s, int R, int64_t items[GS_N]) {
   items[GS_REDF] = 1;
   items[GS_SWEEP] = (s.N + 255) / 256;
   items[GS_VGRAM] = vgram_blocks(s);
-  items[GS_REDV] = (np + 255) / 256;
+  items[GS_REDV] = (np + kSymPairs - 1) / kSymPairs;
   items[GS_ROW] = nsg * R8;
   items[GS_REDW] = ((int64_t)s.KP * s.Mpad + 255) / 256;
   items[GS_BUP] = bupdate_blocks(s);
-  items[GS_REDG] = (np + 255) / 256;
+  items[GS_REDG] = (np + kSymPairs - 1) / kSymPairs;
   items[GS_ADV] = 1;
 }
 
