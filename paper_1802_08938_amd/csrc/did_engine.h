@@ -17,6 +17,10 @@ struct did_ctx {
   int dev = 0;
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // MFMA path: a second stream on which the V partials and their reduction run while the
+  // row pass runs on st (both only read the packed C); ev_c: C packed, ev_v: V reduced
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_c = nullptr, ev_v = nullptr;
   didk::Shape s{};
   bool own_x = true;
   void* X = nullptr;   // float32 (column-major), or the column-pass tiled bf16 copy (s.xbf16)

@@ -106,7 +106,11 @@ void release(did_ctx* h) {
   if (!h) return;
   DeviceGuard g(h->dev);
   if (h->st) (void)hipStreamSynchronize(h->st);
+  if (h->st2) (void)hipStreamSynchronize(h->st2);
   for (hipEvent_t ev : h->prof_events) (void)hipEventDestroy(ev);
+  if (h->ev_c) (void)hipEventDestroy(h->ev_c);
+  if (h->ev_v) (void)hipEventDestroy(h->ev_v);
+  if (h->st2) (void)hipStreamDestroy(h->st2);
   h->prof_events.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
@@ -299,6 +303,10 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     unsigned char* cq = nullptr;
     if ((rc = dalloc(h, &cq, didk::cq_bytes(s)))) return rc;
     h->Cq = cq;
+    if ((e = hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->ev_c, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->ev_v, hipEventDisableTiming)) != hipSuccess)
+      return dev_fail(h, e, "second stream");
     if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
     if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
     if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
@@ -559,16 +567,22 @@ int did_iterate(did_handle h, int32_t n) {
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
     if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
-    if ((e = didk::vgram(s, h->Cq, h->Vpart, h->st)) != hipSuccess) return dev_fail(h, e, "V partials");
-    DID_MARK(3);
-    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st)) != hipSuccess)
+    // V = tril(C'C'^T) on the second stream, overlapped with the row pass and the W
+    // reduction; the B update waits for it
+    if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess || (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
+      return dev_fail(h, e, "stream order");
+    if ((e = didk::vgram(s, h->Cq, h->Vpart, h->st2)) != hipSuccess) return dev_fail(h, e, "V partials");
+    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st2)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
+    if ((e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
+    DID_MARK(3);
     DID_MARK(4);
     if ((e = didk::rowpass(s, h->XR, h->Cq, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
     DID_MARK(6);
+    if ((e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
     if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "B update");
     DID_MARK(7);
