@@ -117,8 +117,8 @@ void fill_inst(GInst& d, did_ctx* h, double* fcur) {
   d.B = h->B;
   d.C = h->C;
   d.Cq = h->Cq;
-  d.BqE = h->BqE;
-  d.BqH = h->BqH;
+  d.Bq = h->Bq;
+  d.Bsc = h->Bsc;
   d.H = h->H;
   d.fpart = h->fpart;
   d.G = h->G;

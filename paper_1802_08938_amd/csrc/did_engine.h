@@ -27,8 +27,8 @@ struct did_ctx {
   void* XR = nullptr;  // X as the row pass reads it: X itself, or the row-pass tiled bf16 copy
   float* B = nullptr;
   float* C = nullptr;
-  __bf16* BqE = nullptr;
-  __bf16* BqH = nullptr;
+  _Float16* Bq = nullptr;  // B packed as MFMA operands (layout in did_kernels.h)
+  float* Bsc = nullptr;     // column scales of the packed B
   double* G = nullptr;
   double* Gpart = nullptr;
   double* V = nullptr;

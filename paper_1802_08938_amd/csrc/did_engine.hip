@@ -195,7 +195,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
     t += b(2 * didk::tiled_x_elems(s) * (s.xbf16 ? 2 : 4));
   else if (x_copied)
     t += b(M * N * 4);
-  t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(KP * KP * 8) +
+  t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(didk::bsc_floats(s.KP) * 4) + b(KP * KP * 8) +
        b((int64_t)didk::bupdate_blocks(s) * NP * 8) + b(KP * KP * 8) + b(KP * s.Mpad * 8);
   if (s.thin) {
     t += b(didk::thin_blocks(s) * didk::thin_slots(16, 4) * 8);
@@ -289,8 +289,8 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   h->R = (int)rb.size() - 1;
   if ((rc = dalloc(h, &h->B, M * K))) return rc;
   if ((rc = dalloc(h, &h->C, (int64_t)K * N))) return rc;
-  if ((rc = dalloc(h, &h->BqE, didk::packed_b_elems(s)))) return rc;
-  h->BqH = h->BqE + (int64_t)didk::bq_units_e(s.KP) * 8;  // H-order units of chunk 0
+  if ((rc = dalloc(h, &h->Bq, didk::packed_b_elems(s)))) return rc;
+  if ((rc = dalloc(h, &h->Bsc, didk::bsc_floats(s.KP)))) return rc;
   if ((rc = dalloc(h, &h->G, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->Gpart, (int64_t)didk::bupdate_blocks(s) * NP))) return rc;
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
@@ -315,7 +315,8 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
   if ((rc = dalloc(h, &h->tdev, 1))) return rc;
 
-  if ((e = hipMemsetAsync(h->BqE, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
+  if ((e = hipMemsetAsync(h->Bq, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
+      (e = hipMemsetAsync(h->Bsc, 0, (size_t)didk::bsc_floats(s.KP) * 4, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->W, 0, (size_t)s.KP * s.Mpad * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
@@ -331,7 +332,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
 
 // Pack B and form G = B^T B.
 hipError_t refresh_b_derived(did_ctx* h) {
-  hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st);
+  hipError_t e = didk::bupdate(h->s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 0, h->st);
   if (e != hipSuccess) return e;
   return didk::reduce_sym(h->Gpart, didk::bupdate_blocks(h->s), h->s.KP, h->G, h->st);
 }
@@ -345,7 +346,7 @@ int objective_pass(did_ctx* h) {
       return dev_fail(h, e, "objective pass");
     return DID_OK;
   }
-  if ((e = didk::colpass(h->s, h->X, h->Cq, h->BqE, h->BqH, h->H, h->fpart, 0, h->st)) != hipSuccess)
+  if ((e = didk::colpass(h->s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 0, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective pass");
   if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(h->s), h->fobj, 0.5, h->st)) != hipSuccess)
     return dev_fail(h, e, "objective reduce");
@@ -521,13 +522,13 @@ static int iterate_thin(did_ctx* h, int32_t n) {
     for (int q = 2; q <= 6; ++q)
       if ((e = mark(q)) != hipSuccess) return dev_fail(h, e, "profile record");
     if (mode == 0) {
-      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
+      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st)) != hipSuccess)
         return dev_fail(h, e, "B update");
     } else {
       for (int i = 0; i < s.K; ++i)
         if ((e = didk::dbcd_b_step(s, X, h->B, h->C, h->tpart, h->W, i, h->st)) != hipSuccess)
           return dev_fail(h, e, "DBCD B step");
-      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 0, h->st)) != hipSuccess)
+      if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 0, h->st)) != hipSuccess)
         return dev_fail(h, e, "pack B");
     }
     if ((e = mark(7)) != hipSuccess) return dev_fail(h, e, "profile record");
@@ -559,7 +560,7 @@ int did_iterate(did_handle h, int32_t n) {
 #define DID_MARK(q) \
   if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
     DID_MARK(0);
-    if ((e = didk::colpass(s, h->X, h->Cq, h->BqE, h->BqH, h->H, h->fpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "column pass");
     DID_MARK(1);
     if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
@@ -577,13 +578,13 @@ int did_iterate(did_handle h, int32_t n) {
     if ((e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
     DID_MARK(3);
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->XR, h->Cq, h->BqE, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
     DID_MARK(6);
     if ((e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
-    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->BqE, h->BqH, h->Gpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st)) != hipSuccess)
       return dev_fail(h, e, "B update");
     DID_MARK(7);
     if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)

@@ -20,23 +20,30 @@ struct Shape {
   int64_t thin_grid; // thin path: blocks per launch (one wave of resident blocks)
 };
 
-// Packed B: per 32-row chunk, the bf16 pieces of B in the two MFMA operand orders as
-// 16-byte units, E order (KP/16 * 3 * 64 units) then H order (KP/32 * 2 * 3 * 64 units, the
-// same count), so that one chunk's operands are one contiguous run of 2 * bq_units_e units.
-inline int bq_units_e(int KP) { return (KP / 16) * 3 * 64; }
-inline int bq_units_chunk(int KP) { return 2 * bq_units_e(KP); }
-// bf16 entries of the packed B buffer
+// Packed B: per 32-row chunk, B in the two MFMA operand orders as 16-byte units of eight
+// fp16 values, E order (KP/16 * 2 * 64 units: two pieces of -B scaled per row) then H order
+// (KP/32 * 2 * 2 * 64 units, the same count: two pieces of B scaled per column), then 8
+// units holding the chunk's 32 row scales as float32, so that one chunk's operands are
+// one contiguous run of bq_units_chunk units.
+inline int bq_units_e(int KP) { return (KP / 16) * 2 * 64; }
+inline int bq_units_chunk(int KP) { return 2 * bq_units_e(KP) + 8; }
+// fp16 entries of the packed B buffer
 inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)bq_units_chunk(s.KP) * 8; }
 inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
 
-// Packed C: per 32-column tile, the bf16 pieces of C in the two MFMA operand orders, as
-// 16-byte units: E order (KP/16 * 3 * 64 units) then W order (KP/32 * 2 * 3 * 64 units).
-inline int cq_units_e(int KP) { return (KP / 16) * 3 * 64; }
+// Packed C: per 32-column tile, C in the two MFMA operand orders, as 16-byte units: E order
+// (KP/16 * 2 * 64 units of fp16 pieces of C scaled per column, then 8 units holding the
+// tile's 32 inverse column scales as float32) and W order (KP/32 * 2 * 3 * 64 units of bf16
+// pieces).
+inline int cq_units_e(int KP) { return (KP / 16) * 2 * 64 + 8; }
 inline int cq_units_w(int KP) { return (KP / 32) * 2 * 3 * 64; }
 inline int cq_units(int KP) { return cq_units_e(KP) + cq_units_w(KP); }
 inline int64_t n_tiles32(const Shape& s) { return (s.N + 31) / 32; }
 // bytes of the packed C buffer
 inline int64_t cq_bytes(const Shape& s) { return n_tiles32(s) * cq_units(s.KP) * 16; }
+// Column scales of B for the H-order operands: floats [0, KP) hold the column maxima
+// (gathered during the B update), [KP, 2 KP) the inverse scales 2^-u_k.
+inline int bsc_floats(int KP) { return 2 * KP; }
 
 // splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
@@ -69,19 +76,18 @@ inline int64_t tiled_x_elems(const Shape& s) { return s.nchunks * n_tiles(s) * 1
 hipError_t tile_x(const Shape& s, const float* src, void* xc, void* xr, hipStream_t st);
 hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 
-// Pack B (three bf16 pieces per entry) into MFMA operand order (Bq: the E-order units of
-// each chunk at BqE, its H-order units at BqH = BqE + bq_units_e units, chunk stride
-// bq_units_chunk units), optionally applying the incremental B update from the
-// reduced messages W (KP x Mpad, float64) and V (KP x KP, float64); writes per-block
-// partials of B^T B into Gpart (n_pairs(KP) doubles per block).  Grid: ceil(M/256).
-hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, __bf16* BqE,
-                   __bf16* BqH, double* Gpart, int update, hipStream_t st);
+// Pack B into MFMA operand order (Bq, layout above; Bsc: its column scales), optionally
+// applying the incremental B update from the reduced messages W (KP x Mpad, float64) and V
+// (KP x KP, float64) first; writes per-block partials of B^T B into Gpart (n_pairs(KP)
+// doubles per block).  The thin path packs nothing (Bq and Bsc may be null there).
+hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _Float16* Bq, float* Bsc,
+                   double* Gpart, int update, hipStream_t st);
 int bupdate_blocks(const Shape& s);
 
 // Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
 // (with_h = 1) H = B^T E written as KP x N floats, row kk contiguous (index kk * N + j).
 // C enters through its packed pieces Cq.
-hipError_t colpass(const Shape& s, const void* X, const void* Cq, const __bf16* BqE, const __bf16* BqH,
+hipError_t colpass(const Shape& s, const void* X, const void* Cq, const _Float16* Bq, const float* Bsc,
                    float* Hout, double* fpart, int with_h, hipStream_t st);
 int64_t colpass_blocks(const Shape& s);
 
@@ -98,7 +104,7 @@ int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
 // Range r covers 32-column tiles [tb[r], tb[r+1]); C enters through Cq.
-hipError_t rowpass(const Shape& s, const void* X, const void* Cq, const __bf16* BqE, float* Wpart,
+hipError_t rowpass(const Shape& s, const void* X, const void* Cq, const _Float16* Bq, float* Wpart,
                    const int64_t* tb, int R, hipStream_t st);
 
 // Fixed-order reductions.
@@ -121,8 +127,8 @@ struct GInst {
   float* B;
   float* C;
   void* Cq;
-  __bf16* BqE;
-  __bf16* BqH;
+  _Float16* Bq;
+  float* Bsc;
   float* H;
   double* fpart;
   double* G;

@@ -108,6 +108,59 @@ __device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b
 
 __device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// Scaled two-way fp16 split, used for the products whose operands carry a power-of-two
+// scale per row, column or tile.  For a value y whose scale group has its largest magnitude
+// in [2^14, 2^15), hi = fp16(y) and lo = fp16(y - hi) (both rounded to nearest even; y - hi
+// is exact in float32).  For |y| >= 2^-3 both pieces are normal fp16 numbers and
+// |y - hi - lo| <= 2^-22 |y|; smaller values keep an absolute error below 2^-25 (the fp16
+// subnormal spacing), 2^-40 of the group's largest magnitude.  A float32 product a*b is
+// then formed from the three piece products hi*hi, hi*lo, lo*hi (each exact in float32,
+// accumulated in float32 by the MFMA); the dropped lo*lo is below 2^-22 |a b|.  That is the
+// accuracy of the three-way bf16 split below at half its MFMA count.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+struct Split2 {
+  f16x8 p[2];
+};
+
+__device__ __forceinline__ Split2 split2(const float (&v)[8]) {
+  Split2 r;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const _Float16 h = (_Float16)v[t];
+    r.p[0][t] = h;
+    r.p[1][t] = (_Float16)(v[t] - (float)h);
+  }
+  return r;
+}
+
+// v_mfma_f32_32x32x16_f16: the lane layout of the bf16 form.
+__device__ __forceinline__ f32x16 mfma16h(f16x8 a, f16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// acc += a * b as three fp16 MFMAs, smallest terms first.
+__device__ __forceinline__ f32x16 mfma_x3(const f16x8 (&a)[2], const f16x8 (&b)[2], f32x16 acc) {
+  acc = mfma16h(a[1], b[0], acc);
+  acc = mfma16h(a[0], b[1], acc);
+  acc = mfma16h(a[0], b[0], acc);
+  return acc;
+}
+
+__device__ __forceinline__ f16x8 as_f16x8(f32x4 v) { return __builtin_bit_cast(f16x8, v); }
+__device__ __forceinline__ f32x4 f16_as_f32x4(f16x8 v) { return __builtin_bit_cast(f32x4, v); }
+
+// Scale exponent of a group whose largest magnitude is x: the s with x 2^s in [2^14, 2^15)
+// (x = m 2^e with m in [0.5, 1), so s = 15 - e), kept within [-113, 126] so that 2^s and
+// 2^-s are normal float32 numbers; 0 for an all-zero group.
+__device__ __forceinline__ int scale_exp(float x) {
+  if (!(x > 0.0f)) return 0;
+  int e;
+  (void)frexpf(x, &e);
+  const int s = 15 - e;
+  return s < -113 ? -113 : (s > 126 ? 126 : s);
+}
+__device__ __forceinline__ float pow2f(int s) { return ldexpf(1.0f, s); }
+
 __device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
 // Element types of X as the passes read it: float (column-major, as given), or one of the
 // two tiled storages (layout in did_kernels.h), bf16 or float32 (xtf32, a distinct type so
@@ -120,43 +173,67 @@ struct x_is_tiled {
   static constexpr bool value = std::is_same<XT, __bf16>::value || std::is_same<XT, xtf32>::value;
 };
 
-// Packed C (Cq), per 32-column tile T, in 16-byte units of eight bf16:
-//   E order, unit (s*3 + p)*64 + l, element t: piece p of C[16s + 8(l/32) + t][32T + l%32]
-//       (B operand of E = X - BC in the column pass; A operand of E'^T in the row pass)
-//   W order, unit UE + ((b*2 + q)*3 + p)*64 + l, element t:
+// Packed C (Cq), per 32-column tile T, in 16-byte units (UE = KP/16 * 2 * 64 + 8):
+//   E order, unit (s*2 + p)*64 + l, element t (eight fp16): piece p of
+//       C[16s + 8(l/32) + t][j] * 2^t_j,  j = 32T + l%32
+//       (B operand of E = X - BC in the column pass; A operand of E'^T in the row pass),
+//       with t_j = scale_exp(max_k C[k][j]) per column;
+//   units KP/16 * 2 * 64 + u, u < 8: the inverse scales 2^-t_j of the tile's 32 columns
+//       (float32, column 32T + 4u + e in element e);
+//   W order, unit UE + ((b*2 + q)*3 + p)*64 + l, element t (eight bf16):
 //       piece p of C[32b + l%32][32T + row32(8q + t, l/32)]
 //       (A operand of W^T in the row pass; both operands of C C^T)
 // Entries with kk >= K or column >= N are zero.
 //
 // pack_block: the 256 threads of a block pack the (up to) eight tiles of columns
 // j0 .. j0 + nv - 1, whose values sit in LDS as Ct[j * K + kk] (j relative to j0); every
-// thread builds whole 16-byte units, so the global stores are coalesced.
+// thread builds whole 16-byte units, so the global stores are coalesced.  Called by all
+// threads of the block, after Ct is complete.
 template <int KP>
 __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, int64_t j0, int nv, const float* Ct, int K,
                                            int64_t ntiles) {
   constexpr int KS = KP / 16;
   constexpr int NB = KP / 32;
-  constexpr int UE = KS * 3 * 64;
+  constexpr int UE0 = KS * 2 * 64;
+  constexpr int UE = UE0 + 8;
   constexpr int UT = UE + NB * 2 * 3 * 64;
   constexpr int GE = 8 * KS * 64;  // E groups per block: (tile, s, half, jj)
   constexpr int GW = 8 * NB * 128; // W groups per block: (tile, b, q, lane)
+  __shared__ int cs[256];          // column scale exponents
   const int tid = threadIdx.x;
   const int64_t T0 = j0 >> 5;
+  {
+    float mx = 0.0f;
+    if (tid < nv)
+      for (int kk = 0; kk < K; ++kk) mx = fmaxf(mx, Ct[tid * K + kk]);
+    cs[tid] = scale_exp(mx);
+  }
+  __syncthreads();
   for (int g = tid; g < GE; g += 256) {
     const int tb = g / (KS * 64), rem = g % (KS * 64), sh = rem >> 5, jj = rem & 31;
     const int s = sh >> 1, h = sh & 1;
     if (T0 + tb >= ntiles) continue;
     const int j = 32 * tb + jj;
+    const float sc = pow2f(cs[j]);
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int kk = 16 * s + 8 * h + t;
-      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] : 0.0f;
+      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] * sc : 0.0f;
     }
-    const Split3 sp = split3(v);
+    const Split2 sp = split2(v);
     f32x4* tile = Cq + (T0 + tb) * UT;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) tile[(s * 3 + p) * 64 + jj + 32 * h] = as_f32x4(sp.p[p]);
+    for (int p = 0; p < 2; ++p) tile[(s * 2 + p) * 64 + jj + 32 * h] = f16_as_f32x4(sp.p[p]);
+  }
+  if (tid < 64) {  // inverse scales: tile tid / 8, unit tid % 8
+    const int tb = tid >> 3, u = tid & 7;
+    if (T0 + tb < ntiles) {
+      f32x4 w;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = pow2f(-cs[32 * tb + 4 * u + e]);
+      Cq[(T0 + tb) * UT + UE0 + u] = w;
+    }
   }
   for (int g = tid; g < GW; g += 256) {
     const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
@@ -325,45 +402,30 @@ hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t 
 }
 
 // ------------------------------------------------------------------ B update + packing
-// Packed operand buffer of B, each entry split into its three bf16 pieces p = 0, 1, 2
-// (rows >= M and columns >= K stay zero from allocation).  A 16-byte unit holds the eight
-// bf16 values lane l feeds to one MFMA; chunk c's units form one contiguous run of
-// UC = 2 * (KP/16) * 3 * 64 units, its E-order units first (at BqE) and then its H-order
-// units (at BqH = BqE + UC / 2 units):
-//   BqE unit c*UC + (s*3 + p)*64 + l, element t: piece p of -B[32c + l%32][16s + 8(l/32) + t]
-//       (A operand of E = X - B C in the column pass; B operand of E'^T in the row pass)
-//   BqH unit c*UC + ((b*2 + q)*3 + p)*64 + l, element t:
-//       piece p of B[32c + row32(8q + t, l/32)][32b + l%32]   (A operand of H = B^T E)
-template <int KP>
-__device__ __forceinline__ void pack_entry(__bf16* BqE, __bf16* BqH, int64_t m, int kk, float v) {
-  constexpr int64_t UC = 2 * (KP / 16) * 3 * 64;  // units per chunk (E then H order)
-  constexpr int NB = KP / 32;
-  const int64_t c = m >> 5;
-  const int r = (int)(m & 31);
-  __bf16 pc[3], nc[3];
-  split3_scalar(v, pc[0], pc[1], pc[2]);
-  split3_scalar(-v, nc[0], nc[1], nc[2]);
-  {
-    const int s = kk >> 4, h = (kk >> 3) & 1, t = kk & 7, l = r + 32 * h;
-#pragma unroll
-    for (int p = 0; p < 3; ++p) BqE[(c * UC + (s * 3 + p) * 64 + l) * 8 + t] = nc[p];
-  }
-  {
-    const int i = 4 * (r >> 3) + (r & 3), h = (r >> 2) & 1, q = i >> 3, t = i & 7;
-    const int b = kk >> 5, l = (kk & 31) + 32 * h;
-#pragma unroll
-    for (int p = 0; p < 3; ++p) BqH[(c * UC + ((b * 2 + q) * 3 + p) * 64 + l) * 8 + t] = pc[p];
-  }
-}
-
+// Packed operand buffer of B (rows >= M and columns >= K stay zero from allocation).  A
+// 16-byte unit holds the eight fp16 values lane l feeds to one MFMA; chunk c's units form
+// one contiguous run of UC = 2 * UE + 8 units (UE = KP/16 * 2 * 64):
+//   unit c*UC + (s*2 + p)*64 + l, element t: piece p of -B[m][16s + 8(l/32) + t] * 2^s_m,
+//       m = 32c + l%32, with s_m = scale_exp(max_k B[m][k])  (A operand of E = X - B C in
+//       the column pass; B operand of E'^T in the row pass);
+//   unit c*UC + UE + ((b*2 + q)*2 + p)*64 + l, element t: piece p of
+//       B[32c + row32(8q + t, l/32)][kk] * 2^u_kk, kk = 32b + l%32, with
+//       u_kk = scale_exp(max_m B[m][kk])   (A operand of H = B^T E);
+//   units c*UC + 2*UE + u, u < 8: 2^-s_m of rows m = 32c + 4u + e (float32, element e).
+// The per-row part is written by the B update (one thread per row); the per-column part
+// needs the column maxima over all rows, which the B update gathers into Bsc[0, KP) with
+// atomic maxima (exact, so the result does not depend on the order), and is written by
+// k_packh afterwards, which also stores 2^-u_kk into Bsc[KP + kk].
 constexpr int kBupRows = 64;      // rows of B per block (one thread each for the update)
 constexpr int kBupThreads = 256;  // threads per block (all of them form the G partial)
 
 template <int KP, bool V_IN_LDS>
 __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
-                                             int64_t Mpad, const double* __restrict__ V, __bf16* __restrict__ BqE,
-                                             __bf16* __restrict__ BqH, double* __restrict__ Gpart, int update,
+                                             int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
+                                             float* __restrict__ bmax, double* __restrict__ Gpart, int update,
                                              int64_t bid) {
+  constexpr int UE = (KP / 16) * 2 * 64;
+  constexpr int64_t UC = 2 * UE + 8;
   // V is the same for every row.  The single-instance kernel reads it with uniform loads,
   // which the compiler serves from scalar registers; the grouped kernels (pointers from the
   // descriptor table) stage it in LDS.
@@ -390,6 +452,7 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   const bool ok = m < M;
   if (tid < kBupRows) {  // the row update, one thread per row of B
     double* db = dbs + tid;  // db[i * kBupRows]: in LDS, as a private array would go to scratch
+    float mx = 0.0f;
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
       db[i * kBupRows] = 0.0;
@@ -411,12 +474,35 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
         }
         bnew = (float)bn;
         if (update) B[(int64_t)i * M + m] = bnew;
-        pack_entry<KP>(BqE, BqH, m, i, bnew);
       }
       Bt[tid * (KP + 1) + i] = bnew;
+      mx = fmaxf(mx, bnew);
+    }
+    if (Bq && ok) {  // E-order units of row m and its inverse scale
+      const int sm = scale_exp(mx);
+      const float sc = pow2f(sm);
+      const int64_t c = m >> 5;
+      const int r = (int)(m & 31);
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        if (i < K) {
+          const float y = -Bt[tid * (KP + 1) + i] * sc;
+          const _Float16 hi = (_Float16)y;
+          const _Float16 lo = (_Float16)(y - (float)hi);
+          const int sq = i >> 4, h = (i >> 3) & 1, t = i & 7, l = r + 32 * h;
+          Bq[(c * UC + (sq * 2 + 0) * 64 + l) * 8 + t] = hi;
+          Bq[(c * UC + (sq * 2 + 1) * 64 + l) * 8 + t] = lo;
+        }
+      }
+      reinterpret_cast<float*>(Bq + (c * UC + 2 * UE) * 8)[r] = pow2f(-sm);
     }
   }
   __syncthreads();
+  if (bmax && tid < K) {  // column maxima over this block's rows (B >= 0: integer order = float order)
+    float mx = 0.0f;
+    for (int r = 0; r < kBupRows; ++r) mx = fmaxf(mx, Bt[r * (KP + 1) + tid]);
+    if (mx > 0.0f) atomicMax(reinterpret_cast<int*>(bmax) + tid, __float_as_int(mx));
+  }
   // Partial of G = B^T B over this block's rows, float64, pairs (a >= b).
   constexpr int NP = KP * (KP + 1) / 2;
   for (int q = tid; q < NP; q += kBupThreads) {
@@ -434,47 +520,112 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
 template <int KP>
 __global__ __launch_bounds__(kBupThreads) void k_bupdate(float* __restrict__ B, int64_t M, int K,
                                                  const double* __restrict__ W, int64_t Mpad,
-                                                 const double* __restrict__ V, __bf16* __restrict__ BqE,
-                                                 __bf16* __restrict__ BqH, double* __restrict__ Gpart,
+                                                 const double* __restrict__ V, _Float16* __restrict__ Bq,
+                                                 float* __restrict__ bmax, double* __restrict__ Gpart,
                                                  int update) {
-  bupdate_body<KP, false>(B, M, K, W, Mpad, V, BqE, BqH, Gpart, update, blockIdx.x);
+  bupdate_body<KP, false>(B, M, K, W, Mpad, V, Bq, bmax, Gpart, update, blockIdx.x);
+}
+
+// H-order units of the two chunks 2*bid, 2*bid + 1 from B and the column maxima in
+// Bsc[0, KP); block 0 also stores 2^-u_kk into Bsc[KP + kk].  256 threads.
+template <int KP>
+__device__ __forceinline__ void packh_body(const float* __restrict__ B, int64_t M, int K, int64_t nchunks,
+                                           _Float16* __restrict__ Bq, float* __restrict__ Bsc, int64_t bid) {
+  constexpr int NB = KP / 32;
+  constexpr int UE = (KP / 16) * 2 * 64;
+  constexpr int64_t UC = 2 * UE + 8;
+  constexpr int GC = NB * 2 * 64;  // groups (b, q, lane) per chunk
+  __shared__ float us[KP];
+  const int tid = threadIdx.x;
+  if (tid < KP) {
+    const int u = tid < K ? scale_exp(Bsc[tid]) : 0;
+    us[tid] = pow2f(u);
+    if (bid == 0) Bsc[KP + tid] = pow2f(-u);
+  }
+  __syncthreads();
+  for (int g = tid; g < 2 * GC; g += 256) {
+    const int64_t c = 2 * bid + g / GC;
+    if (c >= nchunks) continue;
+    const int rem = g % GC, bq = rem >> 6, l = rem & 63;
+    const int b = bq >> 1, q = bq & 1, h = l >> 5;
+    const int kk = 32 * b + (l & 31);
+    const float sc = us[kk];
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t m = 32 * c + row32(8 * q + t, h);
+      v[t] = (m < M && kk < K) ? B[(int64_t)kk * M + m] * sc : 0.0f;
+    }
+    const Split2 sp = split2(v);
+    f32x4* u = reinterpret_cast<f32x4*>(Bq) + c * UC + UE + (int64_t)(bq * 2) * 64 + l;
+    u[0] = f16_as_f32x4(sp.p[0]);
+    u[64] = f16_as_f32x4(sp.p[1]);
+  }
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_packh(const float* __restrict__ B, int64_t M, int K, int64_t nchunks,
+                                               _Float16* __restrict__ Bq, float* __restrict__ Bsc) {
+  packh_body<KP>(B, M, K, nchunks, Bq, Bsc, blockIdx.x);
+}
+
+__global__ void k_zero_f32(float* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0f;
 }
 
 int bupdate_blocks(const Shape& s) { return (int)((s.M + kBupRows - 1) / kBupRows); }
 
-hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, __bf16* BqE, __bf16* BqH,
+hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _Float16* Bq, float* Bsc,
                    double* Gpart, int update, hipStream_t st) {
   const unsigned g = (unsigned)bupdate_blocks(s);
+  if (s.thin) {
+    Bq = nullptr;
+    Bsc = nullptr;
+  } else {
+    k_zero_f32<<<1, 64, 0, st>>>(Bsc, s.KP);
+  }
   if (s.KP == 32)
-    k_bupdate<32><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
+    k_bupdate<32><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update);
   else
-    k_bupdate<64><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, BqE, BqH, Gpart, update);
+    k_bupdate<64><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update);
+  if (!s.thin) {
+    if (s.KP == 32)
+      k_packh<32><<<g, 256, 0, st>>>(B, s.M, s.K, s.nchunks, Bq, Bsc);
+    else
+      k_packh<64><<<g, 256, 0, st>>>(B, s.M, s.K, s.nchunks, Bq, Bsc);
+  }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ column pass
 // Block = 4 waves = 128 consecutive columns; wave w owns columns 128*blockIdx + 32w ..+31
 // and walks all M rows in 32-row chunks:
-//   acc  = X[chunk, cols]                        (E tile, accumulator layout)
-//   acc += (-B[chunk, :]) C[:, cols]             (ceil(K/16) split-bf16 steps) -> E = X - B C
-//   fsum += sum acc^2                            (float64)
-//   H   += B[chunk, :]^T acc                     (2 split-bf16 steps per 32 rows of H)
-// Every float32 product is formed by six bf16 MFMAs over exact three-way splits (split3),
-// which keeps float32 accuracy at the bf16 MFMA rate.  The packed B pieces of chunk c+1
-// are staged into LDS (double buffer shared by the four waves) and the X tile of chunk
-// c+1 is loaded into registers while chunk c is computed.  H is written as KP x N with
-// row kk contiguous over the columns.
+//   P    = (-B[chunk, :] 2^s) (C[:, cols] 2^t)     (KP/16 scaled fp16 steps)
+//   acc  = X[chunk, cols] + P 2^-(s_m + t_j)        (one fma per entry) -> E = X - B C
+//   fsum += sum acc^2                               (float64)
+//   H   += (B[chunk, :] 2^u)^T (acc 2^v)            (2 scaled fp16 steps per 32 rows of H)
+// Every float32 product is formed by three fp16 MFMAs over scaled two-way splits (split2).
+// The operands of P carry one power-of-two scale per row of B and per column of C, fixed
+// when they are packed; those of H one per column of B (packed) and one per column of E,
+// v_j, chosen per chunk from the chunk's largest |E| in the column and never raised: when
+// it drops, the running H of the column is rescaled (exactly, by a power of two) before the
+// chunk is added.  Powers of two commute with rounding, so the scales change no result
+// beyond the splits themselves.  The packed B run of chunk c+1 is staged into LDS (double
+// buffer shared by the four waves) and the X tile of chunk c+1 is loaded into registers
+// while chunk c is computed.  H is written as KP x N with row kk contiguous over the
+// columns.
 template <int KP, bool WITH_H, typename XT>
 __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                             const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
-                                             const __bf16* __restrict__ BqH, float* __restrict__ Hout,
+                                             const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
+                                             const float* __restrict__ Bsc, float* __restrict__ Hout,
                                              double* __restrict__ fpart, int64_t nchunks, int vec4, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE = KS * 3 * 64;              // 16-byte units of the E operand per chunk
-  constexpr int UH = NB * 2 * 3 * 64;          // 16-byte units of the H operand per chunk
-  constexpr int U = WITH_H ? UE + UH : UE;
+  constexpr int UE = KS * 2 * 64;              // 16-byte units of the E operand per chunk
+  constexpr int UH = NB * 2 * 2 * 64;          // 16-byte units of the H operand per chunk
+  constexpr int U = UE + UH + 8;               // the chunk's run, with its 32 row scales
   constexpr int NV = (U + 255) / 256;          // units per thread per chunk
+  constexpr int UCT = KS * 2 * 64 + 8 + NB * 2 * 3 * 64;  // units per packed C tile
   __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
@@ -487,17 +638,27 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   const XT* xtile = X + (tileok ? j0 : 0) * M;
   const uint32_t loff = (uint32_t)(lc * M + 4 * half);
 
-  bf16x8 cP[KS][3];  // pieces of C[16s + 8*half + t][col], from the packed tile
+  f16x8 cP[KS][2];  // pieces of C[16s + 8*half + t][col] 2^t_col, from the packed tile
+  float ct = 1.0f;  // 2^-t_col
+  if (tileok) {
+    const f32x4* ctile = Cq + T * UCT;
 #pragma unroll
-  for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-      cP[s][p] = tileok ? as_bf16x8(Cq[T * (UE + NB * 2 * 3 * 64) + (s * 3 + p) * 64 + l]) : as_bf16x8(f32x4{0, 0, 0, 0});
+      for (int p = 0; p < 2; ++p) cP[s][p] = as_f16x8(ctile[(s * 2 + p) * 64 + l]);
+    ct = reinterpret_cast<const float*>(ctile + KS * 2 * 64)[lc];
+  } else {
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) cP[s][p] = as_f16x8(f32x4{0, 0, 0, 0});
+  }
   f32x16 H[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int i = 0; i < 16; ++i) H[b][i] = 0.0f;
+  int vcur = 126;  // current scale exponent of this column's E operand (never raised)
   double fs0 = 0.0, fs1 = 0.0;
 
   f32x4 stg[NV];
@@ -506,8 +667,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
       const int uu = u < U ? u : U - 1;  // threads past the end reload the last unit
-      // the chunk's E-order units followed by its H-order units (BqH = BqE + UE units)
-      const f32x4* src = reinterpret_cast<const f32x4*>(BqE) + c * (UE + UH) + uu;
+      const f32x4* src = reinterpret_cast<const f32x4*>(Bq) + c * U + uu;
       stg[v] = *src;
     }
   };
@@ -558,72 +718,96 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     }
   };
 
-  // One chunk: compute chunk c from the X tile in xr (loaded one chunk earlier) and the
+  // One chunk: compute chunk c from the X tile in acc (loaded one chunk earlier) and the
   // staged B operands in LDS buffer c & 1; meanwhile stage chunk c+1's B operands and load
-  // its X tile into xr.
-  // acc holds the X tile of chunk c and accumulates in place; xn receives chunk c+1's
-  // (the two tiles alternate roles from one chunk to the next, so nothing is copied)
+  // its X tile into xn (the two tiles alternate roles from one chunk to the next, so
+  // nothing is copied).
   auto step = [&](int64_t c, f32x16& acc, f32x16& xn) {
     const int buf = (int)(c & 1);
     const int64_t cn = c + 1 < nchunks ? c + 1 : c;
     gload(cn);
     xn = xload(cn);
-      // E = X - B C: KS steps of six MFMAs, operands of step s+1 read from LDS during step s
+    {  // E = X - B C: KS steps of three MFMAs, operands of step s+1 read from LDS during step s
       const f32x4* ue = &sb[buf][0] + l;
-      bf16x8 a[3], an[3];
-  #pragma unroll
-      for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[p * 64]);
-  #pragma unroll
+      f16x8 a[2], an[2];
+      f32x16 P;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) P[i] = 0.0f;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) a[p] = as_f16x8(ue[p * 64]);
+#pragma unroll
       for (int s = 0; s < KS; ++s) {
         if (s + 1 < KS) {
-  #pragma unroll
-          for (int p = 0; p < 3; ++p) an[p] = as_bf16x8(ue[((s + 1) * 3 + p) * 64]);
+#pragma unroll
+          for (int p = 0; p < 2; ++p) an[p] = as_f16x8(ue[((s + 1) * 2 + p) * 64]);
         }
-        acc = mfma_x6(a, cP[s], acc);
+        P = mfma_x3(a, cP[s], P);
         if (s + 1 < KS) {
-  #pragma unroll
-          for (int p = 0; p < 3; ++p) a[p] = an[p];
+#pragma unroll
+          for (int p = 0; p < 2; ++p) a[p] = an[p];
         }
       }
-      {  // sum of squares of this 32x32 tile in float32, accumulated across tiles in float64
-        float a0 = 0.0f, a1 = 0.0f;
-  #pragma unroll
-        for (int i = 0; i < 16; i += 2) {
-          a0 += acc[i] * acc[i];
-          a1 += acc[i + 1] * acc[i + 1];
-        }
-        if (c & 1) fs1 += (double)(a0 + a1);
-        else fs0 += (double)(a0 + a1);
+      // rows row32(4q + e, half) = 8q + 4 half + e: their inverse scales are unit 2q + half
+      const f32x4* rs = &sb[buf][UE + UH];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 r4 = rs[2 * q + half];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, acc[4 * q + e]);
       }
-      if (WITH_H) {
-        const f32x4* uh = &sb[buf][UE] + l;
-        bf16x8 h[3], hn[3];
-  #pragma unroll
-        for (int p = 0; p < 3; ++p) h[p] = as_bf16x8(uh[p * 64]);
-        bf16x8 eP[2][3];
-  #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          float v[8];
-  #pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
-          const Split3 sp = split3(v);
-  #pragma unroll
-          for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+    }
+    {  // sum of squares of this 32x32 tile in float32, accumulated across tiles in float64
+      float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        a0 += acc[i] * acc[i];
+        a1 += acc[i + 1] * acc[i + 1];
+      }
+      if (c & 1) fs1 += (double)(a0 + a1);
+      else fs0 += (double)(a0 + a1);
+    }
+    if (WITH_H) {
+      // scale of this chunk's E operand: the largest |E| of the column over the chunk (the
+      // lane and its partner l ^ 32 hold the column's 32 rows)
+      float em = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) em = fmaxf(em, fabsf(acc[i]));
+      em = fmaxf(em, __shfl_xor(em, 32, 64));
+      int v = scale_exp(em);
+      v = (em > 0.0f && v < vcur) ? v : vcur;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) H[b][i] = ldexpf(H[b][i], v - vcur);
+      vcur = v;
+      const f32x4* uh = &sb[buf][UE] + l;
+      f16x8 h[2], hn[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) h[p] = as_f16x8(uh[p * 64]);
+      f16x8 eP[2][2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float y[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) y[t] = ldexpf(acc[8 * q + t], v);
+        const Split2 sp = split2(y);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) eP[q][p] = sp.p[p];
+      }
+#pragma unroll
+      for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
+        if (g + 1 < NB * 2) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p) hn[p] = as_f16x8(uh[((g + 1) * 2 + p) * 64]);
         }
-  #pragma unroll
-        for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
-          if (g + 1 < NB * 2) {
-  #pragma unroll
-            for (int p = 0; p < 3; ++p) hn[p] = as_bf16x8(uh[((g + 1) * 3 + p) * 64]);
-          }
-          H[g >> 1] = mfma_x6(h, eP[g & 1], H[g >> 1]);
-          if (g + 1 < NB * 2) {
-  #pragma unroll
-            for (int p = 0; p < 3; ++p) h[p] = hn[p];
-          }
+        H[g >> 1] = mfma_x3(h, eP[g & 1], H[g >> 1]);
+        if (g + 1 < NB * 2) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p) h[p] = hn[p];
         }
       }
-      sstore(buf ^ 1);
+    }
+    sstore(buf ^ 1);
     __syncthreads();
   };
 
@@ -638,10 +822,14 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   }
 
   if (WITH_H && colok) {  // row kk of H contiguous over columns: coalesced stores
+    const float* ku = Bsc + KP;  // 2^-u_kk
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) Hout[(int64_t)(32 * b + row32(i, half)) * N + col] = H[b][i];
+      for (int i = 0; i < 16; ++i) {
+        const int kk = 32 * b + row32(i, half);
+        Hout[(int64_t)kk * N + col] = ldexpf(H[b][i], -vcur) * ku[kk];
+      }
   }
 
   double fsum = fs0 + fs1;
@@ -655,40 +843,40 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
 
 template <int KP, bool WITH_H, typename XT>
 __global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
-                                                    const __bf16* __restrict__ BqH, float* __restrict__ Hout,
+                                                    const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
+                                                    const float* __restrict__ Bsc, float* __restrict__ Hout,
                                                     double* __restrict__ fpart, int64_t nchunks, int vec4) {
-  colpass_body<KP, WITH_H, XT>(X, M, N, K, Cq, BqE, BqH, Hout, fpart, nchunks, vec4, blockIdx.x);
+  colpass_body<KP, WITH_H, XT>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x);
 }
 
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
 template <typename XT>
-static void colpass_launch(const Shape& s, const XT* X, const f32x4* C, const __bf16* BqE, const __bf16* BqH,
+static void colpass_launch(const Shape& s, const XT* X, const f32x4* C, const _Float16* Bq, const float* Bsc,
                            float* Hout, double* fpart, int with_h, hipStream_t st) {
   const unsigned g = (unsigned)colpass_blocks(s);
   if (s.KP == 32) {
     if (with_h)
-      k_colpass<32, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<32, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<32, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
   } else {
     if (with_h)
-      k_colpass<64, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
     else
-      k_colpass<64, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, BqE, BqH, Hout, fpart, s.nchunks, s.vec4);
+      k_colpass<64, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
   }
 }
 
-hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const __bf16* BqE, const __bf16* BqH,
+hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const _Float16* Bq, const float* Bsc,
                    float* Hout, double* fpart, int with_h, hipStream_t st) {
   const f32x4* C = static_cast<const f32x4*>(Cqv);
   if (s.xbf16)
-    colpass_launch(s, static_cast<const __bf16*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
+    colpass_launch(s, static_cast<const __bf16*>(X), C, Bq, Bsc, Hout, fpart, with_h, st);
   else if (s.xtiled)
-    colpass_launch(s, static_cast<const xtf32*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
+    colpass_launch(s, static_cast<const xtf32*>(X), C, Bq, Bsc, Hout, fpart, with_h, st);
   else
-    colpass_launch(s, static_cast<const float*>(X), C, BqE, BqH, Hout, fpart, with_h, st);
+    colpass_launch(s, static_cast<const float*>(X), C, Bq, Bsc, Hout, fpart, with_h, st);
   return hipGetLastError();
 }
 
@@ -814,7 +1002,7 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t
                                            int64_t bid, int64_t nblk) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE = KS * 3 * 64;
+  constexpr int UE = KS * 2 * 64 + 8;  // E-order units and scales of a packed C tile
   constexpr int UT = UE + NB * 2 * 3 * 64;
   constexpr int NBL = NB * (NB + 1) / 2;  // lower blocks (b1 >= b2)
   constexpr int NP = KP * (KP + 1) / 2;
@@ -896,26 +1084,30 @@ hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) 
 // ------------------------------------------------------------------ row pass
 // Block = 4 waves; wave w owns the 32-row chunk c = 4*sg + w of slab group sg and column
 // range r.  Per 32-column tile T of the range (transposed tiles, rows = columns of X):
-//   acc  = X[chunk, tile]^T
-//   acc += C[:, tile]^T (-B[chunk, :])^T          -> E'^T with E' = X - B C'
-//   WT  += C[:, tile] acc                          -> (E' C'^T)^T for this chunk
-// with split-bf16 products as in the column pass.  The packed C' tile (both operand
-// orders, already split) is copied into LDS for the next tile (double buffer shared by the
-// four waves) and X of the next tile is prefetched into registers.
+//   P    = (C[:, tile] 2^t)^T (-B[chunk, :] 2^s)^T  (scaled fp16 steps, as in the column pass)
+//   acc  = X[chunk, tile]^T + P 2^-(t_j + s_m)       -> E'^T with E' = X - B C'
+//   WT  += C[:, tile] acc                           -> (E' C'^T)^T for this chunk
+// with split-bf16 products for W (six MFMAs per product over exact three-way splits).  The
+// packed C' tile (both operand orders, already split and scaled) is copied into LDS for
+// the next tile (double buffer shared by the four waves) and X of the next tile is
+// prefetched into registers.
 // Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
 template <int KP, typename XT>
 __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                             const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                             const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
                                              float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
                                              const int64_t* __restrict__ tb, int R, int nsg, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE = KS * 3 * 64;      // 16-byte units of the E'^T A operand per tile
+  constexpr int UE0 = KS * 2 * 64;     // 16-byte units of the E'^T A operand per tile
+  constexpr int UE = UE0 + 8;          // ... followed by the tile's inverse column scales
   constexpr int UW = NB * 2 * 3 * 64;  // 16-byte units of the W A operand per tile
   constexpr int UT = UE + UW;
   constexpr int NV = (UT + 255) / 256;
+  constexpr int UB = KS * 2 * 64;      // E-order units of a packed B chunk
+  constexpr int64_t UC = 2 * UB + 8;   // units per packed B chunk
   __shared__ f32x4 sc[2][UT];
   const int id = (int)bid, xcd = id & 7, local = id >> 3;
   const int r = xcd + 8 * (local / nsg), sg = local % nsg;
@@ -928,13 +1120,15 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   const int64_t m0 = (active ? c : 0) * 32, mrow = m0 + lc;
   const bool rowok = active && mrow < M;
 
-  bf16x8 bP[KS][3];  // pieces of -B[m0 + l%32][16s + 8*half + t]
+  f16x8 bP[KS][2];  // pieces of -B[m0 + l%32][16s + 8*half + t] 2^s_m
+  float bs;         // 2^-s_m of this lane's row
   {
-    const f32x4* pe = reinterpret_cast<const f32x4*>(BqE) + (active ? c : 0) * (2 * UE) + l;
+    const f32x4* pe = reinterpret_cast<const f32x4*>(Bq) + (active ? c : 0) * UC;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int p = 0; p < 3; ++p) bP[s][p] = as_bf16x8(pe[(s * 3 + p) * 64]);
+      for (int p = 0; p < 2; ++p) bP[s][p] = as_f16x8(pe[(s * 2 + p) * 64 + l]);
+    bs = reinterpret_cast<const float*>(pe + 2 * UB)[lc];
   }
   f32x16 WT[NB];
 #pragma unroll
@@ -980,57 +1174,70 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     }
   };
 
-  // One tile: compute tile T from the X tile in xr (loaded one tile earlier) and the
-  // staged C' operands in LDS buffer buf; meanwhile stage tile T+1 and load its X tile.
-  // acc holds the X tile of tile T and accumulates in place; xn receives tile T+1's
+  // One tile: compute tile T from the X tile in acc (loaded one tile earlier) and the
+  // staged C' operands in LDS buffer buf; meanwhile stage tile T+1 and load its X tile
+  // into xn.
   auto step = [&](int64_t T, int buf, f32x16& acc, f32x16& xn) {
     const int64_t Tn = T + 1 < thi ? T + 1 : T;
     cload(Tn);
     xn = xload(Tn);
-      if (active) {
+    if (active) {
+      {
         const f32x4* ue = &sc[buf][0] + l;
-        bf16x8 a[3], an[3];
+        f16x8 a[2], an[2];
+        f32x16 P;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) a[p] = as_bf16x8(ue[p * 64]);
+        for (int i = 0; i < 16; ++i) P[i] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) a[p] = as_f16x8(ue[p * 64]);
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
           if (s + 1 < KS) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) an[p] = as_bf16x8(ue[((s + 1) * 3 + p) * 64]);
+            for (int p = 0; p < 2; ++p) an[p] = as_f16x8(ue[((s + 1) * 2 + p) * 64]);
           }
-          acc = mfma_x6(a, bP[s], acc);
+          P = mfma_x3(a, bP[s], P);
           if (s + 1 < KS) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) a[p] = an[p];
+            for (int p = 0; p < 2; ++p) a[p] = an[p];
           }
         }
-        const f32x4* uw = &sc[buf][UE] + l;
-        bf16x8 w[3], wn[3];
+        // rows row32(4q + e, half) = 8q + 4 half + e of the tile: inverse scales in unit 2q + half
+        const f32x4* ts = &sc[buf][UE0];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) w[p] = as_bf16x8(uw[p * 64]);
-        bf16x8 eP[2][3];
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 t4 = ts[2 * q + half];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          float v[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
-          const Split3 sp = split3(v);
-#pragma unroll
-          for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
-        }
-#pragma unroll
-        for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
-          if (g + 1 < NB * 2) {
-#pragma unroll
-            for (int p = 0; p < 3; ++p) wn[p] = as_bf16x8(uw[((g + 1) * 3 + p) * 64]);
-          }
-          WT[g >> 1] = mfma_x6(w, eP[g & 1], WT[g >> 1]);
-          if (g + 1 < NB * 2) {
-#pragma unroll
-            for (int p = 0; p < 3; ++p) w[p] = wn[p];
-          }
+          for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, acc[4 * q + e]);
         }
       }
+      const f32x4* uw = &sc[buf][UE] + l;
+      bf16x8 w[3], wn[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) w[p] = as_bf16x8(uw[p * 64]);
+      bf16x8 eP[2][3];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
+        const Split3 sp = split3(v);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+      }
+#pragma unroll
+      for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
+        if (g + 1 < NB * 2) {
+#pragma unroll
+          for (int p = 0; p < 3; ++p) wn[p] = as_bf16x8(uw[((g + 1) * 3 + p) * 64]);
+        }
+        WT[g >> 1] = mfma_x6(w, eP[g & 1], WT[g >> 1]);
+        if (g + 1 < NB * 2) {
+#pragma unroll
+          for (int p = 0; p < 3; ++p) w[p] = wn[p];
+        }
+      }
+    }
     cstore(buf ^ 1);
     __syncthreads();
   };
@@ -1057,33 +1264,33 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
 
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const __bf16* __restrict__ BqE,
+                                                    const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
                                                     float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
                                                     const int64_t* __restrict__ tb, int R, int nsg) {
-  rowpass_body<KP, XT>(X, M, N, K, Cq, BqE, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
+  rowpass_body<KP, XT>(X, M, N, K, Cq, Bq, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
 }
 
 template <typename XT>
-static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const __bf16* BqE, float* Wpart,
+static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const _Float16* Bq, float* Wpart,
                            const int64_t* tb, int R, hipStream_t st) {
   const int nsg = (int)((s.nchunks + 3) / 4);
   const int R8 = (R + 7) / 8 * 8;
   const unsigned g = (unsigned)((int64_t)nsg * R8);
   if (s.KP == 32)
-    k_rowpass<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
   else
-    k_rowpass<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, BqE, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
 }
 
-hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const __bf16* BqE, float* Wpart,
+hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const _Float16* Bq, float* Wpart,
                    const int64_t* tb, int R, hipStream_t st) {
   const f32x4* Cq = static_cast<const f32x4*>(Cqv);
   if (s.xbf16)
-    rowpass_launch(s, static_cast<const __bf16*>(X), Cq, BqE, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const __bf16*>(X), Cq, Bq, Wpart, tb, R, st);
   else if (s.xtiled)
-    rowpass_launch(s, static_cast<const xtf32*>(X), Cq, BqE, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const xtf32*>(X), Cq, Bq, Wpart, tb, R, st);
   else
-    rowpass_launch(s, static_cast<const float*>(X), Cq, BqE, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const float*>(X), Cq, Bq, Wpart, tb, R, st);
   return hipGetLastError();
 }
 
@@ -1226,8 +1433,8 @@ __device__ __forceinline__ int ginst_find(const GTable* __restrict__ g, int st, 
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void kg_colpass(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_COL)
-  colpass_body<KP, true, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE,
-                             d.BqH, d.H, d.fpart, d.nchunks, d.vec4, bid);
+  colpass_body<KP, true, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.Bq,
+                             d.Bsc, d.H, d.fpart, d.nchunks, d.vec4, bid);
   DID_GROUP_END
 }
 
@@ -1267,7 +1474,7 @@ __global__ __launch_bounds__(256) void kg_reduce_v(const GTable* __restrict__ g)
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void kg_rowpass(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_ROW)
-  rowpass_body<KP, XT>(static_cast<const XT*>(d.XR), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.BqE, d.Wpart,
+  rowpass_body<KP, XT>(static_cast<const XT*>(d.XR), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.Bq, d.Wpart,
                        d.Mpad, d.nchunks, d.tb, d.R, d.nsg, bid);
   DID_GROUP_END
 }
@@ -1275,6 +1482,8 @@ __global__ __launch_bounds__(256, 2) void kg_rowpass(const GTable* __restrict__ 
 template <int KP>
 __global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_REDW)
+  // the column maxima of B start from zero for the B update that follows
+  if (bid == 0 && threadIdx.x < KP) d.Bsc[threadIdx.x] = 0.0f;
   reduce_w_body(d.Wpart, d.R, (int64_t)KP * d.Mpad, d.W, bid);
   DID_GROUP_END
 }
@@ -1282,14 +1491,19 @@ __global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g)
 template <int KP>
 __global__ __launch_bounds__(kBupThreads) void kg_bupdate(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_BUP)
-  bupdate_body<KP, true>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.BqE, d.BqH, d.Gpart, 1, bid);
+  bupdate_body<KP, true>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.Bq, d.Bsc, d.Gpart, 1, bid);
   DID_GROUP_END
 }
 
 template <int KP>
 __global__ __launch_bounds__(256) void kg_reduce_g(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_REDG)
-  reduce_sym_body(d.Gpart, d.bupblocks, KP, d.G, bid);
+  // the G reduction, then the H-order packing of B: both need only the B update
+  const int64_t ng = (KP * (KP + 1) / 2 + kSymPairs - 1) / kSymPairs;
+  if (bid < ng)
+    reduce_sym_body(d.Gpart, d.bupblocks, KP, d.G, bid);
+  else
+    packh_body<KP>(d.B, d.M, d.K, d.nchunks, d.Bq, d.Bsc, bid - ng);
   DID_GROUP_END
 }
 
@@ -1315,7 +1529,7 @@ void ginst_items(const Shape& s, int R, int64_t items[GS_N]) {
   items[GS_ROW] = nsg * R8;
   items[GS_REDW] = ((int64_t)s.KP * s.Mpad + 255) / 256;
   items[GS_BUP] = bupdate_blocks(s);
-  items[GS_REDG] = (np + kSymPairs - 1) / kSymPairs;
+  items[GS_REDG] = (np + kSymPairs - 1) / kSymPairs + bupdate_blocks(s);
   items[GS_ADV] = 1;
 }
 
