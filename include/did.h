@@ -186,7 +186,8 @@ int did_sync(did_handle h);
  * count into *n_stages and the iteration count into *n_iters, and clears the record.
  * did_stage_name(i) names stage i ("column_pass", "row_pass", ...; "" if out of range).
  * On the MFMA path the V partials and their reduction run on a second stream, overlapped
- * with the row pass, so "sweep_v" times the sweep alone and "reduce_v" is empty.
+ * with the row pass, so "sweep_v" times the sweep and the packing of the swept C for the
+ * row pass, and "reduce_v" is empty.
  */
 int did_profile(did_handle h, int32_t enable);
 int did_profile_read(did_handle h, double* ms, int32_t cap, int32_t* n_stages, int64_t* n_iters);

@@ -117,6 +117,7 @@ void fill_inst(GInst& d, did_ctx* h, double* fcur) {
   d.B = h->B;
   d.C = h->C;
   d.Cq = h->Cq;
+  d.Csc = h->Csc;
   d.Bq = h->Bq;
   d.Bsc = h->Bsc;
   d.H = h->H;

@@ -29,6 +29,7 @@ struct did_ctx {
   float* C = nullptr;
   _Float16* Bq = nullptr;  // B packed as MFMA operands (layout in did_kernels.h)
   float* Bsc = nullptr;     // column scales of the packed B
+  float* Csc = nullptr;     // row scales of the packed C
   double* G = nullptr;
   double* Gpart = nullptr;
   double* V = nullptr;

@@ -200,7 +200,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
   if (s.thin) {
     t += b(didk::thin_blocks(s) * didk::thin_slots(16, 4) * 8);
   } else {
-    t += b(didk::vgram_blocks(s) * NP * 8) + b(KP * N * 4) + b(didk::cq_bytes(s)) + b((int64_t)R * KP * s.Mpad * 4) +
+    t += b(didk::vgram_blocks(s) * NP * 8) + b(KP * N * 4) + b(didk::cq_bytes(s)) + b(didk::bsc_floats(s.KP) * 4) + b((int64_t)R * KP * s.Mpad * 4) +
          b((int64_t)(R + 1) * 8) + b(didk::colpass_blocks(s) * 8);
   }
   t += b(kHistCap * 8) + b(8) + b(8);  // fhist, fobj, tdev
@@ -303,6 +303,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     unsigned char* cq = nullptr;
     if ((rc = dalloc(h, &cq, didk::cq_bytes(s)))) return rc;
     h->Cq = cq;
+    if ((rc = dalloc(h, &h->Csc, didk::bsc_floats(s.KP)))) return rc;
     if ((e = hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&h->ev_c, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&h->ev_v, hipEventDisableTiming)) != hipSuccess)
@@ -324,6 +325,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     return dev_fail(h, e, "buffer setup");
   if (!s.thin &&
       ((e = hipMemsetAsync(h->Cq, 0, (size_t)didk::cq_bytes(s), h->st)) != hipSuccess ||
+       (e = hipMemsetAsync(h->Csc, 0, (size_t)didk::bsc_floats(s.KP) * 4, h->st)) != hipSuccess ||
        (e = hipMemcpyAsync(h->rbounds, rb.data(), rb.size() * sizeof(int64_t), hipMemcpyHostToDevice, h->st)) !=
            hipSuccess))
     return dev_fail(h, e, "buffer setup");
@@ -356,7 +358,7 @@ int objective_pass(did_ctx* h) {
 // Repack C after it was changed outside the sweep (the thin path keeps no packed copy).
 hipError_t pack_c(did_ctx* h) {
   if (h->s.thin) return hipSuccess;
-  return didk::packc(h->s, h->C, h->Cq, h->st);
+  return didk::packc(h->s, h->C, h->Cq, h->Csc, h->st);
 }
 
 int apply_init_scale(did_ctx* h) {
@@ -567,18 +569,18 @@ int did_iterate(did_handle h, int32_t n) {
         hipSuccess)
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
     // V = tril(C'C'^T) on the second stream, overlapped with the row pass and the W
     // reduction; the B update waits for it
     if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess || (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
       return dev_fail(h, e, "stream order");
-    if ((e = didk::vgram(s, h->Cq, h->Vpart, h->st2)) != hipSuccess) return dev_fail(h, e, "V partials");
+    if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, h->st2)) != hipSuccess) return dev_fail(h, e, "V partials");
     if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st2)) != hipSuccess)
       return dev_fail(h, e, "V reduce");
     if ((e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
     DID_MARK(3);
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
       return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");

@@ -25,24 +25,25 @@ struct Shape {
 // (KP/32 * 2 * 2 * 64 units, the same count: two pieces of B scaled per column), then 8
 // units holding the chunk's 32 row scales as float32, so that one chunk's operands are
 // one contiguous run of bq_units_chunk units.
-inline int bq_units_e(int KP) { return (KP / 16) * 2 * 64; }
-inline int bq_units_chunk(int KP) { return 2 * bq_units_e(KP) + 8; }
+constexpr inline int bq_units_e(int KP) { return (KP / 16) * 2 * 64; }
+constexpr inline int bq_units_chunk(int KP) { return 2 * bq_units_e(KP) + 8; }
 // fp16 entries of the packed B buffer
 inline int64_t packed_b_elems(const Shape& s) { return s.nchunks * (int64_t)bq_units_chunk(s.KP) * 8; }
 inline int n_pairs(int KP) { return KP * (KP + 1) / 2; }
 
-// Packed C: per 32-column tile, C in the two MFMA operand orders, as 16-byte units: E order
-// (KP/16 * 2 * 64 units of fp16 pieces of C scaled per column, then 8 units holding the
-// tile's 32 inverse column scales as float32) and W order (KP/32 * 2 * 3 * 64 units of bf16
-// pieces).
-inline int cq_units_e(int KP) { return (KP / 16) * 2 * 64 + 8; }
-inline int cq_units_w(int KP) { return (KP / 32) * 2 * 3 * 64; }
-inline int cq_units(int KP) { return cq_units_e(KP) + cq_units_w(KP); }
+// Packed C: per 32-column tile, C in the two MFMA operand orders, as 16-byte units of eight
+// fp16 values: E order (KP/16 * 2 * 64 units: two pieces of C scaled per column, then 8
+// units holding the tile's 32 inverse column scales as float32) and W order
+// (KP/32 * 2 * 2 * 64 units: two pieces of C scaled per row).
+constexpr inline int cq_units_e(int KP) { return (KP / 16) * 2 * 64 + 8; }
+constexpr inline int cq_units_w(int KP) { return (KP / 32) * 2 * 2 * 64; }
+constexpr inline int cq_units(int KP) { return cq_units_e(KP) + cq_units_w(KP); }
 inline int64_t n_tiles32(const Shape& s) { return (s.N + 31) / 32; }
 // bytes of the packed C buffer
 inline int64_t cq_bytes(const Shape& s) { return n_tiles32(s) * cq_units(s.KP) * 16; }
-// Column scales of B for the H-order operands: floats [0, KP) hold the column maxima
-// (gathered during the B update), [KP, 2 KP) the inverse scales 2^-u_k.
+// Column scales of B for the H-order operands (Bsc), and row scales of C for the W-order
+// operands (Csc): floats [0, KP) hold the maxima (gathered by the kernel that changes the
+// factor), [KP, 2 KP) the inverse scales.
 inline int bsc_floats(int KP) { return 2 * KP; }
 
 // splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
@@ -92,19 +93,20 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cq, const _Float16
 int64_t colpass_blocks(const Shape& s);
 
 // Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C, and
-// repacking of the updated columns into Cq.
-hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st);
+// repacking of the updated columns into Cq (row scales in Csc).
+hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, float* Csc, const double* G,
+                 hipStream_t st);
 // Pack C into Cq (after C was set from outside the sweep).
-hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st);
+hipError_t packc(const Shape& s, const float* C, void* Cq, float* Csc, hipStream_t st);
 
 // V partials: tril(C C^T) per block of tiles from the packed C (float64, n_pairs(KP) per
 // block).
-hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st);
+hipError_t vgram(const Shape& s, const void* Cq, const float* Csc, double* Vpart, hipStream_t st);
 int64_t vgram_blocks(const Shape& s);
 
 // Row pass: W partial per column range r: Wpart[r] = (X - BC)[:, range] C[:, range]^T.
 // Range r covers 32-column tiles [tb[r], tb[r+1]); C enters through Cq.
-hipError_t rowpass(const Shape& s, const void* X, const void* Cq, const _Float16* Bq, float* Wpart,
+hipError_t rowpass(const Shape& s, const void* X, const void* Cq, const float* Csc, const _Float16* Bq, float* Wpart,
                    const int64_t* tb, int R, hipStream_t st);
 
 // Fixed-order reductions.
@@ -119,7 +121,7 @@ hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hi
 // group's instances; an instance's items are exactly the blocks of its single-instance
 // launch, run by the same device code, so its results do not depend on the batch.
 constexpr int kMaxBatch = 64;  // instances per group
-enum GStage { GS_COL = 0, GS_REDF, GS_SWEEP, GS_VGRAM, GS_REDV, GS_ROW, GS_REDW, GS_BUP, GS_REDG, GS_ADV, GS_N };
+enum GStage { GS_COL = 0, GS_REDF, GS_SWEEP, GS_PACKW, GS_VGRAM, GS_REDV, GS_ROW, GS_REDW, GS_BUP, GS_REDG, GS_ADV, GS_N };
 
 struct GInst {
   const void* X;   // X as the column pass reads it
@@ -127,6 +129,7 @@ struct GInst {
   float* B;
   float* C;
   void* Cq;
+  float* Csc;
   _Float16* Bq;
   float* Bsc;
   float* H;

@@ -4,10 +4,13 @@
 //   colpass column pass over X: E = X - B C (MFMA), f partial = sum E^2 (float64),
 //           H = B^T E (MFMA),
 //   sweep   the coordinate sweep over the rows of C (float64, one thread per column),
-//   vgram   V = tril(C C^T) partials of the updated C (split-bf16 MFMA, float64 sums),
+//   vgram   V = tril(C C^T) partials of the updated C (MFMA, float64 sums),
 //   rowpass row pass over X: E' = X - B C' (MFMA) and W = E' C'^T per column range (MFMA),
 //   reduce  fixed-order sums of the V, W and f partials (the paper's one Allreduce),
 //   bupdate incremental update of the columns of B, one thread per row of B.
+// Every MFMA product is float32-accurate: each float32 operand is split into two fp16
+// pieces under a power-of-two scale and each product is formed from three fp16 MFMAs
+// (split2 and mfma_x3 below).
 //
 // The coordinate sweep over c_j is written in inner-product form.  With the residual
 // e_j of the column at the start of the sweep and h = B^T e_j, the running inner product
@@ -17,12 +20,12 @@
 // v_ik delta b_k term); it turns the K dependent length-M reductions of the sweep into
 // one MFMA contraction plus O(K^2) float64 work per column.
 //
-// MFMA lane layouts used (v_mfma_f32_32x32x16_bf16): lane l supplies A[l%32][8(l/32) + t]
+// MFMA lane layouts used (v_mfma_f32_32x32x16_f16): lane l supplies A[l%32][8(l/32) + t]
 // and B[8(l/32) + t][l%32], t = 0..7; accumulator register i of lane l holds
 // D[row32(i, l/32)][l%32] with row32(i, h) = 8*(i/4) + 4*h + i%4.  Because the
 // accumulator's row index pairs with l/32, accumulator registers 8q..8q+7 can be fed back
-// directly (after the bf16 split) as the B operand of a second MFMA that reduces over
-// those sixteen rows; no lane shuffles are needed.
+// directly (after the split) as the B operand of a second MFMA that reduces over those
+// sixteen rows; no lane shuffles are needed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,76 +40,29 @@ namespace didk {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int row32(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
 
-// v_mfma_f32_32x32x16_bf16: D(32x32, fp32) += A(32x16) B(16x32); lane l supplies
-// A[l%32][8(l/32) + t] and B[8(l/32) + t][l%32] for t = 0..7; D as for 32x32x2.
-__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
-// Exact three-way split of float32 values into bf16 pieces by truncation: hi keeps the
-// leading 8 significant bits of x (x with its low 16 bits cleared), mid the leading 8 of
-// r1 = x - hi, and lo = r1 - mid; both differences are exact in float32 and lo has at
-// most 8 significant bits, so x = hi + mid + lo exactly, and each piece is the upper half
-// of a float32 (a bf16).  A float32 product a*b is then formed to float32 accuracy by the
-// six bf16 products whose weight is above 2^-24: hi*hi, hi*mid, mid*hi, hi*lo, mid*mid,
-// lo*hi (each exact in float32 and accumulated in float32 by the MFMA).
-struct Split3 {
-  bf16x8 p[3];
+// 16-byte unit counts of the packed operand buffers (layouts at the packing code below),
+// the single definition every kernel takes its offsets and strides from.
+template <int KP>
+struct CqL {  // one 32-column tile of packed C
+  static constexpr int E0 = (KP / 16) * 2 * 64;  // E-order units
+  static constexpr int E = E0 + 8;               // ... and the tile's 32 inverse column scales
+  static constexpr int W = (KP / 32) * 2 * 2 * 64;  // W-order units
+  static constexpr int T = E + W;
 };
-
-__device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ float u2f(uint32_t x) { return __builtin_bit_cast(float, x); }
-// bf16 pair from the upper halves of two float32 bit patterns (element 0 = a)
-__device__ __forceinline__ uint32_t hi_pair(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xFFFF0000u); }
-
-__device__ __forceinline__ Split3 split3(const float (&v)[8]) {
-  uint32_t h[8], m[8], lo[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    h[t] = f2u(v[t]);
-    const float r1 = v[t] - u2f(h[t] & 0xFFFF0000u);
-    m[t] = f2u(r1);
-    lo[t] = f2u(r1 - u2f(m[t] & 0xFFFF0000u));
-  }
-  uint32_t ph[4], pm[4], pl[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    ph[q] = hi_pair(h[2 * q], h[2 * q + 1]);
-    pm[q] = hi_pair(m[2 * q], m[2 * q + 1]);
-    pl[q] = hi_pair(lo[2 * q], lo[2 * q + 1]);
-  }
-  Split3 r;
-  r.p[0] = __builtin_bit_cast(bf16x8, ph);
-  r.p[1] = __builtin_bit_cast(bf16x8, pm);
-  r.p[2] = __builtin_bit_cast(bf16x8, pl);
-  return r;
-}
-
-__device__ __forceinline__ void split3_scalar(float v, __bf16& h, __bf16& m, __bf16& l) {
-  const uint32_t u = f2u(v);
-  const float r1 = v - u2f(u & 0xFFFF0000u);
-  const float r2 = r1 - u2f(f2u(r1) & 0xFFFF0000u);
-  h = __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
-  m = __builtin_bit_cast(__bf16, (uint16_t)(f2u(r1) >> 16));
-  l = __builtin_bit_cast(__bf16, (uint16_t)(f2u(r2) >> 16));
-}
-
-// acc += a * b as six bf16 MFMAs, smallest terms first.
-__device__ __forceinline__ f32x16 mfma_x6(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x16 acc) {
-  acc = mfma16(a[2], b[0], acc);
-  acc = mfma16(a[1], b[1], acc);
-  acc = mfma16(a[0], b[2], acc);
-  acc = mfma16(a[1], b[0], acc);
-  acc = mfma16(a[0], b[1], acc);
-  acc = mfma16(a[0], b[0], acc);
-  return acc;
-}
-
-__device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+template <int KP>
+struct BqL {  // one 32-row chunk of packed B
+  static constexpr int E = (KP / 16) * 2 * 64;      // E-order units
+  static constexpr int H = (KP / 32) * 2 * 2 * 64;  // H-order units
+  static constexpr int S = E + H;                   // the chunk's 32 row scales start here
+  static constexpr int C = S + 8;
+};
+static_assert(CqL<32>::T == cq_units(32) && CqL<64>::T == cq_units(64), "packed C layout");
+static_assert(CqL<32>::E == cq_units_e(32) && CqL<64>::E == cq_units_e(64), "packed C layout");
+static_assert(BqL<32>::C == bq_units_chunk(32) && BqL<64>::C == bq_units_chunk(64), "packed B layout");
+static_assert(BqL<32>::E == bq_units_e(32) && BqL<64>::E == bq_units_e(64), "packed B layout");
 
 // Scaled two-way fp16 split, used for the products whose operands carry a power-of-two
 // scale per row, column or tile.  For a value y whose scale group has its largest magnitude
@@ -115,8 +71,9 @@ __device__ __forceinline__ bf16x8 as_bf16x8(f32x4 v) { return __builtin_bit_cast
 // |y - hi - lo| <= 2^-22 |y|; smaller values keep an absolute error below 2^-25 (the fp16
 // subnormal spacing), 2^-40 of the group's largest magnitude.  A float32 product a*b is
 // then formed from the three piece products hi*hi, hi*lo, lo*hi (each exact in float32,
-// accumulated in float32 by the MFMA); the dropped lo*lo is below 2^-22 |a b|.  That is the
-// accuracy of the three-way bf16 split below at half its MFMA count.
+// accumulated in float32 by the MFMA); the dropped lo*lo is below 2^-22 |a b|.  (A
+// three-way bf16 split by truncation reaches the same accuracy with six MFMAs per product:
+// bf16 keeps the float32 exponent range, but its 8-bit significand needs a third piece.)
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 struct Split2 {
   f16x8 p[2];
@@ -133,7 +90,8 @@ __device__ __forceinline__ Split2 split2(const float (&v)[8]) {
   return r;
 }
 
-// v_mfma_f32_32x32x16_f16: the lane layout of the bf16 form.
+// v_mfma_f32_32x32x16_f16: D(32x32, fp32) += A(32x16) B(16x32); lane l supplies
+// A[l%32][8(l/32) + t] and B[8(l/32) + t][l%32] for t = 0..7 (the layout at the top).
 __device__ __forceinline__ f32x16 mfma16h(f16x8 a, f16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
@@ -161,7 +119,6 @@ __device__ __forceinline__ int scale_exp(float x) {
 }
 __device__ __forceinline__ float pow2f(int s) { return ldexpf(1.0f, s); }
 
-__device__ __forceinline__ f32x4 as_f32x4(bf16x8 v) { return __builtin_bit_cast(f32x4, v); }
 // Element types of X as the passes read it: float (column-major, as given), or one of the
 // two tiled storages (layout in did_kernels.h), bf16 or float32 (xtf32, a distinct type so
 // that the tiled loads are selected at compile time).
@@ -173,40 +130,48 @@ struct x_is_tiled {
   static constexpr bool value = std::is_same<XT, __bf16>::value || std::is_same<XT, xtf32>::value;
 };
 
-// Packed C (Cq), per 32-column tile T, in 16-byte units (UE = KP/16 * 2 * 64 + 8):
-//   E order, unit (s*2 + p)*64 + l, element t (eight fp16): piece p of
+// Packed C (Cq), per 32-column tile T, in 16-byte units of eight fp16 values
+// (UE = KP/16 * 2 * 64 + 8):
+//   E order, unit (s*2 + p)*64 + l, element t: piece p of
 //       C[16s + 8(l/32) + t][j] * 2^t_j,  j = 32T + l%32
 //       (B operand of E = X - BC in the column pass; A operand of E'^T in the row pass),
 //       with t_j = scale_exp(max_k C[k][j]) per column;
 //   units KP/16 * 2 * 64 + u, u < 8: the inverse scales 2^-t_j of the tile's 32 columns
 //       (float32, column 32T + 4u + e in element e);
-//   W order, unit UE + ((b*2 + q)*3 + p)*64 + l, element t (eight bf16):
-//       piece p of C[32b + l%32][32T + row32(8q + t, l/32)]
-//       (A operand of W^T in the row pass; both operands of C C^T)
-// Entries with kk >= K or column >= N are zero.
+//   W order, unit UE + ((b*2 + q)*2 + p)*64 + l, element t: piece p of
+//       C[kk][32T + row32(8q + t, l/32)] * 2^w_kk,  kk = 32b + l%32,
+//       with w_kk = scale_exp(max_j C[kk][j]) per row, over all N columns
+//       (A operand of W^T in the row pass; both operands of C C^T).
+// Entries with kk >= K or column >= N are zero.  The E order depends only on the column,
+// so it is written by the kernel that changes C (the sweep, or k_packc); that kernel also
+// gathers the row maxima into Csc[0, KP) with atomic maxima (exact, so the result does not
+// depend on the order), and k_packw writes the W order afterwards, storing 2^-w_kk into
+// Csc[KP + kk].
 //
-// pack_block: the 256 threads of a block pack the (up to) eight tiles of columns
-// j0 .. j0 + nv - 1, whose values sit in LDS as Ct[j * K + kk] (j relative to j0); every
-// thread builds whole 16-byte units, so the global stores are coalesced.  Called by all
-// threads of the block, after Ct is complete.
+// The block helpers below take the (up to) eight tiles of columns j0 .. j0 + nv - 1, whose
+// values sit in LDS as Ct[j * K + kk] (j relative to j0); every thread builds whole 16-byte
+// units, so the global stores are coalesced.  All threads of the block call them, after Ct
+// is complete.  pack_block takes 256 ints of LDS scratch (cs) from the caller.
 template <int KP>
-__device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, int64_t j0, int nv, const float* Ct, int K,
-                                           int64_t ntiles) {
+__device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __restrict__ cmax, int64_t j0, int nv,
+                                           const float* Ct, int K, int64_t ntiles, int* cs) {
   constexpr int KS = KP / 16;
   constexpr int NB = KP / 32;
-  constexpr int UE0 = KS * 2 * 64;
-  constexpr int UE = UE0 + 8;
-  constexpr int UT = UE + NB * 2 * 3 * 64;
+  constexpr int UE0 = CqL<KP>::E0;
+  constexpr int UT = CqL<KP>::T;
   constexpr int GE = 8 * KS * 64;  // E groups per block: (tile, s, half, jj)
-  constexpr int GW = 8 * NB * 128; // W groups per block: (tile, b, q, lane)
-  __shared__ int cs[256];          // column scale exponents
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x;     // cs[j]: scale exponent of column j0 + j
   const int64_t T0 = j0 >> 5;
   {
     float mx = 0.0f;
     if (tid < nv)
       for (int kk = 0; kk < K; ++kk) mx = fmaxf(mx, Ct[tid * K + kk]);
     cs[tid] = scale_exp(mx);
+  }
+  if (tid < K) {  // row maxima over the block's columns (C >= 0: integer order = float order)
+    float mx = 0.0f;
+    for (int j = 0; j < nv; ++j) mx = fmaxf(mx, Ct[j * K + tid]);
+    if (mx > 0.0f) atomicMax(reinterpret_cast<int*>(cmax) + tid, __float_as_int(mx));
   }
   __syncthreads();
   for (int g = tid; g < GE; g += 256) {
@@ -235,21 +200,43 @@ __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, int64_t j0, i
       Cq[(T0 + tb) * UT + UE0 + u] = w;
     }
   }
+}
+
+// W-order units of the block's tiles, with the row scales from the maxima in Csc[0, KP);
+// block 0 stores the inverse scales into Csc[KP, 2 KP).
+template <int KP>
+__device__ __forceinline__ void packw_block(f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t j0, int nv,
+                                            const float* Ct, int K, int64_t ntiles, int64_t bid) {
+  constexpr int KS = KP / 16;
+  constexpr int NB = KP / 32;
+  constexpr int UE = CqL<KP>::E;
+  constexpr int UT = CqL<KP>::T;
+  constexpr int GW = 8 * NB * 128;  // W groups per block: (tile, b, q, lane)
+  __shared__ float ws[KP];
+  const int tid = threadIdx.x;
+  const int64_t T0 = j0 >> 5;
+  if (tid < KP) {
+    const int w = tid < K ? scale_exp(Csc[tid]) : 0;
+    ws[tid] = pow2f(w);
+    if (bid == 0) Csc[KP + tid] = pow2f(-w);
+  }
+  __syncthreads();
   for (int g = tid; g < GW; g += 256) {
     const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
     const int b = bq >> 1, q = bq & 1;
     if (T0 + tb >= ntiles) continue;
     const int kk = 32 * b + (l & 31), h = l >> 5;
+    const float sc = ws[kk];
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int j = 32 * tb + row32(8 * q + t, h);
-      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] : 0.0f;
+      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] * sc : 0.0f;
     }
-    const Split3 sp = split3(v);
+    const Split2 sp = split2(v);
     f32x4* tile = Cq + (T0 + tb) * UT;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) tile[UE + ((b * 2 + q) * 3 + p) * 64 + l] = as_f32x4(sp.p[p]);
+    for (int p = 0; p < 2; ++p) tile[UE + ((b * 2 + q) * 2 + p) * 64 + l] = f16_as_f32x4(sp.p[p]);
   }
 }
 
@@ -424,8 +411,9 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
                                              int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
                                              float* __restrict__ bmax, double* __restrict__ Gpart, int update,
                                              int64_t bid) {
-  constexpr int UE = (KP / 16) * 2 * 64;
-  constexpr int64_t UC = 2 * UE + 8;
+  constexpr int UE = BqL<KP>::E;
+  constexpr int64_t UC = BqL<KP>::C;
+  constexpr int US = BqL<KP>::S;
   // V is the same for every row.  The single-instance kernel reads it with uniform loads,
   // which the compiler serves from scalar registers; the grouped kernels (pointers from the
   // descriptor table) stage it in LDS.
@@ -494,7 +482,7 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
           Bq[(c * UC + (sq * 2 + 1) * 64 + l) * 8 + t] = lo;
         }
       }
-      reinterpret_cast<float*>(Bq + (c * UC + 2 * UE) * 8)[r] = pow2f(-sm);
+      reinterpret_cast<float*>(Bq + (c * UC + US) * 8)[r] = pow2f(-sm);
     }
   }
   __syncthreads();
@@ -532,8 +520,8 @@ template <int KP>
 __device__ __forceinline__ void packh_body(const float* __restrict__ B, int64_t M, int K, int64_t nchunks,
                                            _Float16* __restrict__ Bq, float* __restrict__ Bsc, int64_t bid) {
   constexpr int NB = KP / 32;
-  constexpr int UE = (KP / 16) * 2 * 64;
-  constexpr int64_t UC = 2 * UE + 8;
+  constexpr int UE = BqL<KP>::E;
+  constexpr int64_t UC = BqL<KP>::C;
   constexpr int GC = NB * 2 * 64;  // groups (b, q, lane) per chunk
   __shared__ float us[KP];
   const int tid = threadIdx.x;
@@ -621,11 +609,13 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
                                              double* __restrict__ fpart, int64_t nchunks, int vec4, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE = KS * 2 * 64;              // 16-byte units of the E operand per chunk
-  constexpr int UH = NB * 2 * 2 * 64;          // 16-byte units of the H operand per chunk
-  constexpr int U = UE + UH + 8;               // the chunk's run, with its 32 row scales
-  constexpr int NV = (U + 255) / 256;          // units per thread per chunk
-  constexpr int UCT = KS * 2 * 64 + 8 + NB * 2 * 3 * 64;  // units per packed C tile
+  constexpr int UE = BqL<KP>::E;      // 16-byte units of the E operand per chunk
+  constexpr int UH = BqL<KP>::H;      // 16-byte units of the H operand per chunk
+  constexpr int US = BqL<KP>::S;      // the chunk's 32 row scales
+  constexpr int U = BqL<KP>::C;       // the chunk's whole run
+  constexpr int NV = (U + 255) / 256; // units per thread per chunk
+  constexpr int UCT = CqL<KP>::T;     // units per packed C tile
+  constexpr int UCE0 = CqL<KP>::E0;   // the tile's inverse column scales
   __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
@@ -646,7 +636,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int p = 0; p < 2; ++p) cP[s][p] = as_f16x8(ctile[(s * 2 + p) * 64 + l]);
-    ct = reinterpret_cast<const float*>(ctile + KS * 2 * 64)[lc];
+    ct = reinterpret_cast<const float*>(ctile + UCE0)[lc];
   } else {
 #pragma unroll
     for (int s = 0; s < KS; ++s)
@@ -748,7 +738,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
         }
       }
       // rows row32(4q + e, half) = 8q + 4 half + e: their inverse scales are unit 2q + half
-      const f32x4* rs = &sb[buf][UE + UH];
+      const f32x4* rs = &sb[buf][US];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f32x4 r4 = rs[2 * q + half];
@@ -775,11 +765,13 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
       em = fmaxf(em, __shfl_xor(em, 32, 64));
       int v = scale_exp(em);
       v = (em > 0.0f && v < vcur) ? v : vcur;
+      if (__ballot(v != vcur)) {  // wave-uniform: rescale only when some column's scale drops
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) H[b][i] = ldexpf(H[b][i], v - vcur);
-      vcur = v;
+          for (int i = 0; i < 16; ++i) H[b][i] = ldexpf(H[b][i], v - vcur);
+        vcur = v;
+      }
       const f32x4* uh = &sb[buf][UE] + l;
       f16x8 h[2], hn[2];
 #pragma unroll
@@ -891,8 +883,8 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const _Float1
 // each updated column is repacked into Cq for the row pass and the next column pass.
 template <int KP, bool G_IN_LDS>
 __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float* __restrict__ C,
-                                           f32x4* __restrict__ Cq, int64_t N, int K, const double* __restrict__ G,
-                                           int64_t bid) {
+                                           f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t N, int K,
+                                           const double* __restrict__ G, int64_t bid) {
   // G = B^T B (KP x KP, both halves stored) is the same for every lane.  The single-instance
   // kernel reads it directly: uniform addresses into memory the kernel does not write, which
   // the compiler serves with scalar loads, so the FMAs below take G from scalar registers.
@@ -900,6 +892,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
   // items stored to memory) stage its strictly lower triangle in LDS instead and read the
   // diagonal from memory: without the diagonal, two blocks of the K > 32 class fit per CU.
   __shared__ double Gs[G_IN_LDS ? KP * (KP - 1) / 2 : 1];  // strictly lower triangle, rows r >= 1
+  __shared__ int cs_own[G_IN_LDS ? 1 : 256];                // packing scratch (else in Gs, see below)
   extern __shared__ float Ct[];                             // the block's columns, stride K (256 * K floats)
   const int tid = threadIdx.x;
   if constexpr (G_IN_LDS) {
@@ -946,45 +939,88 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
   }
   __syncthreads();
   for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
-  pack_block<KP>(Cq, j0, nv, Ct, K, (N + 31) / 32);
+  // the packing scratch reuses Gs once the sweep is done (the barrier above): with its own
+  // 1 kB the grouped K > 32 kernel would no longer fit two blocks per CU
+  int* cs = G_IN_LDS ? reinterpret_cast<int*>(Gs) : cs_own;
+  pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
-                                               f32x4* __restrict__ Cq, int64_t N, int K,
+                                               f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t N, int K,
                                                const double* __restrict__ G) {
-  sweep_body<KP, false>(Hin, C, Cq, N, K, G, blockIdx.x);
+  sweep_body<KP, false>(Hin, C, Cq, Csc, N, K, G, blockIdx.x);
 }
 
-hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, const double* G, hipStream_t st) {
-  const unsigned g = (unsigned)((s.N + 255) / 256);
-  f32x4* q = static_cast<f32x4*>(Cq);
-  if (s.KP == 32)
-    k_sweep<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, s.N, s.K, G);
-  else
-    k_sweep<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, s.N, s.K, G);
-  return hipGetLastError();
-}
-
+// E order of 256 columns of C (block bid), and their contribution to the row maxima.
 template <int KP>
-__global__ __launch_bounds__(256) void k_packc(const float* __restrict__ C, f32x4* __restrict__ Cq, int64_t N, int K) {
+__device__ __forceinline__ void packc_body(const float* __restrict__ C, f32x4* __restrict__ Cq,
+                                           float* __restrict__ Csc, int64_t N, int K, int64_t bid) {
   extern __shared__ float Ct[];  // 256 * K floats
-  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  __shared__ int cs[256];
+  const int64_t j0 = bid * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
   const int ne = nv * K;
   for (int e = threadIdx.x; e < ne; e += 256) Ct[e] = C[j0 * K + e];
   __syncthreads();
-  pack_block<KP>(Cq, j0, nv, Ct, K, (N + 31) / 32);
+  pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
 
-hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st) {
+// W order of 256 columns of C (block bid), once the row maxima are complete.
+template <int KP>
+__device__ __forceinline__ void packw_body(const float* __restrict__ C, f32x4* __restrict__ Cq,
+                                           float* __restrict__ Csc, int64_t N, int K, int64_t bid) {
+  extern __shared__ float Ct[];  // 256 * K floats
+  const int64_t j0 = bid * 256;
+  const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
+  const int ne = nv * K;
+  for (int e = threadIdx.x; e < ne; e += 256) Ct[e] = C[j0 * K + e];
+  __syncthreads();
+  packw_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, bid);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_packc(const float* __restrict__ C, f32x4* __restrict__ Cq,
+                                               float* __restrict__ Csc, int64_t N, int K) {
+  packc_body<KP>(C, Cq, Csc, N, K, blockIdx.x);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_packw(const float* __restrict__ C, f32x4* __restrict__ Cq,
+                                               float* __restrict__ Csc, int64_t N, int K) {
+  packw_body<KP>(C, Cq, Csc, N, K, blockIdx.x);
+}
+
+static hipError_t packw(const Shape& s, const float* C, f32x4* Cq, float* Csc, hipStream_t st) {
+  const unsigned g = (unsigned)((s.N + 255) / 256);
+  if (s.KP == 32)
+    k_packw<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, Cq, Csc, s.N, s.K);
+  else
+    k_packw<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, Cq, Csc, s.N, s.K);
+  return hipGetLastError();
+}
+
+hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, float* Csc, const double* G,
+                 hipStream_t st) {
   const unsigned g = (unsigned)((s.N + 255) / 256);
   f32x4* q = static_cast<f32x4*>(Cq);
+  k_zero_f32<<<1, 64, 0, st>>>(Csc, s.KP);
   if (s.KP == 32)
-    k_packc<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, s.N, s.K);
+    k_sweep<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G);
   else
-    k_packc<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, s.N, s.K);
-  return hipGetLastError();
+    k_sweep<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G);
+  return packw(s, C, q, Csc, st);
+}
+
+hipError_t packc(const Shape& s, const float* C, void* Cq, float* Csc, hipStream_t st) {
+  const unsigned g = (unsigned)((s.N + 255) / 256);
+  f32x4* q = static_cast<f32x4*>(Cq);
+  k_zero_f32<<<1, 64, 0, st>>>(Csc, s.KP);
+  if (s.KP == 32)
+    k_packc<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, Csc, s.N, s.K);
+  else
+    k_packc<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, q, Csc, s.N, s.K);
+  return packw(s, C, q, Csc, st);
 }
 
 // ------------------------------------------------------------------ V = tril(C C^T)
@@ -992,18 +1028,19 @@ hipError_t packc(const Shape& s, const float* C, void* Cq, hipStream_t st) {
 // eight columns of a tile, which is both the A fragment (rows kk, reduction over columns)
 // and the B fragment (reduction over columns, columns kk') of the product.  Each block
 // takes a contiguous run of tiles; wave w takes every fourth tile of the run and forms the
-// lower 32x32 blocks (b1 >= b2) of the tile's contribution with split-bf16 MFMAs (float32
-// within the tile), adding them to float64 accumulators.  The four waves' partials are
-// then added in wave order and written as tril pairs.
+// lower 32x32 blocks (b1 >= b2) of the tile's contribution with scaled fp16 MFMAs (float32
+// within the tile, in units of 2^(w_a + w_b)), adding them to float64 accumulators.  The
+// four waves' partials are then unscaled (exactly), added in wave order and written as
+// tril pairs.
 constexpr int kVBlocks = 256;
 
 template <int KP>
-__device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t ntiles, double* __restrict__ Vpart,
-                                           int64_t bid, int64_t nblk) {
+__device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
+                                           int64_t ntiles, double* __restrict__ Vpart, int64_t bid, int64_t nblk) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE = KS * 2 * 64 + 8;  // E-order units and scales of a packed C tile
-  constexpr int UT = UE + NB * 2 * 3 * 64;
+  constexpr int UE = CqL<KP>::E;  // E-order units and scales of a packed C tile
+  constexpr int UT = CqL<KP>::T;
   constexpr int NBL = NB * (NB + 1) / 2;  // lower blocks (b1 >= b2)
   constexpr int NP = KP * (KP + 1) / 2;
   __shared__ double Vs[4][NP];
@@ -1025,16 +1062,16 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t
       for (int i = 0; i < 16; ++i) v[k][i] = 0.0f;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      bf16x8 w[NB][3];
+      f16x8 w[NB][2];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int p = 0; p < 3; ++p) w[b][p] = as_bf16x8(wu[((b * 2 + q) * 3 + p) * 64]);
+        for (int p = 0; p < 2; ++p) w[b][p] = as_f16x8(wu[((b * 2 + q) * 2 + p) * 64]);
       int k = 0;
 #pragma unroll
       for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
-        for (int b2 = 0; b2 <= b1; ++b2, ++k) v[k] = mfma_x6(w[b1], w[b2], v[k]);
+        for (int b2 = 0; b2 <= b1; ++b2, ++k) v[k] = mfma_x3(w[b1], w[b2], v[k]);
     }
 #pragma unroll
     for (int k = 0; k < NBL; ++k)
@@ -1044,6 +1081,7 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t
   for (int q = l; q < NP; q += 64) Vs[wave][q] = 0.0;
   __syncthreads();
   {
+    const float* inv = Csc + KP;  // 2^-w_kk
     int k = 0;
 #pragma unroll
     for (int b1 = 0; b1 < NB; ++b1)
@@ -1052,7 +1090,7 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int a = 32 * b1 + row32(i, half), b = 32 * b2 + lc;
-          if (a >= b) Vs[wave][a * (a + 1) / 2 + b] = acc[k][i];
+          if (a >= b) Vs[wave][a * (a + 1) / 2 + b] = acc[k][i] * (double)inv[a] * (double)inv[b];
         }
   }
   __syncthreads();
@@ -1061,9 +1099,9 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, int64_t
 }
 
 template <int KP>
-__global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, int64_t ntiles,
-                                               double* __restrict__ Vpart) {
-  vgram_body<KP>(Cq, ntiles, Vpart, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_vgram(const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
+                                               int64_t ntiles, double* __restrict__ Vpart) {
+  vgram_body<KP>(Cq, Csc, ntiles, Vpart, blockIdx.x, gridDim.x);
 }
 
 int64_t vgram_blocks(const Shape& s) {
@@ -1071,13 +1109,13 @@ int64_t vgram_blocks(const Shape& s) {
   return t < kVBlocks ? t : kVBlocks;
 }
 
-hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) {
+hipError_t vgram(const Shape& s, const void* Cq, const float* Csc, double* Vpart, hipStream_t st) {
   const unsigned g = (unsigned)vgram_blocks(s);
   const f32x4* q = static_cast<const f32x4*>(Cq);
   if (s.KP == 32)
-    k_vgram<32><<<g, 256, 0, st>>>(q, n_tiles32(s), Vpart);
+    k_vgram<32><<<g, 256, 0, st>>>(q, Csc, n_tiles32(s), Vpart);
   else
-    k_vgram<64><<<g, 256, 0, st>>>(q, n_tiles32(s), Vpart);
+    k_vgram<64><<<g, 256, 0, st>>>(q, Csc, n_tiles32(s), Vpart);
   return hipGetLastError();
 }
 
@@ -1086,28 +1124,30 @@ hipError_t vgram(const Shape& s, const void* Cq, double* Vpart, hipStream_t st) 
 // range r.  Per 32-column tile T of the range (transposed tiles, rows = columns of X):
 //   P    = (C[:, tile] 2^t)^T (-B[chunk, :] 2^s)^T  (scaled fp16 steps, as in the column pass)
 //   acc  = X[chunk, tile]^T + P 2^-(t_j + s_m)       -> E'^T with E' = X - B C'
-//   WT  += C[:, tile] acc                           -> (E' C'^T)^T for this chunk
-// with split-bf16 products for W (six MFMAs per product over exact three-way splits).  The
-// packed C' tile (both operand orders, already split and scaled) is copied into LDS for
-// the next tile (double buffer shared by the four waves) and X of the next tile is
-// prefetched into registers.
+//   WT  += (C[:, tile] 2^w) (acc 2^v)                -> (E' C'^T)^T for this chunk, scaled
+// where w is the packed per-row scale of C' and v, per row of E' (per lane), the running
+// scale of the column pass's H: chosen per tile from the tile's largest |E'| in the row and
+// never raised, the running WT being rescaled exactly when it drops.  The packed C' tile
+// (both operand orders, already split and scaled) is copied into LDS for the next tile
+// (double buffer shared by the four waves) and X of the next tile is prefetched into
+// registers.
 // Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
 template <int KP, typename XT>
 __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                             const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
+                                             const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
+                                             const _Float16* __restrict__ Bq,
                                              float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
                                              const int64_t* __restrict__ tb, int R, int nsg, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
-  constexpr int UE0 = KS * 2 * 64;     // 16-byte units of the E'^T A operand per tile
-  constexpr int UE = UE0 + 8;          // ... followed by the tile's inverse column scales
-  constexpr int UW = NB * 2 * 3 * 64;  // 16-byte units of the W A operand per tile
-  constexpr int UT = UE + UW;
+  constexpr int UE0 = CqL<KP>::E0;     // 16-byte units of the E'^T A operand per tile
+  constexpr int UE = CqL<KP>::E;       // ... followed by the tile's inverse column scales
+  constexpr int UT = CqL<KP>::T;       // then the W A operand
   constexpr int NV = (UT + 255) / 256;
-  constexpr int UB = KS * 2 * 64;      // E-order units of a packed B chunk
-  constexpr int64_t UC = 2 * UB + 8;   // units per packed B chunk
+  constexpr int64_t UC = BqL<KP>::C;   // units per packed B chunk
+  constexpr int UBS = BqL<KP>::S;      // the chunk's 32 row scales
   __shared__ f32x4 sc[2][UT];
   const int id = (int)bid, xcd = id & 7, local = id >> 3;
   const int r = xcd + 8 * (local / nsg), sg = local % nsg;
@@ -1128,13 +1168,14 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int p = 0; p < 2; ++p) bP[s][p] = as_f16x8(pe[(s * 2 + p) * 64 + l]);
-    bs = reinterpret_cast<const float*>(pe + 2 * UB)[lc];
+    bs = reinterpret_cast<const float*>(pe + UBS)[lc];
   }
   f32x16 WT[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int i = 0; i < 16; ++i) WT[b][i] = 0.0f;
+  int vcur = 126;  // current scale exponent of this row's E' operand (never raised)
 
   f32x4 stg[NV];
   auto cload = [&](int64_t T) {
@@ -1211,30 +1252,45 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
           for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, acc[4 * q + e]);
         }
       }
-      const f32x4* uw = &sc[buf][UE] + l;
-      bf16x8 w[3], wn[3];
+      // scale of this tile's E' operand: the largest |E'| of the row over the tile (the
+      // lane and its partner l ^ 32 hold the row's 32 columns)
+      float em = 0.0f;
 #pragma unroll
-      for (int p = 0; p < 3; ++p) w[p] = as_bf16x8(uw[p * 64]);
-      bf16x8 eP[2][3];
+      for (int i = 0; i < 16; ++i) em = fmaxf(em, fabsf(acc[i]));
+      em = fmaxf(em, __shfl_xor(em, 32, 64));
+      int v = scale_exp(em);
+      v = (em > 0.0f && v < vcur) ? v : vcur;
+      if (__ballot(v != vcur)) {  // wave-uniform: rescale only when some row's scale drops
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) WT[b][i] = ldexpf(WT[b][i], v - vcur);
+        vcur = v;
+      }
+      const f32x4* uw = &sc[buf][UE] + l;
+      f16x8 w[2], wn[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) w[p] = as_f16x8(uw[p * 64]);
+      f16x8 eP[2][2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        float v[8];
+        float y[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = acc[8 * q + t];
-        const Split3 sp = split3(v);
+        for (int t = 0; t < 8; ++t) y[t] = ldexpf(acc[8 * q + t], v);
+        const Split2 sp = split2(y);
 #pragma unroll
-        for (int p = 0; p < 3; ++p) eP[q][p] = sp.p[p];
+        for (int p = 0; p < 2; ++p) eP[q][p] = sp.p[p];
       }
 #pragma unroll
       for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
         if (g + 1 < NB * 2) {
 #pragma unroll
-          for (int p = 0; p < 3; ++p) wn[p] = as_bf16x8(uw[((g + 1) * 3 + p) * 64]);
+          for (int p = 0; p < 2; ++p) wn[p] = as_f16x8(uw[((g + 1) * 2 + p) * 64]);
         }
-        WT[g >> 1] = mfma_x6(w, eP[g & 1], WT[g >> 1]);
+        WT[g >> 1] = mfma_x3(w, eP[g & 1], WT[g >> 1]);
         if (g + 1 < NB * 2) {
 #pragma unroll
-          for (int p = 0; p < 3; ++p) w[p] = wn[p];
+          for (int p = 0; p < 2; ++p) w[p] = wn[p];
         }
       }
     }
@@ -1255,42 +1311,47 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   }
   if (active) {
     float* wp = Wpart + (int64_t)r * KP * Mpad;
+    const float* inv = Csc + KP;  // 2^-w_kk
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) wp[(int64_t)(32 * b + row32(i, half)) * Mpad + m0 + lc] = WT[b][i];
+      for (int i = 0; i < 16; ++i) {
+        const int kk = 32 * b + row32(i, half);
+        wp[(int64_t)kk * Mpad + m0 + lc] = ldexpf(WT[b][i], -vcur) * inv[kk];
+      }
   }
 }
 
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
-                                                    float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
-                                                    const int64_t* __restrict__ tb, int R, int nsg) {
-  rowpass_body<KP, XT>(X, M, N, K, Cq, Bq, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
+                                                    const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
+                                                    const _Float16* __restrict__ Bq, float* __restrict__ Wpart,
+                                                    int64_t Mpad, int64_t nchunks, const int64_t* __restrict__ tb,
+                                                    int R, int nsg) {
+  rowpass_body<KP, XT>(X, M, N, K, Cq, Csc, Bq, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
 }
 
 template <typename XT>
-static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const _Float16* Bq, float* Wpart,
-                           const int64_t* tb, int R, hipStream_t st) {
+static void rowpass_launch(const Shape& s, const XT* X, const f32x4* Cq, const float* Csc, const _Float16* Bq,
+                           float* Wpart, const int64_t* tb, int R, hipStream_t st) {
   const int nsg = (int)((s.nchunks + 3) / 4);
   const int R8 = (R + 7) / 8 * 8;
   const unsigned g = (unsigned)((int64_t)nsg * R8);
   if (s.KP == 32)
-    k_rowpass<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Csc, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
   else
-    k_rowpass<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+    k_rowpass<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, Cq, Csc, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
 }
 
-hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const _Float16* Bq, float* Wpart,
-                   const int64_t* tb, int R, hipStream_t st) {
+hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const float* Csc, const _Float16* Bq,
+                   float* Wpart, const int64_t* tb, int R, hipStream_t st) {
   const f32x4* Cq = static_cast<const f32x4*>(Cqv);
   if (s.xbf16)
-    rowpass_launch(s, static_cast<const __bf16*>(X), Cq, Bq, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const __bf16*>(X), Cq, Csc, Bq, Wpart, tb, R, st);
   else if (s.xtiled)
-    rowpass_launch(s, static_cast<const xtf32*>(X), Cq, Bq, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const xtf32*>(X), Cq, Csc, Bq, Wpart, tb, R, st);
   else
-    rowpass_launch(s, static_cast<const float*>(X), Cq, Bq, Wpart, tb, R, st);
+    rowpass_launch(s, static_cast<const float*>(X), Cq, Csc, Bq, Wpart, tb, R, st);
   return hipGetLastError();
 }
 
@@ -1441,6 +1502,8 @@ __global__ __launch_bounds__(256, 2) void kg_colpass(const GTable* __restrict__ 
 __global__ __launch_bounds__(256) void kg_reduce_f(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_REDF)
   (void)bid;
+  // the row maxima of C start from zero for the sweep that follows
+  if ((int)threadIdx.x < d.K) d.Csc[threadIdx.x] = 0.0f;
   const double r = reduce_f_body(d.fpart, d.colblocks, 0.5);
   if (threadIdx.x == 0) {
     const int64_t t = *d.tdev;
@@ -1453,14 +1516,21 @@ __global__ __launch_bounds__(256) void kg_reduce_f(const GTable* __restrict__ g)
 template <int KP>
 __global__ __launch_bounds__(256) void kg_sweep(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_SWEEP)
-  sweep_body<KP, true>(d.H, d.C, static_cast<f32x4*>(d.Cq), d.N, d.K, d.G, bid);
+  sweep_body<KP, true>(d.H, d.C, static_cast<f32x4*>(d.Cq), d.Csc, d.N, d.K, d.G, bid);
+  DID_GROUP_END
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void kg_packw(const GTable* __restrict__ g) {
+  DID_GROUP_LOOP(GS_PACKW)
+  packw_body<KP>(d.C, static_cast<f32x4*>(d.Cq), d.Csc, d.N, d.K, bid);
   DID_GROUP_END
 }
 
 template <int KP>
 __global__ __launch_bounds__(256) void kg_vgram(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_VGRAM)
-  vgram_body<KP>(static_cast<const f32x4*>(d.Cq), (d.N + 31) / 32, d.Vpart, bid, d.vblocks);
+  vgram_body<KP>(static_cast<const f32x4*>(d.Cq), d.Csc, (d.N + 31) / 32, d.Vpart, bid, d.vblocks);
   DID_GROUP_END
 }
 
@@ -1474,7 +1544,8 @@ __global__ __launch_bounds__(256) void kg_reduce_v(const GTable* __restrict__ g)
 template <int KP, typename XT>
 __global__ __launch_bounds__(256, 2) void kg_rowpass(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_ROW)
-  rowpass_body<KP, XT>(static_cast<const XT*>(d.XR), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.Bq, d.Wpart,
+  rowpass_body<KP, XT>(static_cast<const XT*>(d.XR), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.Csc, d.Bq,
+                       d.Wpart,
                        d.Mpad, d.nchunks, d.tb, d.R, d.nsg, bid);
   DID_GROUP_END
 }
@@ -1524,6 +1595,7 @@ void ginst_items(const Shape& s, int R, int64_t items[GS_N]) {
   items[GS_COL] = colpass_blocks(s);
   items[GS_REDF] = 1;
   items[GS_SWEEP] = (s.N + 255) / 256;
+  items[GS_PACKW] = (s.N + 255) / 256;
   items[GS_VGRAM] = vgram_blocks(s);
   items[GS_REDV] = (np + kSymPairs - 1) / kSymPairs;
   items[GS_ROW] = nsg * R8;
@@ -1549,6 +1621,7 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
   if ((e = occ((const void*)kg_colpass<KP, XT>, 256, 0, &grids[GS_COL])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_f, 256, 0, &grids[GS_REDF])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_sweep<KP>, 256, 256 * KP * sizeof(float), &grids[GS_SWEEP])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_packw<KP>, 256, 256 * KP * sizeof(float), &grids[GS_PACKW])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_vgram<KP>, 256, 0, &grids[GS_VGRAM])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_v<KP>, 256, 0, &grids[GS_REDV])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_rowpass<KP, XT>, 256, 0, &grids[GS_ROW])) != hipSuccess) return e;
@@ -1575,6 +1648,7 @@ static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st
   kg_colpass<KP, XT><<<(unsigned)gr[GS_COL], 256, 0, st>>>(t);
   kg_reduce_f<<<(unsigned)gr[GS_REDF], 256, 0, st>>>(t);
   kg_sweep<KP><<<(unsigned)gr[GS_SWEEP], 256, 256 * KP * sizeof(float), st>>>(t);
+  kg_packw<KP><<<(unsigned)gr[GS_PACKW], 256, 256 * KP * sizeof(float), st>>>(t);
   kg_vgram<KP><<<(unsigned)gr[GS_VGRAM], 256, 0, st>>>(t);
   kg_reduce_v<KP><<<(unsigned)gr[GS_REDV], 256, 0, st>>>(t);
   kg_rowpass<KP, XT><<<(unsigned)gr[GS_ROW], 256, 0, st>>>(t);
