@@ -7,8 +7,9 @@ device (X = B0 C0 + |0.01 N(0,1)|, U[0,1] factors) and stays in HBM.
 
 Prints one JSON line:
   value          iterations/s of the whole job (inputs resident in HBM at the start),
-  roofline       the dominant kernel (column or row pass) against the float32-accurate
-                 MFMA peak of its split-bf16 products,
+  roofline       the dominant kernel (column or row pass) against the roofline that bounds
+                 it: HBM (algorithmic bytes against 8 TB/s) or the float32-accurate MFMA
+                 peak of its split-fp16 products, whichever time floor is larger,
   cpu_baseline   the FP64 oracle timed on a bounded sample of the same workload.
 
 ``--workload paper`` runs the experiments' synthetic shape instead (M = 5, K = 3,
@@ -49,11 +50,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DID iters/s + HBM GB/s (M=5000,N=1e6,K=50); served solves/s, p50/p99 latency"
-PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
-# The passes form every float32 product from six bf16 MFMA products of three-way splits of
-# the operands, so their float32-accurate peak is the bf16 peak over six.
-SPLIT_PRODUCTS = 6
-PEAK_SPLIT_TFLOPS = PEAK_BF16_MFMA_TFLOPS / SPLIT_PRODUCTS
+PEAK_F16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 (and bf16) matrix peak
+# The passes form every float32 product from three fp16 MFMA products of scaled two-way
+# splits of the operands, so their float32-accurate peak is the fp16 peak over three.
+SPLIT_PRODUCTS = 3
+PEAK_SPLIT_TFLOPS = PEAK_F16_MFMA_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
@@ -96,16 +97,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_counts(M, N, K):
+def algorithmic_counts(M, N, K, xbytes=4):
     """Algorithmic work of one iteration and of the dominant kernel.
 
-    Iteration bytes: X read once (4MN), C read and written (8KN), B read (4MK).
-    Column-pass launch: flops 4MNK (E = X - BC and H = B^T E, 2MNK each); bytes 4MN + 8KN.
+    Iteration bytes: X read once (xbytes MN: 4 for float32, 2 for the bf16 storage form), C
+    read and written (8KN), B read (4MK).  A pass (column or row) per launch: flops 4MNK
+    (E = X - BC and H = B^T E, or E' and W = E' C'^T, 2MNK each); bytes xbytes MN + 8KN.
     """
     return dict(
-        iter_bytes=4.0 * M * N + 8.0 * K * N + 4.0 * M * K,
+        iter_bytes=xbytes * M * N + 8.0 * K * N + 4.0 * M * K,
         pass_flops=4.0 * M * N * K,
-        pass_bytes=4.0 * M * N + 8.0 * K * N,
+        pass_bytes=xbytes * M * N + 8.0 * K * N,
     )
 
 
@@ -703,24 +705,35 @@ def main():
             did.did_free(h2)
     ms = ms_total / args.steps
     it_s = 1000.0 / ms
-    cnt = algorithmic_counts(M, N, K)
+    cnt = algorithmic_counts(M, N, K, 2 if cfg.get("x_bf16") else 4)
     dom = max(("column_pass", "row_pass"), key=lambda k: stages[k])
     dom_ms = stages[dom] / max(n_it, 1)
-    achieved = cnt["pass_flops"] / (dom_ms * 1e-3) / 1e12
+    secs = dom_ms * 1e-3
     traffic = measured_traffic(dom, args.workload)
     KP = 32 if K <= 32 else 64
-    issued = SPLIT_PRODUCTS * 4.0 * M * N * KP  # bf16 MFMA flops the pass issues (K padded to KP)
-    roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_SPLIT_TFLOPS, 2),
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic,
-            "kernel_ms": round(dom_ms, 4), "flops_per_launch": cnt["pass_flops"],
-            "peak_note": "float32-accurate flops (4MNK per pass) against the bf16 MFMA peak / 6 "
-                         "(six bf16 products per float32 product)",
-            "mfma_bf16_issued_tflops": round(issued / (dom_ms * 1e-3) / 1e12, 1),
-            "mfma_bf16_issued_frac": round(issued / (dom_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
-            "hbm_algorithmic_gbs": round(cnt["pass_bytes"] / (dom_ms * 1e-3) / 1e9, 1),
-            "hbm_algorithmic_frac": round(cnt["pass_bytes"] / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    issued = SPLIT_PRODUCTS * 4.0 * M * N * KP  # fp16 MFMA flops the pass issues (K padded to KP)
+    tflops = cnt["pass_flops"] / secs / 1e12  # float32-accurate flops
+    gbs = cnt["pass_bytes"] / secs / 1e9      # algorithmic HBM bytes
+    # the roofline that bounds the pass: the larger of its two time floors
+    hbm_bound = cnt["pass_bytes"] / (PEAK_HBM_GBS * 1e9) >= cnt["pass_flops"] / (PEAK_SPLIT_TFLOPS * 1e12)
+    if hbm_bound:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(tflops, 3), "peak": round(PEAK_SPLIT_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(tflops / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic}
+    roof.update({
+        "kernel_ms": round(dom_ms, 4), "bytes_per_launch": cnt["pass_bytes"], "flops_per_launch": cnt["pass_flops"],
+        "f32_accurate_tflops": round(tflops, 3), "f32_accurate_peak_tflops": round(PEAK_SPLIT_TFLOPS, 2),
+        "f32_accurate_frac": round(tflops / PEAK_SPLIT_TFLOPS, 4),
+        "peak_note": "float32-accurate flops (4MNK per pass) against the fp16 MFMA peak / 3 (three fp16 "
+                     "products per float32 product); algorithmic bytes (X once, C read and written) "
+                     "against 8 TB/s",
+        "mfma_f16_issued_tflops": round(issued / secs / 1e12, 1),
+        "mfma_f16_issued_frac": round(issued / secs / 1e12 / PEAK_F16_MFMA_TFLOPS, 4),
+        "hbm_algorithmic_gbs": round(gbs, 1), "hbm_algorithmic_frac": round(gbs / PEAK_HBM_GBS, 4)})
     if traffic is not None:
-        roof["hbm_measured_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        roof["hbm_measured_gbs"] = round(traffic / secs / 1e9, 1)
     line = {
         "metric": METRIC,
         "value": round(it_s, 4),
