@@ -156,7 +156,6 @@ template <int KP>
 __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __restrict__ cmax, int64_t j0, int nv,
                                            const float* Ct, int K, int64_t ntiles, int* cs) {
   constexpr int KS = KP / 16;
-  constexpr int NB = KP / 32;
   constexpr int UE0 = CqL<KP>::E0;
   constexpr int UT = CqL<KP>::T;
   constexpr int GE = 8 * KS * 64;  // E groups per block: (tile, s, half, jj)
@@ -207,7 +206,6 @@ __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __rest
 template <int KP>
 __device__ __forceinline__ void packw_block(f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t j0, int nv,
                                             const float* Ct, int K, int64_t ntiles, int64_t bid) {
-  constexpr int KS = KP / 16;
   constexpr int NB = KP / 32;
   constexpr int UE = CqL<KP>::E;
   constexpr int UT = CqL<KP>::T;
@@ -411,7 +409,6 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
                                              int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
                                              float* __restrict__ bmax, double* __restrict__ Gpart, int update,
                                              int64_t bid) {
-  constexpr int UE = BqL<KP>::E;
   constexpr int64_t UC = BqL<KP>::C;
   constexpr int US = BqL<KP>::S;
   // V is the same for every row.  The single-instance kernel reads it with uniform loads,
@@ -610,7 +607,6 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = BqL<KP>::E;      // 16-byte units of the E operand per chunk
-  constexpr int UH = BqL<KP>::H;      // 16-byte units of the H operand per chunk
   constexpr int US = BqL<KP>::S;      // the chunk's 32 row scales
   constexpr int U = BqL<KP>::C;       // the chunk's whole run
   constexpr int NV = (U + 255) / 256; // units per thread per chunk
@@ -672,16 +668,8 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   auto xload = [&](int64_t c) {
     f32x16 v;
     if constexpr (x_is_tiled<XT>::value) {  // tiled copy XC
-      // A wave past the last tile either loads zeros (float32) or reads tile 0, in bounds
-      // (bf16); either way its f partial is dropped and its H stores are masked by
-      // col < N.  Each form is the faster one for its storage (measured).
-      if constexpr (std::is_same<XT, xtf32>::value) {
-        if (!tileok) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) v[i] = 0.0f;
-          return v;
-        }
-      }
+      // A wave past the last tile reads tile 0, in bounds (no branch in the chunk loop);
+      // its f partial is dropped and its H stores are masked by col < N.
       return ld_tile(X + ((tileok ? T : 0) * nchunks + c) * 1024, l);
     } else {  // column-major float32 X
       const int64_t m0 = c * 32;
@@ -1038,7 +1026,6 @@ template <int KP>
 __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
                                            int64_t ntiles, double* __restrict__ Vpart, int64_t bid, int64_t nblk) {
   constexpr int NB = KP / 32;
-  constexpr int KS = KP / 16;
   constexpr int UE = CqL<KP>::E;  // E-order units and scales of a packed C tile
   constexpr int UT = CqL<KP>::T;
   constexpr int NBL = NB * (NB + 1) / 2;  // lower blocks (b1 >= b2)
