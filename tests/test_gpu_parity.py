@@ -158,6 +158,64 @@ def test_unstructured_data_within_fp32_conditioning(M, N, K):
     assert rel_fro(out[1][1], C1o) <= tol
 
 
+def _badly_scaled(M, N, K, seed):
+    """Planted X whose rows and columns span 1e-2 .. 1e2, and factors whose components are
+    imbalanced by 1e3 each way between B and C (the same X, with very uneven factors);
+    initial factors are the planted ones perturbed by up to 10 %."""
+    r = np.random.default_rng(seed)
+    rs = 10.0 ** r.uniform(-2, 2, M)
+    cs = 10.0 ** r.uniform(-2, 2, N)
+    comp = 10.0 ** np.linspace(-3, 3, K)
+    Bp = (rs[:, None] * (0.2 + r.random((M, K)))) * comp[None, :]
+    Cp = ((0.2 + r.random((K, N))) * cs[None, :]) / comp[:, None]
+    X32 = to_f32_colmajor(Bp @ Cp)
+    B0 = (Bp * (1 + 0.1 * r.random((M, K)))).astype(np.float32)
+    C0 = (Cp * (1 + 0.1 * r.random((K, N)))).astype(np.float32)
+    return X32, B0, C0
+
+
+def _relative_sensitivity(X32, B0, C0, draws=3):
+    """Movement of the oracle's one-iteration factors under elementwise relative
+    perturbations of X, B0 and C0 at float32 rounding size: normwise for B and C, and for
+    the worst single row of B and column of C."""
+    X = as_oracle_input(X32)
+    B1, C1, _ = oracle.did_run(X, B0, C0, 1)
+    e = np.finfo(np.float32).eps
+    worst = np.zeros(4)
+    for d in range(draws):
+        q = np.random.default_rng(100 + d)
+        B2, C2, _ = oracle.did_run(X * (1 + e * q.standard_normal(X.shape)), B0 * (1 + e * q.standard_normal(B0.shape)),
+                                   C0 * (1 + e * q.standard_normal(C0.shape)), 1)
+        worst = np.maximum(worst, [rel_fro(B2, B1), rel_fro(C2, C1), _worst_row(B2, B1), _worst_row(C2.T, C1.T)])
+    return worst
+
+
+def _worst_row(a, b):
+    nb = np.linalg.norm(b, axis=1)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.where(nb > 0, nb, 1.0)))
+
+
+@pytest.mark.parametrize("M,N,K,seed", [(150, 700, 6, 1), (130, 500, 40, 2)])
+def test_badly_scaled_data_and_components(M, N, K, seed):
+    """The MFMA products split each operand into two fp16 pieces under a power-of-two scale
+    per row, column or chunk; rows and columns of very different magnitude, and components
+    imbalanced by 1e6 between B and C, must keep float32 accuracy row by row and column by
+    column, not only normwise.  Bars: max(1e-5, 10 x the oracle's own sensitivity)
+    normwise and max(1e-4, 10 x sensitivity) per row of B and column of C."""
+    torch = require_gpu()
+    X32, B0, C0 = _badly_scaled(M, N, K, seed)
+    announce(f"badly scaled data M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1,), B0=B0, C0=C0)
+    Bi, Ci = out["init"]
+    sens = _relative_sensitivity(X32, Bi, Ci)
+    B1o, C1o, _ = _oracle_from(X32, Bi, Ci, 1)
+    B1, C1 = out[1]
+    assert rel_fro(B1, B1o) <= max(TOL_FACTORS, 10 * sens[0])
+    assert rel_fro(C1, C1o) <= max(TOL_FACTORS, 10 * sens[1])
+    assert _worst_row(B1, B1o) <= max(1e-4, 10 * sens[2])
+    assert _worst_row(C1.T, C1o.T) <= max(1e-4, 10 * sens[3])
+
+
 def test_zero_data_and_guard_on_gpu():
     """X = 0 with small-integer factors: C becomes exactly 0, every v_ii = 0 keeps B."""
     torch = require_gpu()
