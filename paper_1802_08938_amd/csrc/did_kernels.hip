@@ -148,10 +148,10 @@ struct x_is_tiled {
 // depend on the order), and k_packw writes the W order afterwards, storing 2^-w_kk into
 // Csc[KP + kk].
 //
-// The block helpers below take the (up to) eight tiles of columns j0 .. j0 + nv - 1, whose
-// values sit in LDS as Ct[j * K + kk] (j relative to j0); every thread builds whole 16-byte
-// units, so the global stores are coalesced.  All threads of the block call them, after Ct
-// is complete.  pack_block takes 256 ints of LDS scratch (cs) from the caller.
+// pack_block takes the (up to) eight tiles of columns j0 .. j0 + nv - 1, whose values sit
+// in LDS as Ct[j * K + kk] (j relative to j0); every thread builds whole 16-byte units, so
+// the global stores are coalesced.  All threads of the block call it, after Ct is
+// complete; it takes 256 ints of LDS scratch (cs) from the caller.
 template <int KP>
 __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __restrict__ cmax, int64_t j0, int nv,
                                            const float* Ct, int K, int64_t ntiles, int* cs) {
@@ -201,18 +201,20 @@ __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __rest
   }
 }
 
-// W-order units of the block's tiles, with the row scales from the maxima in Csc[0, KP);
-// block 0 stores the inverse scales into Csc[KP, 2 KP).
+// W-order units of the eight tiles of columns 256 bid .. 256 bid + 255, read straight from
+// C (each group's eight loads are coalesced across the lanes, which take consecutive
+// coordinates), with the row scales from the maxima in Csc[0, KP); block 0 stores the
+// inverse scales into Csc[KP, 2 KP).  No LDS staging, so that many blocks stay resident.
 template <int KP>
-__device__ __forceinline__ void packw_block(f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t j0, int nv,
-                                            const float* Ct, int K, int64_t ntiles, int64_t bid) {
+__device__ __forceinline__ void packw_body(const float* __restrict__ C, f32x4* __restrict__ Cq,
+                                           float* __restrict__ Csc, int64_t N, int K, int64_t bid) {
   constexpr int NB = KP / 32;
   constexpr int UE = CqL<KP>::E;
   constexpr int UT = CqL<KP>::T;
   constexpr int GW = 8 * NB * 128;  // W groups per block: (tile, b, q, lane)
   __shared__ float ws[KP];
   const int tid = threadIdx.x;
-  const int64_t T0 = j0 >> 5;
+  const int64_t j0 = bid * 256, T0 = bid * 8, ntiles = (N + 31) / 32;
   if (tid < KP) {
     const int w = tid < K ? scale_exp(Csc[tid]) : 0;
     ws[tid] = pow2f(w);
@@ -228,8 +230,8 @@ __device__ __forceinline__ void packw_block(f32x4* __restrict__ Cq, float* __res
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int j = 32 * tb + row32(8 * q + t, h);
-      v[t] = (j < nv && kk < K) ? Ct[j * K + kk] * sc : 0.0f;
+      const int64_t j = j0 + 32 * tb + row32(8 * q + t, h);
+      v[t] = (j < N && kk < K) ? C[j * K + kk] * sc : 0.0f;
     }
     const Split2 sp = split2(v);
     f32x4* tile = Cq + (T0 + tb) * UT;
@@ -954,19 +956,6 @@ __device__ __forceinline__ void packc_body(const float* __restrict__ C, f32x4* _
   pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
 
-// W order of 256 columns of C (block bid), once the row maxima are complete.
-template <int KP>
-__device__ __forceinline__ void packw_body(const float* __restrict__ C, f32x4* __restrict__ Cq,
-                                           float* __restrict__ Csc, int64_t N, int K, int64_t bid) {
-  extern __shared__ float Ct[];  // 256 * K floats
-  const int64_t j0 = bid * 256;
-  const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
-  const int ne = nv * K;
-  for (int e = threadIdx.x; e < ne; e += 256) Ct[e] = C[j0 * K + e];
-  __syncthreads();
-  packw_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, bid);
-}
-
 template <int KP>
 __global__ __launch_bounds__(256) void k_packc(const float* __restrict__ C, f32x4* __restrict__ Cq,
                                                float* __restrict__ Csc, int64_t N, int K) {
@@ -982,9 +971,9 @@ __global__ __launch_bounds__(256) void k_packw(const float* __restrict__ C, f32x
 static hipError_t packw(const Shape& s, const float* C, f32x4* Cq, float* Csc, hipStream_t st) {
   const unsigned g = (unsigned)((s.N + 255) / 256);
   if (s.KP == 32)
-    k_packw<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, Cq, Csc, s.N, s.K);
+    k_packw<32><<<g, 256, 0, st>>>(C, Cq, Csc, s.N, s.K);
   else
-    k_packw<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(C, Cq, Csc, s.N, s.K);
+    k_packw<64><<<g, 256, 0, st>>>(C, Cq, Csc, s.N, s.K);
   return hipGetLastError();
 }
 
@@ -1608,7 +1597,7 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
   if ((e = occ((const void*)kg_colpass<KP, XT>, 256, 0, &grids[GS_COL])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_f, 256, 0, &grids[GS_REDF])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_sweep<KP>, 256, 256 * KP * sizeof(float), &grids[GS_SWEEP])) != hipSuccess) return e;
-  if ((e = occ((const void*)kg_packw<KP>, 256, 256 * KP * sizeof(float), &grids[GS_PACKW])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_packw<KP>, 256, 0, &grids[GS_PACKW])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_vgram<KP>, 256, 0, &grids[GS_VGRAM])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_v<KP>, 256, 0, &grids[GS_REDV])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_rowpass<KP, XT>, 256, 0, &grids[GS_ROW])) != hipSuccess) return e;
@@ -1635,7 +1624,7 @@ static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st
   kg_colpass<KP, XT><<<(unsigned)gr[GS_COL], 256, 0, st>>>(t);
   kg_reduce_f<<<(unsigned)gr[GS_REDF], 256, 0, st>>>(t);
   kg_sweep<KP><<<(unsigned)gr[GS_SWEEP], 256, 256 * KP * sizeof(float), st>>>(t);
-  kg_packw<KP><<<(unsigned)gr[GS_PACKW], 256, 256 * KP * sizeof(float), st>>>(t);
+  kg_packw<KP><<<(unsigned)gr[GS_PACKW], 256, 0, st>>>(t);
   kg_vgram<KP><<<(unsigned)gr[GS_VGRAM], 256, 0, st>>>(t);
   kg_reduce_v<KP><<<(unsigned)gr[GS_REDV], 256, 0, st>>>(t);
   kg_rowpass<KP, XT><<<(unsigned)gr[GS_ROW], 256, 0, st>>>(t);
