@@ -126,6 +126,12 @@ int did_default_opts(did_opts* opts);
  * pointer is uploaded) with K coordinates, and draw the initial factors.
  *   X must be finite and >= 0 (eq. opt:nmf takes X in R_+^{M x N}); a negative, NaN or
  *   infinite entry returns DID_EINVAL.
+ *   A device X must be complete when the call is made: the engine reads it on its own
+ *   stream (opts.stream, or a stream it creates), which is not ordered after other streams,
+ *   so the caller synchronises the stream that wrote X first.  A borrowed X (borrow_x = 1)
+ *   must not be written while the handle lives.
+ *   Column-major float32 X (DID_F32 with x_tiled = 0, outside the thin-matrix path) needs
+ *   32 M < 2^32; taller X returns DID_EINVAL and is accepted with x_tiled = 1.
  *   seed selects B^0 and C^0: entry i (column-major index) of B is U[0,1) from
  *   splitmix64 (Steele, Lea & Flood, OOPSLA 2014) keyed by (seed, 1, i), of C keyed by
  *   (seed, 2, i); the draw does not depend on the launch configuration.
@@ -158,9 +164,11 @@ int did_iterate(did_handle h, int32_t n);
 int did_objective(did_handle h, double* f);
 
 /*
- * Copy the current factors out: B (M x K, ld M) and C (K x N, ld K), float32.  Either
- * pointer may be NULL to skip it; each may be host or device memory the caller owns.
- * Synchronises the handle's stream.
+ * Copy the current factors out: the problem's outputs B >= 0 (M x K, ld M) and C >= 0
+ * (K x N, ld K) of eq. opt:nmf, float32, at the current iterate.  Either pointer may be
+ * NULL to skip it; each may be host or device memory the caller owns (the library writes
+ * M K and K N floats and never keeps the pointers).  Synchronises the handle's stream.
+ * Returns DID_EDEVICE if the copy fails (the handle then becomes sticky-failed).
  */
 int did_factors(did_handle h, float* B, float* C);
 
@@ -193,8 +201,11 @@ int did_profile(did_handle h, int32_t enable);
 int did_profile_read(did_handle h, double* ms, int32_t cap, int32_t* n_stages, int64_t* n_iters);
 const char* did_stage_name(int32_t stage);
 
-/* Release every engine-owned resource of h.  NULL is a no-op (returns DID_OK).  A batch
- * member must be removed from its batch first (DID_ESTATE). */
+/* Release every engine-owned resource of h (the state of one problem of eq. opt:nmf: its
+ * copy of X, the factors and the derived buffers), after the queued work has finished.
+ * NULL is a no-op (returns DID_OK).  Also accepted for a sticky-failed handle.  A batch
+ * member must be removed from its batch first (DID_ESTATE); caller memory (a borrowed X,
+ * the stream passed in opts) is never released. */
 int did_free(did_handle h);
 
 /* Device bytes the engine holds for h (X included when the engine owns a copy). */
@@ -313,9 +324,17 @@ int did_server_release(did_server s, int64_t job);
 int did_server_memory(did_server s, int64_t* used, int64_t* peak);
 int did_server_free(did_server s);
 
-/* Message for the calling thread's last failure ("" if none).  Valid until the next
+/* Message for the calling thread's last failure ("" if none): the reason a call returned
+ * a DID_E* code (a violated condition of eq. opt:nmf's input, a shape limit, or the HIP
+ * error behind DID_EDEVICE).  The string is owned by the library and valid until the next
  * call on the same thread. */
 const char* did_last_error(void);
+
+/* Debugging aid for failure handling: the next call on h that checks the handle fails
+ * with DID_EDEVICE as a device error would, and h becomes sticky-failed (every later call
+ * returns DID_EDEVICE; did_free still releases it).  No device work is involved.  Returns
+ * DID_EINVAL for NULL. */
+int did_debug_inject_fault(did_handle h);
 
 #ifdef __cplusplus
 }

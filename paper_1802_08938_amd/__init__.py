@@ -26,7 +26,7 @@ __all__ = [
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_opts", "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step",
     "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
-    "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED",
+    "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED", "did_debug_inject_fault",
 ]
 
 DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
@@ -44,6 +44,7 @@ EXPORTED_SYMBOLS = (
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step", "did_server_poll",
     "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
+    "did_debug_inject_fault",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -137,6 +138,7 @@ def lib():
         "did_server_release": [vp, i64],
         "did_server_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "did_server_free": [vp],
+        "did_debug_inject_fault": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -372,3 +374,8 @@ def did_server_memory(s):
 
 def did_server_free(s):
     _check(lib().did_server_free(s))
+
+
+def did_debug_inject_fault(h):
+    """Make the next checked call on h fail as a device error would (sticky DID_EDEVICE)."""
+    _check(lib().did_debug_inject_fault(h))

@@ -44,11 +44,13 @@ struct did_ctx {
   int64_t* rbounds = nullptr;
   double* fpart = nullptr;
   double* fhist = nullptr;
+  int64_t hist_cap = int64_t(1) << 16;  // entries of fhist (a ring indexed by t)
   double* fobj = nullptr;
   int64_t* tdev = nullptr;  // device copy of t (used by the batched form)
   int* flag = nullptr;
   int64_t t = 0;
   int sticky = 0;
+  int inject_fault = 0;   // did_debug_inject_fault: the next checked call fails as a device error would
   int64_t dev_bytes = 0;  // device memory held by the engine for this instance
   did_batch_ctx* batch = nullptr;
   std::vector<void*> allocs;
@@ -71,6 +73,15 @@ int check_free_handle(did_ctx* h);  // check_handle and not a batch member
 // Row-pass target recorded by did_autotune for the shape class of (M, N, KP, X storage),
 // else the default (4096).
 int tuned_row_blocks(int64_t M, int64_t N, int KP, int xbf16);
+
+// Shared by the single-instance engine and the allocation-free entry point (did_engine.hip).
+int check_shape(int64_t M, int64_t N, int32_t K);
+int make_shape(didk::Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o);
+int row_target(const didk::Shape& s, const did_opts& o);
+void range_params(int64_t N, int64_t nchunks, int n_blocks, int row_blocks, int64_t* T, int64_t* P, int64_t* S);
+hipError_t refresh_b_derived(did_ctx* h);  // pack B and form G = B^T B
+hipError_t pack_c(did_ctx* h);             // pack C after it was set from outside the sweep
+int iterate_mfma(did_ctx* h, int32_t n);   // n iterations of the MFMA path on h's buffers
 
 // Make a device current for the duration of a call.
 struct DeviceGuard {

@@ -63,6 +63,10 @@ int dalloc_bytes(did_ctx* h, void** p, size_t bytes) {
 int check_handle(did_ctx* h) {
   if (!h) return fail(DID_EINVAL, "NULL handle");
   if (h->sticky) return fail(DID_EDEVICE, "handle is in a failed state after an earlier device error");
+  if (h->inject_fault) {  // did_debug_inject_fault: fail as a device error would
+    h->inject_fault = 0;
+    return dev_fail(h, hipErrorLaunchFailure, "injected device fault (did_debug_inject_fault)");
+  }
   return DID_OK;
 }
 
@@ -77,7 +81,7 @@ int check_free_handle(did_ctx* h) {
 
 using namespace didengine;
 
-namespace {
+namespace didengine {
 
 // Kernel stages of one iteration, in launch order.
 constexpr int kStages = 8;
@@ -119,11 +123,11 @@ void release(did_ctx* h) {
   delete h;
 }
 
-// Column ranges of the row pass, in 32-column tiles: P contiguous blocks of tiles (the
-// paper's shards; block p holds tiles [T p / P, T (p+1) / P)), each split into S
-// sub-ranges; W partials are summed in ascending range order.  Returns R + 1 tile bounds.
-std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks, int row_blocks) {
-  const int64_t T = (N + 31) / 32;
+// Parameters of the row pass's column ranges (didk::range_bounds): T tiles, P blocks (the
+// paper's shards), at most S sub-ranges per block; W partials are summed in ascending
+// range order.
+void range_params(int64_t N, int64_t nchunks, int n_blocks, int row_blocks, int64_t* T, int64_t* P, int64_t* S) {
+  *T = (N + 31) / 32;
   const int64_t slab_groups = (nchunks + 3) / 4;
   // about row_blocks blocks of (range, slab group) (default 4096: several rounds of
   // resident blocks, so the last partial round costs little)
@@ -131,16 +135,17 @@ std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks, int r
   int64_t want = (target + slab_groups - 1) / slab_groups;
   // at least 16 tiles (512 columns) per range: the W partials (R x KP x M floats) then
   // stay below a sixteenth of X for K <= 64
-  want = std::max<int64_t>(1, std::min<int64_t>(want, std::max<int64_t>(1, T / 16)));
-  const int64_t P = n_blocks > 0 ? std::min<int64_t>(n_blocks, T) : 1;
-  const int64_t S = std::max<int64_t>(1, (want + P - 1) / P);
-  std::vector<int64_t> b;
-  b.push_back(0);
-  for (int64_t p = 0; p < P; ++p) {
-    const int64_t a0 = T * p / P, a1 = T * (p + 1) / P, n = a1 - a0;
-    const int64_t Sp = std::max<int64_t>(1, std::min<int64_t>(S, n));
-    for (int64_t q = 1; q <= Sp; ++q) b.push_back(a0 + (n * q) / Sp);
-  }
+  want = std::max<int64_t>(1, std::min<int64_t>(want, std::max<int64_t>(1, *T / 16)));
+  *P = n_blocks > 0 ? std::min<int64_t>(n_blocks, *T) : 1;
+  *S = std::max<int64_t>(1, (want + *P - 1) / *P);
+}
+
+// The R + 1 tile bounds of the column ranges.
+std::vector<int64_t> make_ranges(int64_t N, int64_t nchunks, int n_blocks, int row_blocks) {
+  int64_t T, P, S;
+  range_params(N, nchunks, n_blocks, row_blocks, &T, &P, &S);
+  std::vector<int64_t> b((size_t)didk::range_bounds(T, P, S, nullptr) + 1);
+  didk::range_bounds(T, P, S, b.data());
   return b;
 }
 
@@ -174,6 +179,10 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
     return fail(DID_EINVAL, "DID_ALG_DBCD runs on the thin-matrix path only (M <= 16, K <= 8, M <= 8 or K <= 4)");
   if (s.thin && s.xbf16) return fail(DID_EINVAL, "the thin-matrix path stores X as float32 only");
   if (s.thin && o.x_tiled) return fail(DID_EINVAL, "the thin-matrix path reads X as given (x_tiled must be 0)");
+  // The passes address column-major X (and the carried residual) from a wave-uniform base
+  // plus a 32-bit per-lane offset of up to 32 M elements: taller X must use a tiled storage.
+  if (!s.thin && !s.xtiled && 32 * M > (int64_t)0xFFFFFFFF)
+    return fail(DID_EINVAL, "column-major X needs 32 * M < 2^32 (32-bit lane offsets); use x_tiled = 1");
   if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
     return fail(DID_EDEVICE, "thin path: occupancy query failed");
   return DID_OK;
@@ -459,7 +468,66 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
   return DID_OK;
 }
 
-}  // namespace
+// Iterations of the MFMA path on the buffers of h (shared by did_iterate and the
+// allocation-free did_iterate_static).  With a second stream (h->st2) the V partials and
+// their reduction overlap the row pass; without one they run in order on h->st.
+int iterate_mfma(did_ctx* h, int32_t n) {
+  const Shape& s = h->s;
+  hipError_t e;
+  for (int32_t it = 0; it < n; ++it) {
+    hipEvent_t* ev = nullptr;
+    if (h->profiling) {
+      const size_t base = h->prof_events.size();
+      h->prof_events.resize(base + kStages + 1, nullptr);
+      for (int q = 0; q <= kStages; ++q)
+        if ((e = hipEventCreate(&h->prof_events[base + q])) != hipSuccess) return dev_fail(h, e, "profile event");
+      ev = h->prof_events.data() + base;
+    }
+#define DID_MARK(q) \
+  if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
+    DID_MARK(0);
+    if ((e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st)) != hipSuccess)
+      return dev_fail(h, e, "column pass");
+    DID_MARK(1);
+    if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % h->hist_cap), 0.5, h->st)) !=
+        hipSuccess)
+      return dev_fail(h, e, "objective reduce");
+    DID_MARK(2);
+    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    // V = tril(C'C'^T), on the second stream when there is one (overlapped with the row pass
+    // and the W reduction; the B update waits for it)
+    hipStream_t sv = h->st;
+    if (h->st2) {
+      if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess ||
+          (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
+        return dev_fail(h, e, "stream order");
+      sv = h->st2;
+    }
+    if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, sv)) != hipSuccess) return dev_fail(h, e, "V partials");
+    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, sv)) != hipSuccess)
+      return dev_fail(h, e, "V reduce");
+    if (h->st2 && (e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
+    DID_MARK(3);
+    DID_MARK(4);
+    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
+      return dev_fail(h, e, "row pass");
+    DID_MARK(5);
+    if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
+    DID_MARK(6);
+    if (h->st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
+    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st)) != hipSuccess)
+      return dev_fail(h, e, "B update");
+    DID_MARK(7);
+    if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
+      return dev_fail(h, e, "G reduce");
+    DID_MARK(8);
+#undef DID_MARK
+    ++h->t;
+  }
+  return DID_OK;
+}
+
+}  // namespace didengine
 
 extern "C" {
 
@@ -517,7 +585,7 @@ static int iterate_thin(did_ctx* h, int32_t n) {
     if ((e = didk::thin_pass(s, X, h->B, h->G, h->C, h->tpart, mode, h->st)) != hipSuccess)
       return dev_fail(h, e, "thin column pass");
     if ((e = mark(1)) != hipSuccess) return dev_fail(h, e, "profile record");
-    if ((e = didk::thin_reduce(s, h->tpart, h->W, h->V, h->fhist + (h->t % kHistCap), 0.5, mode == 0, h->st)) !=
+    if ((e = didk::thin_reduce(s, h->tpart, h->W, h->V, h->fhist + (h->t % h->hist_cap), 0.5, mode == 0, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "thin reduce");
     // the thin path has no separate sweep, V or row pass: their stages are empty
@@ -547,55 +615,8 @@ int did_iterate(did_handle h, int32_t n) {
   if (rc) return rc;
   if (n < 0) return fail(DID_EINVAL, "n must be >= 0");
   DeviceGuard g(h->dev);
-  const Shape& s = h->s;
-  hipError_t e;
-  if (s.thin) return iterate_thin(h, n);
-  for (int32_t it = 0; it < n; ++it) {
-    hipEvent_t* ev = nullptr;
-    if (h->profiling) {
-      const size_t base = h->prof_events.size();
-      h->prof_events.resize(base + kStages + 1, nullptr);
-      for (int q = 0; q <= kStages; ++q)
-        if ((e = hipEventCreate(&h->prof_events[base + q])) != hipSuccess) return dev_fail(h, e, "profile event");
-      ev = h->prof_events.data() + base;
-    }
-#define DID_MARK(q) \
-  if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
-    DID_MARK(0);
-    if ((e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st)) != hipSuccess)
-      return dev_fail(h, e, "column pass");
-    DID_MARK(1);
-    if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % kHistCap), 0.5, h->st)) !=
-        hipSuccess)
-      return dev_fail(h, e, "objective reduce");
-    DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
-    // V = tril(C'C'^T) on the second stream, overlapped with the row pass and the W
-    // reduction; the B update waits for it
-    if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess || (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
-      return dev_fail(h, e, "stream order");
-    if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, h->st2)) != hipSuccess) return dev_fail(h, e, "V partials");
-    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, h->st2)) != hipSuccess)
-      return dev_fail(h, e, "V reduce");
-    if ((e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
-    DID_MARK(3);
-    DID_MARK(4);
-    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
-      return dev_fail(h, e, "row pass");
-    DID_MARK(5);
-    if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
-    DID_MARK(6);
-    if ((e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
-    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st)) != hipSuccess)
-      return dev_fail(h, e, "B update");
-    DID_MARK(7);
-    if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
-      return dev_fail(h, e, "G reduce");
-    DID_MARK(8);
-#undef DID_MARK
-    ++h->t;
-  }
-  return DID_OK;
+  if (h->s.thin) return iterate_thin(h, n);
+  return iterate_mfma(h, n);
 }
 
 int did_objective(did_handle h, double* f) {
@@ -724,6 +745,12 @@ int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int3
 int did_mem_bytes(did_handle h, int64_t* bytes) {
   if (!h || !bytes) return fail(DID_EINVAL, "NULL argument");
   *bytes = h->dev_bytes;
+  return DID_OK;
+}
+
+int did_debug_inject_fault(did_handle h) {
+  if (!h) return fail(DID_EINVAL, "NULL handle");
+  h->inject_fault = 1;
   return DID_OK;
 }
 

@@ -57,7 +57,29 @@ inline uint64_t stream_key(uint64_t seed, uint64_t stream) {
   return mix64(seed ^ (stream * 0xD1B54A32D192ED03ull));
 }
 
+// Column ranges of the row pass, in 32-column tiles: P contiguous blocks of the T tiles
+// (the paper's shards; block p holds tiles [T p / P, T (p+1) / P)), each split into up to S
+// sub-ranges.  Writes the R + 1 bounds into b (if not null) and returns R.  Shared by the
+// host plan and the device kernel that the allocation-free entry point uses.
+__host__ __device__ inline int64_t range_bounds(int64_t T, int64_t P, int64_t S, int64_t* b) {
+  int64_t r = 0;
+  if (b) b[0] = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    const int64_t a0 = T * p / P, a1 = T * (p + 1) / P, n = a1 - a0;
+    const int64_t Sp = S < n ? (S > 1 ? S : 1) : (n > 1 ? n : 1);
+    for (int64_t q = 1; q <= Sp; ++q) {
+      ++r;
+      if (b) b[r] = a0 + (n * q) / Sp;
+    }
+  }
+  return r;
+}
+
 // ---- launchers (all asynchronous on `st`; they return the launch status) ----
+// zero `bytes` (a multiple of 16) bytes at the 16-byte aligned p with a fill kernel
+hipError_t zero16(void* p, int64_t bytes, hipStream_t st);
+// range_bounds on the device into tb (R + 1 entries)
+hipError_t ranges_on_device(int64_t* tb, int64_t T, int64_t P, int64_t S, hipStream_t st);
 hipError_t fill_uniform(float* out, int64_t n, uint64_t key, hipStream_t st);
 hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t st);
 // Tiled storage of X (the bf16 form, and the float32 form on request): two copies in

@@ -556,6 +556,29 @@ __global__ __launch_bounds__(256) void k_packh(const float* __restrict__ B, int6
   packh_body<KP>(B, M, K, nchunks, Bq, Bsc, blockIdx.x);
 }
 
+__global__ void k_zero16(f32x4* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = f32x4{0, 0, 0, 0};
+}
+
+hipError_t zero16(void* p, int64_t bytes, hipStream_t st) {
+  const int64_t n = bytes / 16;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_zero16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<f32x4*>(p), n);
+  return hipGetLastError();
+}
+
+__global__ void k_ranges(int64_t* tb, int64_t T, int64_t P, int64_t S) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) (void)range_bounds(T, P, S, tb);
+}
+
+hipError_t ranges_on_device(int64_t* tb, int64_t T, int64_t P, int64_t S, hipStream_t st) {
+  k_ranges<<<1, 64, 0, st>>>(tb, T, P, S);
+  return hipGetLastError();
+}
+
 __global__ void k_zero_f32(float* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0f;
 }

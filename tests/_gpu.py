@@ -29,7 +29,9 @@ def announce(msg):
 def device_x(torch, X32):
     """Column-major float32 X (M x N) on the device: a (N, M) row-major tensor."""
     Xc = np.ascontiguousarray(np.asarray(X32, dtype=np.float32).T)
-    return torch.from_numpy(Xc).to("cuda")
+    Xd = torch.from_numpy(Xc).to("cuda")
+    torch.cuda.synchronize()  # the engine reads X on its own stream
+    return Xd
 
 
 def read_factors(h, M, N, K):
@@ -47,6 +49,7 @@ def run_gpu(torch, X32, K, seed=12345, iters=(1,), opts=None, B0=None, C0=None):
     if B0 is not None:
         Bd = torch.from_numpy(np.ascontiguousarray(np.asarray(B0, np.float32).T)).to("cuda")
         Cd = torch.from_numpy(np.ascontiguousarray(np.asarray(C0, np.float32).T)).to("cuda")
+        torch.cuda.synchronize()
         h = did.did_init_from_factors(Xd, M, N, K, Bd, Cd, opts)
     else:
         h = did.did_init_ex(Xd, M, N, K, seed, opts)

@@ -151,3 +151,29 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_column_major_x_lane_offset_bound():
+    """Column-major float32 X is addressed with 32-bit lane offsets of up to 32 M elements:
+    a taller X is refused (before any allocation) unless it is kept in tile order."""
+    _lib_or_skip()
+    M, N, K = 140_000_000, 32, 8  # 32 M >= 2^32
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    with pytest.raises(did.DidError) as ei:
+        did.did_mem_estimate(M, N, K, o)
+    assert ei.value.code == did.DID_EINVAL and "32-bit lane offsets" in str(ei.value)
+    o.x_tiled = 1
+    assert did.did_mem_estimate(M, N, K, o) > 8 * M * N
+    o.x_tiled = 0
+    assert did.did_mem_estimate(134_217_727, N, K, o) > 0  # 32 M = 2^32 - 32: accepted
+    L = did.lib()
+    h = ctypes.c_void_p(7)
+    dummy = (ctypes.c_float * 4)()
+    assert L.did_init_ex(ctypes.cast(dummy, ctypes.c_void_p), M, N, K, 1, ctypes.byref(o), ctypes.byref(h)) == did.DID_EINVAL
+    assert h.value is None
+
+
+def test_fault_injection_needs_a_handle():
+    L = _lib_or_skip()
+    assert L.did_debug_inject_fault(None) == did.DID_EINVAL

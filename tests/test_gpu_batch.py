@@ -229,6 +229,7 @@ def test_server_rejects_oversized_and_thin_jobs():
     so.hbm_budget = 1 << 20
     s = did.did_server_create(so)
     X = torch.ones((1000, 300), device="cuda")
+    torch.cuda.synchronize()
     announce("server rejections")
     try:
         with pytest.raises(did.DidError) as ei:
@@ -260,6 +261,7 @@ def test_autotune_records_and_applies():
         assert did.did_mem_estimate(M, N, K, o) == did.did_mem_estimate(M, N, K, o2)
         assert before > 0
         X = torch.rand((N, M), device="cuda")
+        torch.cuda.synchronize()  # the engine reads X on its own stream
         h = did.did_init_ex(X, M, N, K, 5, o)
         try:
             assert did.did_mem_bytes(h) == did.did_mem_estimate(M, N, K, o)
@@ -280,6 +282,7 @@ def test_memory_estimate_matches_allocation(M, N, K, xd, borrow, tiled):
     o.borrow_x = borrow
     o.x_tiled = tiled
     X = torch.rand((N, M), device="cuda")
+    torch.cuda.synchronize()  # the engine reads X on its own stream
     h = did.did_init_ex(X, M, N, K, 5, o)
     try:
         assert did.did_mem_bytes(h) == did.did_mem_estimate(M, N, K, o, x_on_device=True)

@@ -413,11 +413,13 @@ def test_tiled_x_rejected_on_thin_shapes_and_bad_values():
     ot = did.did_default_opts()
     ot.x_tiled = 1
     Xt = torch.rand((1000, 5), device="cuda")
+    torch.cuda.synchronize()
     with pytest.raises(did.DidError) as ei:
         did.did_init_ex(Xt, 5, 1000, 3, 1, ot)
     assert ei.value.code == did.DID_EINVAL
     ot.x_tiled = 2
     X = torch.rand((1000, 100), device="cuda")
+    torch.cuda.synchronize()
     with pytest.raises(did.DidError) as ei:
         did.did_init_ex(X, 100, 1000, 8, 1, ot)
     assert ei.value.code == did.DID_EINVAL
@@ -538,3 +540,26 @@ def test_stopping_rule_iteration_count_matches_oracle():
     assert t_did is not None and t_dbcd is not None
     assert abs(t_did - t_dbcd) <= 1
     assert abs(t_did - t_or) <= 1, (t_did, t_or)
+
+
+def test_injected_fault_is_sticky():
+    """A faked device error (host-side flag, no device fault) makes the handle
+    sticky-failed: every later call returns DID_EDEVICE and did_free still releases it."""
+    torch = require_gpu()
+    rng = np.random.default_rng(21)
+    X32 = to_f32_colmajor(rng.random((64, 200)))
+    announce("injected sticky fault")
+    h = did.did_init(device_x(torch, X32), 64, 200, 4, 3)
+    try:
+        did.did_iterate(h, 1)
+        did.did_debug_inject_fault(h)
+        with pytest.raises(did.DidError) as ei:
+            did.did_iterate(h, 1)
+        assert ei.value.code == did.DID_EDEVICE and "injected" in str(ei.value)
+        for call in (lambda: did.did_iterate(h, 1), lambda: did.did_objective(h), lambda: read_factors(h, 64, 200, 4),
+                     lambda: did.did_history(h), lambda: did.did_sync(h), lambda: did.did_iterations(h)):
+            with pytest.raises(did.DidError) as ei:
+                call()
+            assert ei.value.code == did.DID_EDEVICE
+    finally:
+        did.did_free(h)
