@@ -324,6 +324,37 @@ int did_server_release(did_server s, int64_t job);
 int did_server_memory(did_server s, int64_t* used, int64_t* peak);
 int did_server_free(did_server s);
 
+/*
+ * Allocation-free form of did_iterate, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  It runs
+ * n >= 0 DID iterations (Alg. 3) from the caller's factors, with the same kernels and the
+ * same iterates as did_init_from_factors(X, M, N, K, B, C, opts) followed by
+ * did_iterate(n), and leaves B^n, C^n in place of B, C.
+ *   X   device pointer, column-major float32 M x N (read as given; 32 M < 2^32), complete
+ *       on opts->stream when the work starts and unchanged until it has finished.
+ *   B   device pointer, M x K column-major float32, read and overwritten.
+ *   C   device pointer, K x N column-major float32, read and overwritten.
+ *   f   NULL, or a device pointer to n doubles: f[t] = f(B^t, C^t) (eq. opt:nmf), the
+ *       objective of the iterate that iteration t+1 starts from.
+ *   opts  NULL for the defaults; n_blocks and row_blocks are honoured; x_dtype must be
+ *       DID_F32, x_tiled 0, refresh_every 1 and algorithm DID_ALG_DID; borrow_x and
+ *       init_scale do not apply.  All work is queued on opts->stream (NULL: the null
+ *       stream) and the call returns without synchronising.
+ * Every intermediate buffer lives in one static device array of DID_STATIC_SCRATCH_BYTES
+ * (128 MiB; each device the library runs on holds it until the process ends): the call
+ * makes no device allocation, no memset and no host round trip.  At K > 32 an instance
+ * needs about 772 bytes per column of X, 1028 bytes per row, and 256 bytes per row for
+ * each of the row pass's column ranges (half of each at K <= 32); one that does not fit
+ * returns DID_EINVAL with the size it needs (fewer ranges, a smaller row_blocks, shrink it).
+ * Shapes of the thin-matrix path (M <= 16, K <= 8, M <= 8 or K <= 4) return DID_EINVAL.
+ * X, B and C are not validated (that would need a host round trip): they must be finite
+ * and nonnegative.  Calls that overlap on one device race on the shared array: the caller
+ * serialises them (one stream, or events).
+ */
+#define DID_STATIC_SCRATCH_BYTES ((int64_t)128 << 20)
+int did_iterate_static(const float* X, int64_t M, int64_t N, int32_t K, float* B, float* C, int32_t n,
+                       const did_opts* opts, double* f);
+
 /* Message for the calling thread's last failure ("" if none): the reason a call returned
  * a DID_E* code (a violated condition of eq. opt:nmf's input, a shape limit, or the HIP
  * error behind DID_EDEVICE).  The string is owned by the library and valid until the next

@@ -27,12 +27,14 @@ __all__ = [
     "did_server_opts", "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step",
     "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
     "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED", "did_debug_inject_fault",
+    "did_iterate_static", "DID_STATIC_SCRATCH_BYTES",
 ]
 
 DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
 DID_F32, DID_BF16 = 0, 1
 DID_ALG_DID, DID_ALG_DBCD = 0, 1
 DID_MAX_K = 64
+DID_STATIC_SCRATCH_BYTES = 128 << 20
 DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED = 0, 1, 2, 3
 
 EXPORTED_SYMBOLS = (
@@ -44,7 +46,7 @@ EXPORTED_SYMBOLS = (
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step", "did_server_poll",
     "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
-    "did_debug_inject_fault",
+    "did_debug_inject_fault", "did_iterate_static",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -139,6 +141,7 @@ def lib():
         "did_server_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "did_server_free": [vp],
         "did_debug_inject_fault": [vp],
+        "did_iterate_static": [vp, i64, i64, i32, vp, vp, i32, ctypes.POINTER(did_opts), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -374,6 +377,14 @@ def did_server_memory(s):
 
 def did_server_free(s):
     _check(lib().did_server_free(s))
+
+
+def did_iterate_static(X, M, N, K, B, C, n, opts=None, f=None):
+    """n iterations from the caller's device factors B, C (overwritten), with every
+    intermediate buffer in the library's static workspace (no device allocation).
+    f: None or a device buffer of n float64 objectives."""
+    op = ctypes.byref(opts) if opts is not None else None
+    _check(lib().did_iterate_static(_ptr(X), M, N, K, _ptr(B), _ptr(C), n, op, _ptr(f)))
 
 
 def did_debug_inject_fault(h):

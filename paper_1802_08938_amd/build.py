@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "did_engine.hip"), os.path.join(CSRC, "did_kernels.hip"),
-           os.path.join(CSRC, "did_thin.hip"), os.path.join(CSRC, "did_batch.hip")]
+           os.path.join(CSRC, "did_thin.hip"), os.path.join(CSRC, "did_batch.hip"),
+           os.path.join(CSRC, "did_static.hip")]
 LIB = os.path.join(HERE, "libdid.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
