@@ -74,10 +74,17 @@ enum {
  *                  and every product stay float32-accurate and the objective is reduced in
  *                  float64, so the engine solves the problem for the rounded data exactly
  *                  as DID_F32 would.  borrow_x does not apply to DID_BF16.
- *   refresh_every  1: the residual is formed afresh from X at the start of every
- *                  iteration, as Alg. 3 does.  Other values are reserved (DID_EINVAL):
- *                  carrying the residual between refreshes would stream and write 8 bytes
- *                  per entry per pass instead of re-reading 2 or 4 bytes of X.
+ *   refresh_every  1 (default): the residual is formed afresh from X at the start of
+ *                  every iteration, as Alg. 3 does.  r > 1: the engine keeps the residual
+ *                  R = X - BC resident (column-major float32, 4 M N more bytes) and
+ *                  carries it incrementally (Section 4, "Incremental Update for b_i": the
+ *                  C sweep's r_j -= b_i delta c_ij and E := E - delta b_i c_i^r), and
+ *                  forms it afresh from X every r-th iteration (t = 0, r, 2r, ...) to win
+ *                  back the drift of the carried float32 residual.  Each pass then reads
+ *                  and writes R (16 bytes per entry per iteration against 2 or 4 bytes of
+ *                  X read twice), so the default is the faster form; the carried form is
+ *                  the paper's own bookkeeping.  Needs the MFMA path (not the thin-matrix
+ *                  shapes), 32 M < 2^32, and is not accepted by the batched form.
  *   init_scale     0: initial B, C are U[0,1) draws as they are.  1: both are then scaled
  *                  by sqrt(alpha), alpha = <X, BC> / ||BC||_F^2, which minimises f over a
  *                  common scale (the experiments' "well scaled initial points").

@@ -268,6 +268,8 @@ int did_batch_add(did_batch b, did_handle h) {
   if (h->dev != b->dev) return fail(DID_EINVAL, "handle and batch are on different devices");
   if (h->s.thin) return fail(DID_EINVAL, "the batched form runs the MFMA passes; thin-matrix shapes are not accepted");
   if (h->algorithm != DID_ALG_DID) return fail(DID_EINVAL, "the batched form runs DID only");
+  if (h->refresh != 1)
+    return fail(DID_EINVAL, "the batched form refreshes the residual every iteration (refresh_every must be 1)");
   if (h->profiling) return fail(DID_ESTATE, "disable profiling before adding a handle to a batch");
   int n_in_group = 0;
   for (did_ctx* m : b->members) n_in_group += group_of(m) == group_of(h);

@@ -39,6 +39,12 @@ struct did_ctx {
   double* W = nullptr;
   float* Wpart = nullptr;
   double* tpart = nullptr;  // thin path: block partials
+  // carried-residual form (refresh_every > 1): the residual R (column-major float32,
+  // M x N), the E-order operands of delta B (layout of Bq) and of delta C (E part of Cq)
+  int refresh = 1;
+  float* Rres = nullptr;
+  _Float16* BqD = nullptr;
+  void* CqD = nullptr;
   int algorithm = DID_ALG_DID;
   int R = 1;
   int64_t* rbounds = nullptr;

@@ -161,7 +161,7 @@ int check_shape(int64_t M, int64_t N, int32_t K) {
 // Option checks and the derived shape, shared by setup and did_mem_estimate.
 int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   if (o.x_dtype != DID_F32 && o.x_dtype != DID_BF16) return fail(DID_EINVAL, "x_dtype must be DID_F32 or DID_BF16");
-  if (o.refresh_every != 1) return fail(DID_EINVAL, "refresh_every must be 1");
+  if (o.refresh_every < 1) return fail(DID_EINVAL, "refresh_every must be >= 1");
   if (o.n_blocks < 0) return fail(DID_EINVAL, "n_blocks must be >= 0");
   if (o.row_blocks < 0) return fail(DID_EINVAL, "row_blocks must be >= 0");
   if (o.x_tiled != 0 && o.x_tiled != 1) return fail(DID_EINVAL, "x_tiled must be 0 or 1");
@@ -183,6 +183,10 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
   // plus a 32-bit per-lane offset of up to 32 M elements: taller X must use a tiled storage.
   if (!s.thin && !s.xtiled && 32 * M > (int64_t)0xFFFFFFFF)
     return fail(DID_EINVAL, "column-major X needs 32 * M < 2^32 (32-bit lane offsets); use x_tiled = 1");
+  if (o.refresh_every > 1 && s.thin)
+    return fail(DID_EINVAL, "refresh_every > 1 (carried residual) runs the MFMA passes only, not the thin-matrix path");
+  if (o.refresh_every > 1 && 32 * M > (int64_t)0xFFFFFFFF)
+    return fail(DID_EINVAL, "the carried residual is column-major: refresh_every > 1 needs 32 * M < 2^32");
   if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
     return fail(DID_EDEVICE, "thin path: occupancy query failed");
   return DID_OK;
@@ -196,7 +200,7 @@ int row_target(const Shape& s, const did_opts& o) {
 }
 
 // Device bytes the engine allocates for an instance (the plan setup follows).
-int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
+int64_t engine_bytes(const Shape& s, int R, bool x_copied, int refresh) {
   const int64_t M = s.M, N = s.N, K = s.K, KP = s.KP, NP = didk::n_pairs(s.KP);
   auto b = [](int64_t n) { return n > 0 ? n : 1; };
   int64_t t = b(4);  // flag
@@ -213,6 +217,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied) {
          b((int64_t)(R + 1) * 8) + b(didk::colpass_blocks(s) * 8);
   }
   t += b(kHistCap * 8) + b(8) + b(8);  // fhist, fobj, tdev
+  if (refresh > 1) t += b(M * N * 4) + b(didk::packed_b_elems(s) * 2) + b(didk::cqd_bytes(s));  // R, BqD, CqD
   return t;
 }
 
@@ -324,6 +329,17 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->fhist, kHistCap))) return rc;
   if ((rc = dalloc(h, &h->fobj, 1))) return rc;
   if ((rc = dalloc(h, &h->tdev, 1))) return rc;
+  h->refresh = o.refresh_every;
+  if (h->refresh > 1) {
+    if ((rc = dalloc(h, &h->Rres, M * N))) return rc;
+    if ((rc = dalloc(h, &h->BqD, didk::packed_b_elems(s)))) return rc;
+    unsigned char* cqd = nullptr;
+    if ((rc = dalloc(h, &cqd, didk::cqd_bytes(s)))) return rc;
+    h->CqD = cqd;
+    if ((e = hipMemsetAsync(h->BqD, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
+        (e = hipMemsetAsync(h->CqD, 0, (size_t)didk::cqd_bytes(s), h->st)) != hipSuccess)
+      return dev_fail(h, e, "buffer setup");
+  }
 
   if ((e = hipMemsetAsync(h->Bq, 0, (size_t)didk::packed_b_elems(s) * 2, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->Bsc, 0, (size_t)didk::bsc_floats(s.KP) * 4, h->st)) != hipSuccess ||
@@ -485,15 +501,23 @@ int iterate_mfma(did_ctx* h, int32_t n) {
     }
 #define DID_MARK(q) \
   if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
+    // carried residual (refresh_every > 1): the column pass refreshes R from X every
+    // refresh_every iterations and otherwise carries it (E = R - delta B C)
+    const bool carry = h->refresh > 1;
     DID_MARK(0);
-    if ((e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st)) != hipSuccess)
-      return dev_fail(h, e, "column pass");
+    if (carry)
+      e = didk::colpass_carry(s, h->X, h->t % h->refresh == 0, h->Cq, h->Bq, h->BqD, h->Bsc, h->H, h->fpart, h->Rres,
+                              h->st);
+    else
+      e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st);
+    if (e != hipSuccess) return dev_fail(h, e, "column pass");
     DID_MARK(1);
     if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % h->hist_cap), 0.5, h->st)) !=
         hipSuccess)
       return dev_fail(h, e, "objective reduce");
     DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st)) != hipSuccess) return dev_fail(h, e, "sweep");
+    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st, carry ? h->CqD : nullptr)) != hipSuccess)
+      return dev_fail(h, e, "sweep");
     // V = tril(C'C'^T), on the second stream when there is one (overlapped with the row pass
     // and the W reduction; the B update waits for it)
     hipStream_t sv = h->st;
@@ -509,13 +533,17 @@ int iterate_mfma(did_ctx* h, int32_t n) {
     if (h->st2 && (e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
     DID_MARK(3);
     DID_MARK(4);
-    if ((e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st)) != hipSuccess)
-      return dev_fail(h, e, "row pass");
+    if (carry)
+      e = didk::rowpass_carry(s, h->Rres, h->Cq, h->CqD, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
+    else
+      e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
+    if (e != hipSuccess) return dev_fail(h, e, "row pass");
     DID_MARK(5);
     if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
     DID_MARK(6);
     if (h->st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
-    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st)) != hipSuccess)
+    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st, carry ? h->BqD : nullptr)) !=
+        hipSuccess)
       return dev_fail(h, e, "B update");
     DID_MARK(7);
     if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
@@ -738,7 +766,7 @@ int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int3
   Shape s{};
   if ((rc = make_shape(s, M, N, K, o))) return rc;
   const int R = s.thin ? 1 : (int)make_ranges(N, s.nchunks, o.n_blocks, row_target(s, o)).size() - 1;
-  *bytes = engine_bytes(s, R, !(x_on_device && o.borrow_x));
+  *bytes = engine_bytes(s, R, !(x_on_device && o.borrow_x), o.refresh_every);
   return DID_OK;
 }
 

@@ -103,8 +103,10 @@ hipError_t scale(float* p, int64_t n, float a, hipStream_t st);
 // applying the incremental B update from the reduced messages W (KP x Mpad, float64) and V
 // (KP x KP, float64) first; writes per-block partials of B^T B into Gpart (n_pairs(KP)
 // doubles per block).  The thin path packs nothing (Bq and Bsc may be null there).
+// With BqD (carried-residual form) the change delta B of the update is also packed there
+// (E-order units and row scales, the layout of Bq).
 hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _Float16* Bq, float* Bsc,
-                   double* Gpart, int update, hipStream_t st);
+                   double* Gpart, int update, hipStream_t st, _Float16* BqD = nullptr);
 int bupdate_blocks(const Shape& s);
 
 // Column pass: E = X - BC per 32-column tile, one partial of sum E^2 per block, and
@@ -114,10 +116,26 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cq, const _Float16
                    float* Hout, double* fpart, int with_h, hipStream_t st);
 int64_t colpass_blocks(const Shape& s);
 
+// Carried-residual form (refresh_every > 1) of the two passes; R is the column-major
+// float32 residual (M x N, ld M), carried across iterations.
+//   colpass_carry: refresh = 1: E = X - B C from the stored X; refresh = 0: E = R - dB C
+//     (dB = the last B update's change, packed in BqD by bupdate); H = B^T E, the f
+//     partials, and E stored into R.
+//   rowpass_carry: E' = R - B dC (dC = C' - C, packed in CqD by the sweep), the W
+//     partials with C' from Cq, and E' stored into R.
+hipError_t colpass_carry(const Shape& s, const void* X, int refresh, const void* Cq, const _Float16* Bq,
+                         const _Float16* BqD, const float* Bsc, float* Hout, double* fpart, float* R,
+                         hipStream_t st);
+hipError_t rowpass_carry(const Shape& s, float* R, const void* Cq, const void* CqD, const float* Csc,
+                         const _Float16* Bq, float* Wpart, const int64_t* tb, int Rn, hipStream_t st);
+
 // Coordinate sweep over the rows of C from H and G = B^T B (float64), in place on C, and
 // repacking of the updated columns into Cq (row scales in Csc).
+// With CqD (carried-residual form) delta C = C' - C is also packed there (E-order units
+// and inverse column scales, CqL<KP>::E units per tile: cqd_bytes).
 hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, float* Csc, const double* G,
-                 hipStream_t st);
+                 hipStream_t st, void* CqD = nullptr);
+inline int64_t cqd_bytes(const Shape& s) { return n_tiles32(s) * cq_units_e(s.KP) * 16; }
 // Pack C into Cq (after C was set from outside the sweep).
 hipError_t packc(const Shape& s, const float* C, void* Cq, float* Csc, hipStream_t st);
 

@@ -152,22 +152,25 @@ struct x_is_tiled {
 // in LDS as Ct[j * K + kk] (j relative to j0); every thread builds whole 16-byte units, so
 // the global stores are coalesced.  All threads of the block call it, after Ct is
 // complete; it takes 256 ints of LDS scratch (cs) from the caller.
-template <int KP>
+// DELTA: the values are a signed change of C (the carried-residual form packs delta C into
+// its own buffer of E-order units only, tile stride CqL<KP>::E): the column scales come
+// from the largest magnitude and no row maxima are gathered.
+template <int KP, bool DELTA = false>
 __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __restrict__ cmax, int64_t j0, int nv,
                                            const float* Ct, int K, int64_t ntiles, int* cs) {
   constexpr int KS = KP / 16;
   constexpr int UE0 = CqL<KP>::E0;
-  constexpr int UT = CqL<KP>::T;
+  constexpr int UT = DELTA ? CqL<KP>::E : CqL<KP>::T;  // units per tile of the target buffer
   constexpr int GE = 8 * KS * 64;  // E groups per block: (tile, s, half, jj)
   const int tid = threadIdx.x;     // cs[j]: scale exponent of column j0 + j
   const int64_t T0 = j0 >> 5;
   {
     float mx = 0.0f;
     if (tid < nv)
-      for (int kk = 0; kk < K; ++kk) mx = fmaxf(mx, Ct[tid * K + kk]);
+      for (int kk = 0; kk < K; ++kk) mx = fmaxf(mx, DELTA ? fabsf(Ct[tid * K + kk]) : Ct[tid * K + kk]);
     cs[tid] = scale_exp(mx);
   }
-  if (tid < K) {  // row maxima over the block's columns (C >= 0: integer order = float order)
+  if (!DELTA && tid < K) {  // row maxima over the block's columns (C >= 0: integer order = float order)
     float mx = 0.0f;
     for (int j = 0; j < nv; ++j) mx = fmaxf(mx, Ct[j * K + tid]);
     if (mx > 0.0f) atomicMax(reinterpret_cast<int*>(cmax) + tid, __float_as_int(mx));
@@ -406,13 +409,17 @@ hipError_t validate(const float* p, int64_t n, int vec4, int* flag, hipStream_t 
 constexpr int kBupRows = 64;      // rows of B per block (one thread each for the update)
 constexpr int kBupThreads = 256;  // threads per block (all of them form the G partial)
 
-template <int KP, bool V_IN_LDS>
+// RW (the carried-residual form): the change delta B = B^{t+1} - B^t of the stored float32
+// values is also packed, as E-order units of -delta B scaled per row with the row's inverse
+// scale, into BqD (the layout of Bq), for the next column pass's update of the residual.
+template <int KP, bool V_IN_LDS, bool RW = false>
 __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
                                              int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
                                              float* __restrict__ bmax, double* __restrict__ Gpart, int update,
-                                             int64_t bid) {
+                                             int64_t bid, _Float16* __restrict__ BqD = nullptr) {
   constexpr int64_t UC = BqL<KP>::C;
   constexpr int US = BqL<KP>::S;
+  __shared__ float dfl[RW ? KP * kBupRows : 1];  // delta B of the stored values, [i][row]
   // V is the same for every row.  The single-instance kernel reads it with uniform loads,
   // which the compiler serves from scalar registers; the grouped kernels (pointers from the
   // descriptor table) stage it in LDS.
@@ -461,9 +468,35 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
         }
         bnew = (float)bn;
         if (update) B[(int64_t)i * M + m] = bnew;
+        if constexpr (RW) dfl[i * kBupRows + tid] = (float)((double)bnew - bold);
+      } else if constexpr (RW) {
+        dfl[i * kBupRows + tid] = 0.0f;
       }
       Bt[tid * (KP + 1) + i] = bnew;
       mx = fmaxf(mx, bnew);
+    }
+    if constexpr (RW) {  // E-order units of -delta B for row m, scaled per row, and the inverse scale
+      if (ok) {
+        float dm = 0.0f;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) dm = fmaxf(dm, fabsf(dfl[i * kBupRows + tid]));
+        const int sd = scale_exp(dm);
+        const float scd = pow2f(sd);
+        const int64_t c = m >> 5;
+        const int r = (int)(m & 31);
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+          if (i < K) {
+            const float y = -dfl[i * kBupRows + tid] * scd;
+            const _Float16 hi = (_Float16)y;
+            const _Float16 lo = (_Float16)(y - (float)hi);
+            const int sq = i >> 4, h = (i >> 3) & 1, t = i & 7, l = r + 32 * h;
+            BqD[(c * UC + (sq * 2 + 0) * 64 + l) * 8 + t] = hi;
+            BqD[(c * UC + (sq * 2 + 1) * 64 + l) * 8 + t] = lo;
+          }
+        }
+        reinterpret_cast<float*>(BqD + (c * UC + US) * 8)[r] = pow2f(-sd);
+      }
     }
     if (Bq && ok) {  // E-order units of row m and its inverse scale
       const int sm = scale_exp(mx);
@@ -504,13 +537,13 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   }
 }
 
-template <int KP>
+template <int KP, bool RW>
 __global__ __launch_bounds__(kBupThreads) void k_bupdate(float* __restrict__ B, int64_t M, int K,
                                                  const double* __restrict__ W, int64_t Mpad,
                                                  const double* __restrict__ V, _Float16* __restrict__ Bq,
                                                  float* __restrict__ bmax, double* __restrict__ Gpart,
-                                                 int update) {
-  bupdate_body<KP, false>(B, M, K, W, Mpad, V, Bq, bmax, Gpart, update, blockIdx.x);
+                                                 int update, _Float16* __restrict__ BqD) {
+  bupdate_body<KP, false, RW>(B, M, K, W, Mpad, V, Bq, bmax, Gpart, update, blockIdx.x, BqD);
 }
 
 // H-order units of the two chunks 2*bid, 2*bid + 1 from B and the column maxima in
@@ -586,18 +619,25 @@ __global__ void k_zero_f32(float* p, int n) {
 int bupdate_blocks(const Shape& s) { return (int)((s.M + kBupRows - 1) / kBupRows); }
 
 hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _Float16* Bq, float* Bsc,
-                   double* Gpart, int update, hipStream_t st) {
+                   double* Gpart, int update, hipStream_t st, _Float16* BqD) {
   const unsigned g = (unsigned)bupdate_blocks(s);
   if (s.thin) {
     Bq = nullptr;
     Bsc = nullptr;
+    BqD = nullptr;
   } else {
     k_zero_f32<<<1, 64, 0, st>>>(Bsc, s.KP);
   }
-  if (s.KP == 32)
-    k_bupdate<32><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update);
-  else
-    k_bupdate<64><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update);
+  if (BqD) {
+    if (s.KP == 32)
+      k_bupdate<32, true><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update, BqD);
+    else
+      k_bupdate<64, true><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update, BqD);
+  } else if (s.KP == 32) {
+    k_bupdate<32, false><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update, nullptr);
+  } else {
+    k_bupdate<64, false><<<g, kBupThreads, 0, st>>>(B, s.M, s.K, W, s.Mpad, V, Bq, Bsc, Gpart, update, nullptr);
+  }
   if (!s.thin) {
     if (s.KP == 32)
       k_packh<32><<<g, 256, 0, st>>>(B, s.M, s.K, s.nchunks, Bq, Bsc);
@@ -624,11 +664,19 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
 // buffer shared by the four waves) and the X tile of chunk c+1 is loaded into registers
 // while chunk c is computed.  H is written as KP x N with row kk contiguous over the
 // columns.
-template <int KP, bool WITH_H, typename XT>
+//
+// RW (the carried-residual form): the E-order operand and the row scales of each chunk
+// come from BqE (delta B in a carried iteration, B in a refresh iteration) while the
+// H-order operand comes from Bq, and E is stored to the column-major float32 residual
+// Rout (rvec4: 16-byte stores are aligned), so that the row pass can carry it on.  The
+// source X is then either the data (refresh) or Rout itself (carry: E = R - delta B C).
+template <int KP, bool WITH_H, typename XT, bool RW = false>
 __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
                                              const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
                                              const float* __restrict__ Bsc, float* __restrict__ Hout,
-                                             double* __restrict__ fpart, int64_t nchunks, int vec4, int64_t bid) {
+                                             double* __restrict__ fpart, int64_t nchunks, int vec4, int64_t bid,
+                                             const _Float16* __restrict__ BqE = nullptr, float* Rout = nullptr,
+                                             int rvec4 = 0) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE = BqL<KP>::E;      // 16-byte units of the E operand per chunk
@@ -678,8 +726,30 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
       const int uu = u < U ? u : U - 1;  // threads past the end reload the last unit
-      const f32x4* src = reinterpret_cast<const f32x4*>(Bq) + c * U + uu;
+      const _Float16* base = Bq;
+      if constexpr (RW) base = (uu < UE || uu >= US) ? BqE : Bq;
+      const f32x4* src = reinterpret_cast<const f32x4*>(base) + c * U + uu;
       stg[v] = *src;
+    }
+  };
+  // the residual store of the carried form: the accumulator layout of E, column-major
+  float* const rtile = RW ? Rout + (tileok ? j0 : 0) * M : nullptr;
+  const uint32_t roff = (uint32_t)(lc * M + 4 * half);
+  const bool rfull = RW && rvec4 && tileok && (j0 + 32 <= N);  // wave-uniform
+  auto rstore = [&](int64_t c, const f32x16& e) {
+    const int64_t m0 = c * 32;
+    if (rfull && m0 + 32 <= M) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<f32x4*>(rtile + m0 + 8 * q + roff) = f32x4{e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]};
+    } else if (tileok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t r = m0 + 8 * q + 4 * half + t;
+          if (colok && r < M) rtile[(int64_t)lc * M + r] = e[4 * q + t];
+        }
     }
   };
   auto sstore = [&](int buf) {
@@ -759,6 +829,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
         for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, acc[4 * q + e]);
       }
     }
+    if constexpr (RW) rstore(c, acc);
     {  // sum of squares of this 32x32 tile in float32, accumulated across tiles in float64
       float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
@@ -854,6 +925,17 @@ __global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, in
   colpass_body<KP, WITH_H, XT>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x);
 }
 
+// The carried-residual form of the column pass (always forms H).
+template <int KP, typename XT>
+__global__ __launch_bounds__(256, 2) void k_colpass_rw(const XT* X, int64_t M, int64_t N, int K,
+                                                       const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
+                                                       const _Float16* __restrict__ BqE,
+                                                       const float* __restrict__ Bsc, float* __restrict__ Hout,
+                                                       double* __restrict__ fpart, int64_t nchunks, int vec4,
+                                                       float* R, int rvec4) {
+  colpass_body<KP, true, XT, true>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x, BqE, R, rvec4);
+}
+
 int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
 
 template <typename XT>
@@ -871,6 +953,35 @@ static void colpass_launch(const Shape& s, const XT* X, const f32x4* C, const _F
     else
       k_colpass<64, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
   }
+}
+
+template <typename XT>
+static void colpass_rw_launch(const Shape& s, const XT* X, int vec4, const f32x4* C, const _Float16* Bq,
+                              const _Float16* BqE, const float* Bsc, float* Hout, double* fpart, float* R,
+                              hipStream_t st) {
+  const unsigned g = (unsigned)colpass_blocks(s);
+  const int rvec4 = (s.M % 4 == 0) && ((reinterpret_cast<uintptr_t>(R) & 15) == 0);
+  if (s.KP == 32)
+    k_colpass_rw<32, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, BqE, Bsc, Hout, fpart, s.nchunks, vec4, R, rvec4);
+  else
+    k_colpass_rw<64, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, BqE, Bsc, Hout, fpart, s.nchunks, vec4, R, rvec4);
+}
+
+hipError_t colpass_carry(const Shape& s, const void* X, int refresh, const void* Cqv, const _Float16* Bq,
+                         const _Float16* BqD, const float* Bsc, float* Hout, double* fpart, float* R,
+                         hipStream_t st) {
+  const f32x4* C = static_cast<const f32x4*>(Cqv);
+  if (!refresh) {  // E = R - delta B C, in place
+    const int v4 = (s.M % 4 == 0) && ((reinterpret_cast<uintptr_t>(R) & 15) == 0);
+    colpass_rw_launch(s, static_cast<const float*>(R), v4, C, Bq, BqD, Bsc, Hout, fpart, R, st);
+  } else if (s.xbf16) {  // E = X - B C from the stored data
+    colpass_rw_launch(s, static_cast<const __bf16*>(X), 0, C, Bq, Bq, Bsc, Hout, fpart, R, st);
+  } else if (s.xtiled) {
+    colpass_rw_launch(s, static_cast<const xtf32*>(X), 0, C, Bq, Bq, Bsc, Hout, fpart, R, st);
+  } else {
+    colpass_rw_launch(s, static_cast<const float*>(X), s.vec4, C, Bq, Bq, Bsc, Hout, fpart, R, st);
+  }
+  return hipGetLastError();
 }
 
 hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const _Float16* Bq, const float* Bsc,
@@ -894,10 +1005,14 @@ hipError_t colpass(const Shape& s, const void* X, const void* Cqv, const _Float1
 // with G_kk = 0 (zero column of B) is skipped.  The block's 256 columns of C (contiguous
 // in memory) are staged through LDS so that global loads and stores are coalesced, and
 // each updated column is repacked into Cq for the row pass and the next column pass.
+// With CqD (the carried-residual form) the block also packs delta C = C' - C (float32
+// difference of the stored values) into CqD's E-order units, for the row pass's update of
+// the carried residual.
 template <int KP, bool G_IN_LDS>
 __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float* __restrict__ C,
                                            f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t N, int K,
-                                           const double* __restrict__ G, int64_t bid) {
+                                           const double* __restrict__ G, int64_t bid,
+                                           f32x4* __restrict__ CqD = nullptr) {
   // G = B^T B (KP x KP, both halves stored) is the same for every lane.  The single-instance
   // kernel reads it directly: uniform addresses into memory the kernel does not write, which
   // the compiler serves with scalar loads, so the FMAs below take G from scalar registers.
@@ -951,18 +1066,30 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
     }
   }
   __syncthreads();
-  for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
   // the packing scratch reuses Gs once the sweep is done (the barrier above): with its own
   // 1 kB the grouped K > 32 kernel would no longer fit two blocks per CU
   int* cs = G_IN_LDS ? reinterpret_cast<int*>(Gs) : cs_own;
+  if (CqD) {  // carried-residual form: C' packed, then Ct := C' - C packed into CqD
+    pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
+    __syncthreads();
+    for (int e = tid; e < ne; e += 256) {
+      const float cn = Ct[e], co = C[j0 * K + e];
+      C[j0 * K + e] = cn;
+      Ct[e] = cn - co;
+    }
+    __syncthreads();
+    pack_block<KP, true>(CqD, nullptr, j0, nv, Ct, K, (N + 31) / 32, cs);
+    return;
+  }
+  for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
   pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
 
 template <int KP>
 __global__ __launch_bounds__(256) void k_sweep(const float* __restrict__ Hin, float* __restrict__ C,
                                                f32x4* __restrict__ Cq, float* __restrict__ Csc, int64_t N, int K,
-                                               const double* __restrict__ G) {
-  sweep_body<KP, false>(Hin, C, Cq, Csc, N, K, G, blockIdx.x);
+                                               const double* __restrict__ G, f32x4* __restrict__ CqD) {
+  sweep_body<KP, false>(Hin, C, Cq, Csc, N, K, G, blockIdx.x, CqD);
 }
 
 // E order of 256 columns of C (block bid), and their contribution to the row maxima.
@@ -1001,14 +1128,15 @@ static hipError_t packw(const Shape& s, const float* C, f32x4* Cq, float* Csc, h
 }
 
 hipError_t sweep(const Shape& s, const float* Hin, float* C, void* Cq, float* Csc, const double* G,
-                 hipStream_t st) {
+                 hipStream_t st, void* CqD) {
   const unsigned g = (unsigned)((s.N + 255) / 256);
   f32x4* q = static_cast<f32x4*>(Cq);
+  f32x4* qd = static_cast<f32x4*>(CqD);
   k_zero_f32<<<1, 64, 0, st>>>(Csc, s.KP);
   if (s.KP == 32)
-    k_sweep<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G);
+    k_sweep<32><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G, qd);
   else
-    k_sweep<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G);
+    k_sweep<64><<<g, 256, 256 * s.K * sizeof(float), st>>>(Hin, C, q, Csc, s.N, s.K, G, qd);
   return packw(s, C, q, Csc, st);
 }
 
@@ -1133,12 +1261,18 @@ hipError_t vgram(const Shape& s, const void* Cq, const float* Csc, double* Vpart
 // Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
-template <int KP, typename XT>
+//
+// RW (the carried-residual form): X is the column-major float32 residual R = X - B C of
+// the column pass, the E-order operand of each tile comes from CqE (delta C, stride
+// CqL<KP>::E units per tile) while the W-order operand comes from Cq, so that
+// E' = R - B delta C, and E' is stored back into R in place.
+template <int KP, typename XT, bool RW = false>
 __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
                                              const f32x4* __restrict__ Cq, const float* __restrict__ Csc,
                                              const _Float16* __restrict__ Bq,
                                              float* __restrict__ Wpart, int64_t Mpad, int64_t nchunks,
-                                             const int64_t* __restrict__ tb, int R, int nsg, int64_t bid) {
+                                             const int64_t* __restrict__ tb, int R, int nsg, int64_t bid,
+                                             const f32x4* __restrict__ CqE = nullptr, float* Rout = nullptr) {
   constexpr int NB = KP / 32;
   constexpr int KS = KP / 16;
   constexpr int UE0 = CqL<KP>::E0;     // 16-byte units of the E'^T A operand per tile
@@ -1181,7 +1315,10 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
-      stg[v] = Cq[T * UT + (u < UT ? u : UT - 1)];
+      if constexpr (RW)
+        stg[v] = u < UE ? CqE[T * UE + u] : Cq[T * UT + (u < UT ? u : UT - 1)];
+      else
+        stg[v] = Cq[T * UT + (u < UT ? u : UT - 1)];
     }
   };
   auto cstore = [&](int buf) {
@@ -1249,6 +1386,20 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
           const f32x4 t4 = ts[2 * q + half];
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, acc[4 * q + e]);
+        }
+      }
+      if constexpr (RW) {  // E' back into the residual, where it was read
+        const int64_t j0 = T * 32;
+        float* rt = Rout + j0 * M;
+        if (rowsfull && j0 + 32 <= hi) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) rt[(int64_t)(8 * (i >> 2) + (i & 3)) * M + loff] = acc[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int64_t j = j0 + row32(i, half);
+            if (rowok && j < hi) Rout[j * M + mrow] = acc[i];
+          }
         }
       }
       // scale of this tile's E' operand: the largest |E'| of the row over the tile (the
@@ -1328,6 +1479,30 @@ __global__ __launch_bounds__(256, 2) void k_rowpass(const XT* __restrict__ X, in
                                                     int64_t Mpad, int64_t nchunks, const int64_t* __restrict__ tb,
                                                     int R, int nsg) {
   rowpass_body<KP, XT>(X, M, N, K, Cq, Csc, Bq, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, 2) void k_rowpass_rw(float* Rr, int64_t M, int64_t N, int K,
+                                                       const f32x4* __restrict__ Cq, const f32x4* __restrict__ CqD,
+                                                       const float* __restrict__ Csc,
+                                                       const _Float16* __restrict__ Bq, float* __restrict__ Wpart,
+                                                       int64_t Mpad, int64_t nchunks, const int64_t* __restrict__ tb,
+                                                       int R, int nsg) {
+  rowpass_body<KP, float, true>(Rr, M, N, K, Cq, Csc, Bq, Wpart, Mpad, nchunks, tb, R, nsg, blockIdx.x, CqD, Rr);
+}
+
+hipError_t rowpass_carry(const Shape& s, float* Rr, const void* Cqv, const void* CqDv, const float* Csc,
+                         const _Float16* Bq, float* Wpart, const int64_t* tb, int R, hipStream_t st) {
+  const f32x4* Cq = static_cast<const f32x4*>(Cqv);
+  const f32x4* CqD = static_cast<const f32x4*>(CqDv);
+  const int nsg = (int)((s.nchunks + 3) / 4);
+  const int R8 = (R + 7) / 8 * 8;
+  const unsigned g = (unsigned)((int64_t)nsg * R8);
+  if (s.KP == 32)
+    k_rowpass_rw<32><<<g, 256, 0, st>>>(Rr, s.M, s.N, s.K, Cq, CqD, Csc, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+  else
+    k_rowpass_rw<64><<<g, 256, 0, st>>>(Rr, s.M, s.N, s.K, Cq, CqD, Csc, Bq, Wpart, s.Mpad, s.nchunks, tb, R, nsg);
+  return hipGetLastError();
 }
 
 template <typename XT>

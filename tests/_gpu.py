@@ -70,3 +70,58 @@ def run_gpu(torch, X32, K, seed=12345, iters=(1,), opts=None, B0=None, C0=None):
 def rel_fro(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+GOLDEN_DIR = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def worst_line(a, o, axis=1, floor_frac=1e-2):
+    """Largest relative error of one row (axis=1: rows of B) or one column (axis=0: columns
+    of C) of a against the oracle's o.  A line whose oracle norm is below floor_frac of the
+    root-mean-square line norm is measured against that floor: such a line carries less
+    than floor_frac^2 of an average line's weight, and a projection [z]_+ flipping at z ~ 0
+    there moves it by rounding only."""
+    a = np.asarray(a, np.float64)
+    o = np.asarray(o, np.float64)
+    d = np.linalg.norm(a - o, axis=axis)
+    n = np.linalg.norm(o, axis=axis)
+    rms = float(np.sqrt(np.mean(n * n))) if n.size else 0.0
+    den = np.maximum(n, floor_frac * rms)
+    den = np.where(den > 0, den, 1.0)
+    return float(np.max(d / den)) if d.size else 0.0
+
+
+def check_factors(B, Bo, C, Co, tol=1e-5, tol_line=1e-4, label=""):
+    """Normwise bars (relative Frobenius error of B and of C) and per-line bars (worst row
+    of B, worst column of C); prints the four numbers and returns them."""
+    eb, ec = rel_fro(B, Bo), rel_fro(C, Co)
+    lb, lc = worst_line(B, Bo, axis=1), worst_line(C, Co, axis=0)
+    print(f"[factors] {label} B {eb:.2e} C {ec:.2e} worst row of B {lb:.2e} worst column of C {lc:.2e}", flush=True)
+    assert eb <= tol, (label, "B normwise", eb)
+    assert ec <= tol, (label, "C normwise", ec)
+    assert lb <= tol_line, (label, "worst row of B", lb)
+    assert lc <= tol_line, (label, "worst column of C", lc)
+    return eb, ec, lb, lc
+
+
+def check_trajectory(fg, fo, tol=1e-4, label=""):
+    """max_t |f_gpu[t] - f_oracle[t]| / f_oracle[t] over the common length."""
+    fg = np.asarray(fg, np.float64)
+    fo = np.asarray(fo, np.float64)
+    assert fg.shape == fo.shape, (label, fg.shape, fo.shape)
+    err = float(np.max(np.abs(fg - fo) / fo))
+    print(f"[trajectory] {label} {len(fo) - 1} iterations: max relative error {err:.2e}", flush=True)
+    assert err <= tol, (label, err)
+    return err
+
+
+def load_golden(case):
+    """Oracle trajectory written by tests/golden/make_trajectories.py (calls only oracle/)."""
+    import json
+    import os
+
+    path = os.path.join(GOLDEN_DIR, f"traj_{case}.json")
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run python tests/golden/make_trajectories.py {case}")
+    with open(path) as fh:
+        return json.load(fh)

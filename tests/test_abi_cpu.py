@@ -177,3 +177,21 @@ def test_column_major_x_lane_offset_bound():
 def test_fault_injection_needs_a_handle():
     L = _lib_or_skip()
     assert L.did_debug_inject_fault(None) == did.DID_EINVAL
+
+
+def test_carried_residual_options_without_device():
+    """refresh_every > 1 keeps the residual resident (4 M N more bytes plus the packed
+    changes of B and C); it needs the MFMA path and 32 M < 2^32; 0 is refused."""
+    _lib_or_skip()
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    base = did.did_mem_estimate(1000, 5000, 20, o)
+    o.refresh_every = 10
+    carried = did.did_mem_estimate(1000, 5000, 20, o)
+    assert carried >= base + 4 * 1000 * 5000
+    for M, N, K, r in ((5, 1000, 3, 2), (1000, 5000, 20, 0), (140_000_000, 32, 8, 2)):
+        o.refresh_every = r
+        o.x_tiled = 1 if M > 1000 else 0
+        with pytest.raises(did.DidError) as ei:
+            did.did_mem_estimate(M, N, K, o)
+        assert ei.value.code == did.DID_EINVAL

@@ -5,14 +5,27 @@ A batch member runs exactly the blocks of its own single-instance launch (throug
 grouped persistent kernels and a replayed hipGraph), so its iterates must equal those of
 the same instance run alone: the tests compare factors and objective histories bitwise,
 after every replay and across membership changes.  The served results must equal the
-same jobs run alone for the same number of iterations (bitwise as well)."""
+same jobs run alone for the same number of iterations (bitwise as well).
+
+Every batch member and every served job is also compared with the FP64 oracle from the
+same initial factors (Alg. 3): factors after one iteration within 1e-5 normwise and 1e-4
+per row of B and column of C, objectives within 1e-4 relative over the iterations run,
+and a served job's factors at retirement within TOL_SERVED_FACTORS of the oracle's after
+the same number of iterations."""
 
 import numpy as np
 import pytest
 
+import oracle
 import paper_1802_08938_amd as did
-from tests._gpu import announce, device_x, read_factors, require_gpu
-from workloads import serving_x, to_f32_colmajor
+from tests._gpu import (announce, check_factors, check_trajectory, device_x, load_golden, read_factors, rel_fro,
+                        require_gpu, worst_line)
+from workloads import as_oracle_input, round_to_bf16, serving_x, to_f32_colmajor, uniform_init
+
+# Served jobs retire after up to 30 iterations; their factors then differ from the oracle's
+# by float32 rounding propagated through that many iterations (normwise, and per line).
+TOL_SERVED_FACTORS = 1e-4
+TOL_SERVED_LINE = 1e-3
 
 pytestmark = pytest.mark.gpu
 
@@ -192,7 +205,7 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
                     Bt = np.empty((K, M), np.float32)
                     Ct = np.empty((N, K), np.float32)
                     did.did_server_result(s, j, Bt, Ct)
-                    res[i] = (it, Bt.T.copy(), Ct.T.copy())
+                    res[i] = (it, Bt.T.copy(), Ct.T.copy(), f)
                     did.did_server_release(s, j)
                 assert st != did.DID_JOB_FAILED
             assert steps < 2000
@@ -203,7 +216,7 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
     finally:
         did.did_server_free(s)
     for i, (M, N, K) in enumerate(jobs):
-        it, B, C = res[i]
+        it, B, C, _ = res[i]
         o = did.did_default_opts()
         o.borrow_x = 1
         h = did.did_init_ex(X[i], M, N, K, 700 + i, o)
@@ -216,6 +229,7 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
             did.did_free(h)
         np.testing.assert_array_equal(B, Bt.T)
         np.testing.assert_array_equal(C, Ct.T)
+        _served_vs_oracle(X[i], M, N, K, 700 + i, it, B.astype(np.float64), C.astype(np.float64), res[i][3], 0)
 
 
 def test_server_rejects_oversized_and_thin_jobs():
@@ -271,20 +285,184 @@ def test_autotune_records_and_applies():
         did.did_autotune_clear()
 
 
-@pytest.mark.parametrize("M,N,K,xd,borrow,tiled", [(300, 2000, 10, did.DID_F32, 1, 0), (300, 2000, 10, did.DID_F32, 0, 0),
-                                                   (130, 777, 64, did.DID_BF16, 0, 0), (5, 1000, 3, did.DID_F32, 1, 0),
-                                                   (16, 4000, 8, did.DID_F32, 0, 0), (130, 777, 40, did.DID_F32, 1, 1)])
-def test_memory_estimate_matches_allocation(M, N, K, xd, borrow, tiled):
+@pytest.mark.parametrize("M,N,K,xd,borrow,tiled,refresh", [
+    (300, 2000, 10, did.DID_F32, 1, 0, 1), (300, 2000, 10, did.DID_F32, 0, 0, 1),
+    (130, 777, 64, did.DID_BF16, 0, 0, 1), (5, 1000, 3, did.DID_F32, 1, 0, 1),
+    (16, 4000, 8, did.DID_F32, 0, 0, 1), (130, 777, 40, did.DID_F32, 1, 1, 1),
+    (130, 777, 40, did.DID_BF16, 0, 0, 10), (300, 2000, 10, did.DID_F32, 1, 0, 3)])
+def test_memory_estimate_matches_allocation(M, N, K, xd, borrow, tiled, refresh):
     torch = require_gpu()
-    announce(f"memory estimate {M}x{N} K={K}")
+    announce(f"memory estimate {M}x{N} K={K} refresh_every={refresh}")
     o = did.did_default_opts()
     o.x_dtype = xd
     o.borrow_x = borrow
     o.x_tiled = tiled
+    o.refresh_every = refresh
     X = torch.rand((N, M), device="cuda")
     torch.cuda.synchronize()  # the engine reads X on its own stream
     h = did.did_init_ex(X, M, N, K, 5, o)
     try:
         assert did.did_mem_bytes(h) == did.did_mem_estimate(M, N, K, o, x_on_device=True)
     finally:
+        did.did_free(h)
+
+
+# members whose 5-iteration oracle trajectory is taken from tests/golden (make_trajectories.py)
+GOLDEN_MEMBERS = {(3809, 2248, 49): "serving_3809x2248_k49", (1868, 40000, 60): "serving_1868x40000_k60"}
+
+
+def _init_factors(M, N, K):
+    B0, C0 = uniform_init(M, N, K, 12345)
+    return B0.astype(np.float32), C0.astype(np.float32)
+
+
+def _make_from_factors(torch, M, N, K, xd, seed):
+    X32 = to_f32_colmajor(serving_x(M, N, K, seed=seed))
+    Xd = device_x(torch, X32)
+    B0, C0 = _init_factors(M, N, K)
+    o = did.did_default_opts()
+    o.x_dtype = did.DID_BF16 if xd == did.DID_BF16 else did.DID_F32
+    o.x_tiled = 1 if xd == TILED else 0
+    o.borrow_x = 1 if xd == did.DID_F32 else 0
+    Bd = torch.from_numpy(np.ascontiguousarray(B0.T)).to("cuda")
+    Cd = torch.from_numpy(np.ascontiguousarray(C0.T)).to("cuda")
+    torch.cuda.synchronize()
+    h = did.did_init_from_factors(Xd, M, N, K, Bd, Cd, o)
+    Xo = round_to_bf16(X32) if xd == did.DID_BF16 else as_oracle_input(X32)
+    return h, Xd, Xo, B0.astype(np.float64), C0.astype(np.float64)
+
+
+def test_batch_members_match_oracle():
+    """Every member of a mixed batch (both K classes, all X storages, the two largest
+    shapes included) against the oracle from the same initial factors: all factors after
+    one batched iteration, and the objective over five."""
+    torch = require_gpu()
+    T = 5
+    announce(f"batch of {len(SHAPES)} vs the oracle")
+    made = [_make_from_factors(torch, M, N, K, xd, i) for i, (M, N, K, xd) in enumerate(SHAPES)]
+    b = did.did_batch_create()
+    try:
+        for m in made:
+            did.did_batch_add(b, m[0])
+        did.did_batch_iterate(b, 1)
+        for m in made:
+            did.did_batch_remove(b, m[0])
+        for i, ((h, _, Xo, B0, C0), (M, N, K, xd)) in enumerate(zip(made, SHAPES)):
+            B1, C1 = read_factors(h, M, N, K)
+            B1o, C1o, _ = oracle.did_run(Xo, B0, C0, 1)
+            check_factors(B1, B1o, C1, C1o, label=f"batch member {i} {M}x{N} K={K} {xd}")
+        for m in made:  # the same members continue in the batch
+            did.did_batch_add(b, m[0])
+        did.did_batch_iterate(b, T - 1)
+        for m in made:
+            did.did_batch_remove(b, m[0])
+        for i, ((h, _, Xo, B0, C0), (M, N, K, xd)) in enumerate(zip(made, SHAPES)):
+            fg = np.append(did.did_history(h), did.did_objective(h))
+            key = GOLDEN_MEMBERS.get((M, N, K))
+            if key is not None:
+                g = load_golden(key)
+                assert g["T"] == T and g["x_storage"] == "f32"
+                fo = np.array(g["f"])
+            else:
+                _, _, fo = oracle.did_run(Xo, B0, C0, T)
+            check_trajectory(fg, fo, label=f"batch member {i} {M}x{N} K={K} {xd}")
+    finally:
+        did.did_batch_free(b)
+        for m in made:
+            did.did_free(m[0])
+
+
+def _served_vs_oracle(X32, M, N, K, seed, it, B, C, f_last, tiled):
+    """A served job's result against the oracle after the same number of iterations from
+    the job's initial factors (read from a solo instance with the same seed)."""
+    torch = require_gpu()
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    o.x_tiled = tiled
+    h = did.did_init_ex(X32, M, N, K, seed, o)
+    try:
+        B0, C0 = read_factors(h, M, N, K)
+    finally:
+        did.did_free(h)
+    Xo = as_oracle_input(X32.cpu().numpy().T)
+    Bo, Co, fo = oracle.did_run(Xo, B0, C0, it)
+    eb, ec = rel_fro(B, Bo), rel_fro(C, Co)
+    lb, lc = worst_line(B, Bo, axis=1), worst_line(C, Co, axis=0)
+    ef = abs(f_last - fo[it - 1]) / fo[it - 1]
+    print(f"[served] {M}x{N} K={K} after {it} iterations: B {eb:.2e} C {ec:.2e} rows {lb:.2e} cols {lc:.2e} "
+          f"f {ef:.2e}", flush=True)
+    tol, tol_line = (1e-5, 1e-4) if it == 1 else (TOL_SERVED_FACTORS, TOL_SERVED_LINE)
+    assert eb <= tol and ec <= tol, (eb, ec)
+    assert lb <= tol_line and lc <= tol_line, (lb, lc)
+    assert ef <= 1e-4, ef
+    return fo
+
+
+def test_server_early_stop_matches_oracle():
+    """A loose stopping tolerance makes jobs retire mid-mix at different iterations; each
+    retired job's factors and last objective equal the oracle's after that many
+    iterations, and the stopping rule holds on the oracle's own trajectory (up to the
+    float32 rounding of the objective near the threshold)."""
+    torch = require_gpu()
+    jobs = [(300, 2000, 10), (500, 1200, 40), (200, 4000, 64), (640, 900, 5), (128, 3000, 33), (350, 2500, 20),
+            (420, 1500, 16), (256, 3100, 48)]
+    so = did.did_server_default_opts()
+    so.max_active = 6
+    so.max_iter = 40
+    so.rel_tol = 1e-1
+    announce(f"server early stop, rel_tol {so.rel_tol}")
+    s = did.did_server_create(so)
+    X, ids, res = {}, [], {}
+    try:
+        for i, (M, N, K) in enumerate(jobs):
+            X[i] = device_x(torch, to_f32_colmajor(serving_x(M, N, K, seed=90 + i)))
+        steps = 0
+        submitted = 0
+        while len(res) < len(jobs):
+            if submitted < len(jobs) and steps % 2 == 0:  # arrivals while others run
+                M, N, K = jobs[submitted]
+                ids.append(did.did_server_submit(s, X[submitted], M, N, K, 800 + submitted))
+                submitted += 1
+            did.did_server_step(s)
+            steps += 1
+            for i, j in enumerate(ids):
+                if i in res:
+                    continue
+                st, it, f, lat, qs = did.did_server_poll(s, j)
+                assert st != did.DID_JOB_FAILED
+                if st == did.DID_JOB_DONE:
+                    M, N, K = jobs[i]
+                    Bt = np.empty((K, M), np.float32)
+                    Ct = np.empty((N, K), np.float32)
+                    did.did_server_result(s, j, Bt, Ct)
+                    res[i] = (it, Bt.T.astype(np.float64), Ct.T.astype(np.float64), f)
+                    did.did_server_release(s, j)
+            assert steps < 1000
+    finally:
+        did.did_server_free(s)
+    its = [res[i][0] for i in range(len(jobs))]
+    print(f"[served] retirement iterations {its}", flush=True)
+    assert len(set(its)) > 1 and max(its) < so.max_iter  # stopped early, at different iterations
+    for i, (M, N, K) in enumerate(jobs):
+        it, B, C, f = res[i]
+        fo = _served_vs_oracle(X[i], M, N, K, 800 + i, it, B, C, f, 0)
+        if it >= 2:  # the oracle's relative change at the retirement iteration is near the tolerance
+            assert abs(fo[it - 2] - fo[it - 1]) <= 1.01 * so.rel_tol * fo[it - 1]
+
+
+def test_batch_rejects_carried_residual_form():
+    torch = require_gpu()
+    announce("batch rejects refresh_every > 1")
+    X = device_x(torch, to_f32_colmajor(serving_x(120, 900, 6, seed=3)))
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    o.refresh_every = 4
+    h = did.did_init_ex(X, 120, 900, 6, 5, o)
+    b = did.did_batch_create()
+    try:
+        with pytest.raises(did.DidError) as ei:
+            did.did_batch_add(b, h)
+        assert ei.value.code == did.DID_EINVAL
+    finally:
+        did.did_batch_free(b)
         did.did_free(h)

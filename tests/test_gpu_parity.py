@@ -18,13 +18,15 @@ import oracle
 import paper_1802_08938_amd as did
 from workloads import as_oracle_input, image_like, large_halfnormal, planted_lowrank, round_to_bf16, to_f32_colmajor
 
-from _gpu import announce, device_x, read_factors, rel_fro, require_gpu, run_gpu
+from _gpu import (announce, check_factors, check_trajectory, device_x, load_golden, read_factors, rel_fro,
+                  require_gpu, run_gpu, worst_line)
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
 TOL_FACTORS = 1e-5
 TOL_OBJ = 1e-4
+TOL_UNSTRUCTURED_CAP = 1e-3  # ceiling of the data-derived bar on ill-conditioned inputs
 
 
 def _mat(rows):
@@ -57,47 +59,52 @@ def test_planted_500x2000_k10_parity_50_iterations():
     out = run_gpu(torch, X32, 10, iters=(1, 50))
     B0, C0 = out["init"]
     B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    check_factors(out[1][0], B1o, out[1][1], C1o, label="planted, 1 iteration")
     _, _, fo = _oracle_from(X32, B0, C0, 50)
-    fg = np.append(out["hist"], out["f"])
-    assert fg.shape == fo.shape
-    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label="planted")
     assert np.all(out[50][0] >= 0) and np.all(out[50][1] >= 0)
 
 
-def test_image_like_784x70000_k16_parity():
-    torch = require_gpu()
-    X, _, _ = image_like(784, 70000, 16, seed=2)
-    X32 = to_f32_colmajor(X)
-    opts = did.did_default_opts()
-    opts.n_blocks = 4
-    announce("image-like 784x70000 K=16, 4 blocks")
-    out = run_gpu(torch, X32, 16, iters=(1, 10), opts=opts)
-    B0, C0 = out["init"]
-    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1, P=4)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
-    _, _, fo = _oracle_from(X32, B0, C0, 10, P=4)
-    fg = np.append(out["hist"], out["f"])
-    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+def _golden_case(case):
+    from tests.golden.make_trajectories import data, initial_factors
+
+    g = load_golden(case)
+    X32, Xo, K, P, T, bf16, _ = data(case)
+    assert (g["M"], g["N"], g["K"], g["P"], g["T"]) == (X32.shape[0], X32.shape[1], K, P, T)
+    if abs(float(np.sum(Xo)) - g["x_sum"]) > 1e-9 * abs(g["x_sum"]):
+        print(f"[golden] {case}: data checksum differs from the golden's (host BLAS rounding); "
+              "the trajectory bar still applies", flush=True)
+    B0, C0 = initial_factors(X32.shape[0], X32.shape[1], K)
+    return g, X32, Xo, K, P, T, bf16, B0, C0
 
 
-@pytest.mark.parametrize("blocks", [1])
-def test_large_slice_5000x15625_k50_parity(blocks):
+def _sampled_golden_factors(g, out):
+    """Sampled columns of C and rows of B after one iteration against the golden's."""
+    cols, rows = g["sample_cols"], g["sample_rows"]
+    C1o = np.array(g["C1_cols"]).T
+    B1o = np.array(g["B1_rows"])
+    check_factors(out[1][0][rows], B1o, out[1][1][:, cols], C1o, label=f"{g['case']}, sampled, 1 iteration")
+
+
+@pytest.mark.parametrize("case", ["image_like_p4", "large_slice_b1"])
+def test_named_workloads_parity_50_iterations(case):
+    """The image-like workload (784 x 70000, K = 16, 4 blocks) and slices of the large one
+    (5000 x 15625 and 5000 x 62500, K = 50, 1 and 4 blocks) from the same initial factors as
+    the oracle: factors after one iteration (all of them, or for the 4-block slice sampled
+    columns and rows the oracle recorded) and the objective over 50 iterations."""
     torch = require_gpu()
-    X, _ = large_halfnormal(5000, 1_000_000, 50, seed=3, n_blocks=64, take_blocks=blocks)
-    X32 = to_f32_colmajor(X)
-    del X
-    announce(f"large slice 5000x{X32.shape[1]} K=50")
-    out = run_gpu(torch, X32, 50, iters=(1, 3))
-    B0, C0 = out["init"]
-    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
-    _, _, fo = _oracle_from(X32, B0, C0, 3)
-    fg = np.append(out["hist"], out["f"])
-    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+    g, X32, Xo, K, P, T, _, B0, C0 = _golden_case(case)
+    o = did.did_default_opts()
+    o.n_blocks = P
+    announce(f"{case}: {X32.shape[0]}x{X32.shape[1]} K={K} P={P}, {T} iterations")
+    out = run_gpu(torch, X32, K, iters=(1, T), opts=o, B0=B0.astype(np.float32), C0=C0.astype(np.float32))
+    np.testing.assert_array_equal(out["init"][0], B0)
+    if "sample_cols" in g:
+        _sampled_golden_factors(g, out)
+    else:
+        B1o, C1o, _ = oracle.did_run(Xo, B0, C0, 1, P=P)
+        check_factors(out[1][0], B1o, out[1][1], C1o, label=f"{case}, 1 iteration")
+    check_trajectory(np.append(out["hist"], out["f"]), g["f"], label=case)
 
 
 @pytest.mark.parametrize("M,N,K", [
@@ -120,11 +127,9 @@ def test_edge_shapes_parity(M, N, K):
     out = run_gpu(torch, X32, K, iters=(1, 5))
     B0, C0 = out["init"]
     B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"edge {M}x{N} K={K}")
     _, _, fo = _oracle_from(X32, B0, C0, 5)
-    fg = np.append(out["hist"], out["f"])
-    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"edge {M}x{N} K={K}")
 
 
 def _fp32_sensitivity(X32, B0, C0, draws=3):
@@ -145,17 +150,21 @@ def _fp32_sensitivity(X32, B0, C0, draws=3):
 @pytest.mark.parametrize("M,N,K", [(100, 300, 32), (130, 260, 64), (70, 129, 33)])
 def test_unstructured_data_within_fp32_conditioning(M, N, K):
     """Dense U[0,2] data with K close to M/3 is ill-conditioned for NMF: the tolerance is
-    max(1e-5, 10 x the oracle's own movement under float32-sized perturbations of X)."""
+    max(1e-5, 10 x the oracle's own movement under float32-sized perturbations of X), capped
+    at 1e-3; the test prints the bar it used."""
     torch = require_gpu()
     rng = np.random.default_rng(M * 7 + N + K)
     X32 = to_f32_colmajor(rng.random((M, N)) * 2.0)
     announce(f"unstructured data M={M} N={N} K={K}")
     out = run_gpu(torch, X32, K, iters=(1,))
     B0, C0 = out["init"]
-    tol = max(TOL_FACTORS, 10.0 * _fp32_sensitivity(X32, B0, C0))
+    sens = _fp32_sensitivity(X32, B0, C0)
+    tol = min(TOL_UNSTRUCTURED_CAP, max(TOL_FACTORS, 10.0 * sens))
     B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= tol
-    assert rel_fro(out[1][1], C1o) <= tol
+    eb, ec = rel_fro(out[1][0], B1o), rel_fro(out[1][1], C1o)
+    print(f"[unstructured] {M}x{N} K={K}: oracle float32 sensitivity {sens:.2e}, bar {tol:.2e}, "
+          f"B {eb:.2e} C {ec:.2e}", flush=True)
+    assert eb <= tol and ec <= tol
 
 
 def _badly_scaled(M, N, K, seed):
@@ -242,8 +251,7 @@ def test_zero_column_of_b_is_skipped_on_gpu():
     out = run_gpu(torch, X32, K, iters=(1,), B0=B0.astype(np.float32), C0=C0.astype(np.float32))
     np.testing.assert_array_equal(out[1][1][2], C0.astype(np.float32)[2].astype(np.float64))
     B1o, C1o, _ = _oracle_from(X32, out["init"][0], out["init"][1], 1)
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
+    check_factors(out[1][0], B1o, out[1][1], C1o, label="zero column of B")
 
 
 def test_rejects_negative_and_nonfinite_x():
@@ -358,11 +366,9 @@ def test_bf16_storage_form_matches_oracle_on_rounded_x(M, N, K):
     out = run_gpu(torch, X32, K, iters=(1, 10), opts=o)
     B0, C0 = out["init"]
     B1o, C1o, _ = oracle.did_run(Xr, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"bf16 {M}x{N} K={K}")
     _, _, fo = oracle.did_run(Xr, B0, C0, 10)
-    fg = np.append(out["hist"], out["f"])
-    assert np.max(np.abs(fg - fo) / fo) <= TOL_OBJ
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"bf16 {M}x{N} K={K}")
 
 
 @pytest.mark.parametrize("M,N,K", [(500, 2000, 10), (130, 777, 64), (97, 1234, 33), (64, 4001, 7)])
@@ -460,8 +466,7 @@ def test_thin_path_parity(M, N, K):
     out = run_gpu(torch, X32, K, iters=(1, 20))
     B0, C0 = out["init"]
     B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
-    assert rel_fro(out[1][0], B1o) <= TOL_FACTORS
-    assert rel_fro(out[1][1], C1o) <= TOL_FACTORS
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"thin {M}x{N} K={K}")
     _, _, fo = _oracle_from(X32, B0, C0, 20)
     fg = np.append(out["hist"], out["f"])
     # M = 1, K = 1 factors exactly, so f falls to its float32 rounding floor (about
@@ -563,3 +568,67 @@ def test_injected_fault_is_sticky():
             assert ei.value.code == did.DID_EDEVICE
     finally:
         did.did_free(h)
+
+
+
+# ---------------------------------------------------------------- carried residual (a7)
+# refresh_every = r > 1 keeps R = X - BC resident and carries it (the C sweep's
+# r_j -= b_i delta c_ij and E := E - delta b_i c_i^r of Section 4), refreshing it from X
+# every r-th iteration.  In exact arithmetic the iterates are those of Alg. 3, so the
+# oracle (which carries its own float64 residual) is the reference at the same bars.
+
+@pytest.mark.parametrize("M,N,K,storage,r", [(300, 2000, 10, "f32", 3), (130, 777, 64, "f32", 10),
+                                             (97, 1234, 33, "bf16", 10), (200, 3001, 20, "f32-tiled", 4),
+                                             (37, 45, 3, "f32", 2)])
+def test_carried_residual_matches_oracle(M, N, K, storage, r):
+    torch = require_gpu()
+    rng = np.random.default_rng(11 * M + N + K)
+    X32 = to_f32_colmajor(rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N))))
+    Xo = round_to_bf16(X32) if storage == "bf16" else as_oracle_input(X32)
+    o = did.did_default_opts()
+    o.refresh_every = r
+    o.x_dtype = did.DID_BF16 if storage == "bf16" else did.DID_F32
+    o.x_tiled = 1 if storage == "f32-tiled" else 0
+    T = 3 * r + 2  # several refresh cycles and carried stretches
+    announce(f"carried residual {M}x{N} K={K} {storage} refresh_every={r}, {T} iterations")
+    out = run_gpu(torch, X32, K, iters=(1, T), opts=o)
+    B0, C0 = out["init"]
+    B1o, C1o, _ = oracle.did_run(Xo, B0, C0, 1)
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"carried r={r} {M}x{N} K={K}, 1 iteration")
+    BTo, CTo, fo = oracle.did_run(Xo, B0, C0, T)
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"carried r={r} {M}x{N} K={K}")
+    check_factors(out[T][0], BTo, out[T][1], CTo, tol=1e-4, tol_line=1e-3,
+                  label=f"carried r={r} {M}x{N} K={K}, {T} iterations")
+
+
+@pytest.mark.parametrize("r", [1, 10])
+def test_bf16_large_slice_refresh_every_parity_50_iterations(r):
+    """The precision form on the large workload's first column block (5000 x 15625, K = 50,
+    X stored as bf16), refreshing the residual every iteration or carrying it with a
+    refresh every 10 iterations: the objective over 50 iterations against the oracle run
+    on bf16(X) (which carries its float64 residual throughout)."""
+    torch = require_gpu()
+    g, X32, Xo, K, P, T, bf16, B0, C0 = _golden_case("large_slice_b1_bf16")
+    assert bf16
+    o = did.did_default_opts()
+    o.x_dtype = did.DID_BF16
+    o.refresh_every = r
+    announce(f"bf16 large slice, refresh_every={r}, {T} iterations")
+    out = run_gpu(torch, X32, K, iters=(T,), opts=o, B0=B0.astype(np.float32), C0=C0.astype(np.float32))
+    check_trajectory(np.append(out["hist"], out["f"]), g["f"], label=f"bf16 slice refresh_every={r}")
+
+
+def test_carried_residual_rejections():
+    torch = require_gpu()
+    announce("carried residual rejections")
+    X = device_x(torch, np.ones((5, 300), np.float32))
+    o = did.did_default_opts()
+    o.refresh_every = 2
+    with pytest.raises(did.DidError) as ei:  # thin-matrix shape
+        did.did_init_ex(X, 5, 300, 3, 1, o)
+    assert ei.value.code == did.DID_EINVAL
+    o.refresh_every = 0
+    X2 = device_x(torch, np.ones((64, 300), np.float32))
+    with pytest.raises(did.DidError) as ei:
+        did.did_init_ex(X2, 64, 300, 3, 1, o)
+    assert ei.value.code == did.DID_EINVAL
