@@ -9,7 +9,17 @@ Prints one JSON line:
   value          iterations/s of the whole job (inputs resident in HBM at the start),
   roofline       the dominant kernel (column or row pass) against the roofline that bounds
                  it: HBM (algorithmic bytes against 8 TB/s) or the float32-accurate MFMA
-                 peak of its split-fp16 products, whichever time floor is larger,
+                 peak of its split-fp16 products, whichever time floor is larger; with
+                 iter_frac (the whole iteration's algorithmic bytes against 8 TB/s) and
+                 limiter (what the committed SQ counters show stalls the pass),
+  precision_form X stored as bf16 with the residual refreshed every iteration or carried
+                 and refreshed every 10: iterations/s, speedup over the plain form, and the
+                 objective error against the FP64 oracle (original X and bf16(X)) on the
+                 first column block over 50 iterations,
+  batched_form   48 served-distribution jobs advanced as one batch against one after
+                 another: instance-iterations/s and speedup,
+  served_form    a shortened served run (300 jobs of the Poisson schedule): solves/s,
+                 p50/p99 latency, queue depth, share of jobs stopped by the 1e-4 rule,
   cpu_baseline   the FP64 oracle timed on a bounded sample of the same workload.
 
 ``--workload paper`` runs the experiments' synthetic shape instead (M = 5, K = 3,
@@ -56,6 +66,9 @@ PEAK_F16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 (and bf16) matrix peak
 SPLIT_PRODUCTS = 3
 PEAK_SPLIT_TFLOPS = PEAK_F16_MFMA_TFLOPS / SPLIT_PRODUCTS
 PEAK_HBM_GBS = 8000.0
+# the arithmetic the path computes in: products float32-accurate from three fp16 MFMAs of
+# scaled two-way splits with float32 accumulation; sweep, B update and objective in float64
+DTYPE = "f32 (split-fp16x3 MFMA, fp32 accumulate; fp64 sweep, B update, objective)"
 
 WORKLOADS = {
     "large": dict(M=5000, N=1_000_000, K=50, n_blocks=64,
@@ -137,6 +150,58 @@ def measured_traffic(kernel, workload):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def sq_limiter(kernel):
+    """What limits a pass, from the committed SQ counter summary (when it was taken on the
+    current kernel sources): MFMA busy fraction, non-MFMA VALU instructions per MFMA and
+    the share of wave cycles spent waiting.  None when the summary is stale or absent."""
+    path = os.path.join(ROOT, "profiles", "sq_counters_large.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"kernel source sha256[:16]: {kernel_source_hash()}" not in text:
+        return None
+    col = 1 if kernel == "column_pass" else 2
+    vals = {}
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 3:
+            vals[cells[0]] = cells[col]
+    try:
+        mfma = float(vals["MFMA busy per SIMD, fraction of busy cycles (`SQ_VALU_MFMA_BUSY_CYCLES` / 1024 / busy cycles)"])
+        valu = float(vals["non-MFMA VALU instructions per MFMA"])
+        wait = float(vals["`SQ_WAIT_ANY` / `SQ_WAVE_CYCLES`"])
+        clk = float(vals["implied clock, GHz (busy cycles / duration)"])
+    except (KeyError, ValueError):
+        return None
+    # one wave64 VALU instruction occupies the SIMD 4 cycles, an MFMA 32x32x16 32 cycles
+    valu_busy = mfma * valu * 4.0 / 32.0
+    kind = "issue (MFMA + VALU work)" if mfma + valu_busy >= 0.8 else "latency (waves waiting)"
+    return {"label": kind, "mfma_busy": mfma, "valu_per_mfma": valu, "valu_busy_est": round(valu_busy, 3),
+            "wait_frac": wait, "clock_ghz": clk, "source": "profiles/sq_counters_large.md"}
+
+
+def timed_iterations(torch, did, h, stream, warmup, steps, profile_iters=3):
+    """ms per iteration over `steps` timed iterations (HIP events on the engine's stream,
+    no per-stage events), then per-stage milliseconds from `profile_iters` profiled ones."""
+    did.did_iterate(h, warmup)
+    did.did_sync(h)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    did.did_iterate(h, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    stages, n_it = {}, 0
+    if profile_iters:
+        did.did_profile(h, True)
+        did.did_iterate(h, profile_iters)
+        stages, n_it = did.did_profile_read(h)
+        did.did_profile(h, False)
+    return ms, stages, max(n_it, 1)
 
 
 def make_input(torch, name, cfg):
@@ -321,7 +386,7 @@ def run_paper_shape(args, torch, did):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32 data; fp64 sweep, messages and objective (thin path, no MFMA)",
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "M": M, "N": N, "K": K, "n_blocks": cfg["n_blocks"]},
         "stage_ms_per_iter": {k: round(v / max(n_it, 1), 4) for k, v in stages.items()},
@@ -391,7 +456,7 @@ def run_nsweep(args, torch, did):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "M": M, "N": last["N"], "K": K, "n_blocks": cfg["n_blocks"]},
         "sweep": rows,
@@ -411,14 +476,14 @@ def _job_inputs(torch, jobs, x_dtype):
     return out
 
 
-def run_batch(args, torch, did):
-    """Plain form (instances one after another) against the batched form, same jobs."""
+def batch_measure(torch, did, n_jobs, T, W, x_given):
+    """Plain form (instances one after another) against the batched form on the same jobs
+    from the served workload's shape distribution; returns a dict of rates."""
     import numpy as np
 
     from workloads import serving_jobs
 
-    cfg = WORKLOADS["batch"]
-    jobs = serving_jobs(cfg["jobs"], seed=5)
+    jobs = serving_jobs(n_jobs, seed=5)
     log(f"batch: generating {len(jobs)} inputs")
     Xs = _job_inputs(torch, jobs, did.DID_F32)
     stream = torch.cuda.Stream()
@@ -429,12 +494,11 @@ def run_batch(args, torch, did):
         for j, X in zip(jobs, Xs):
             o = did.did_default_opts()
             o.borrow_x = 1
-            o.x_tiled = 0 if args.x_given else 1
+            o.x_tiled = 0 if x_given else 1
             o.stream = stream.cuda_stream
             hs.append(did.did_init_ex(X, j["M"], j["N"], j["K"], 1000 + j["seed"], o))
         return hs
 
-    T, W = args.steps, args.warmup
     flops_it = sum(8.0 * j["M"] * j["N"] * j["K"] for j in jobs)
     # plain form: each instance alone, one after another, on one stream
     hs = make_all()
@@ -479,47 +543,56 @@ def run_batch(args, torch, did):
         did.did_batch_free(b)
         for h in hs:
             did.did_free(h)
+    del Xs
+    torch.cuda.empty_cache()
     n_it = len(jobs) * T
+    return {"jobs": len(jobs), "iterations_per_job": T, "ms_per_batched_iteration": round(batch_ms / T, 4),
+            "instance_iter_s": round(n_it / (batch_ms / 1e3), 2),
+            "plain_form_instance_iter_s": round(n_it / (plain_ms / 1e3), 2),
+            "speedup_vs_plain_form": round(plain_ms / batch_ms, 3),
+            "batched_tflops_fp32_equiv": round(flops_it * T / (batch_ms / 1e3) / 1e12, 2),
+            "plain_tflops_fp32_equiv": round(flops_it * T / (plain_ms / 1e3) / 1e12, 2),
+            "results_bitwise_equal_to_plain": bool(same),
+            "objective_error_vs_plain_form": 0.0 if same else None,
+            "x_layout": "as given (column-major)" if x_given else "tile order (x_tiled=1)"}
+
+
+def run_batch(args, torch, did):
+    cfg = WORKLOADS["batch"]
+    r = batch_measure(torch, did, cfg["jobs"], args.steps, args.warmup, args.x_given)
     line = {
         "metric": METRIC,
-        "value": round(n_it / (batch_ms / 1e3), 2),
+        "value": r["instance_iter_s"],
         "unit": "instance-iter/s",
         "n_gpus": 1,
-        "steps": T,
-        "warmup": W,
-        "ms_per_step": round(batch_ms / T, 4),
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_batched_iteration"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE,
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "jobs": len(jobs),
-                   "x_layout": "as given (column-major)" if args.x_given else "tile order (x_tiled=1)"},
-        "plain_form_instance_iter_s": round(n_it / (plain_ms / 1e3), 2),
-        "speedup_vs_plain_form": round(plain_ms / batch_ms, 3),
-        "batched_tflops_fp32_equiv": round(flops_it * T / (batch_ms / 1e3) / 1e12, 2),
-        "plain_tflops_fp32_equiv": round(flops_it * T / (plain_ms / 1e3) / 1e12, 2),
-        "results_bitwise_equal_to_plain": bool(same),
-        "objective_error_vs_plain_form": 0.0 if same else None,
+        "config": {"workload": cfg["desc"], "jobs": r["jobs"], "x_layout": r["x_layout"]},
     }
+    line.update({k: v for k, v in r.items() if k not in ("jobs", "x_layout")})
     emit(torch, line)
 
 
-def run_serve(args, torch, did):
-    """Poisson arrivals into the server; latency from the scheduled arrival to retirement."""
+def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1e-4):
+    """Poisson arrivals (200 jobs/s) into the server; latency from the scheduled arrival to
+    retirement.  Returns a dict of throughput, latency and queue figures."""
     import numpy as np
 
     from workloads import serving_jobs, serving_x_device
 
-    cfg = WORKLOADS["serve"]
-    n_jobs = args.serve_jobs or cfg["jobs"]
     jobs = serving_jobs(n_jobs, seed=5, rate=200.0)
     so = did.did_server_default_opts()
     so.hbm_budget = 200 << 30
-    so.max_active = args.serve_slots
-    so.max_iter = 50
-    so.rel_tol = 1e-4
-    so.x_tiled = 1 if args.serve_tiled else 0  # float32 jobs keep X in tile order
+    so.max_active = slots
+    so.max_iter = max_iter
+    so.rel_tol = rel_tol
+    so.x_tiled = 1 if tiled else 0  # float32 jobs keep X in tile order
     stream = torch.cuda.Stream()
     so.stream = stream.cuda_stream
     srv = did.did_server_create(so)
@@ -545,7 +618,7 @@ def run_serve(args, torch, did):
                     X = serving_x_device(torch, j["M"], j["N"], j["K"], j["seed"], generator=gen)
                 side.synchronize()
                 jid = did.did_server_submit(srv, X, j["M"], j["N"], j["K"], 1000 + j["seed"],
-                                            did.DID_BF16 if args.serve_bf16 else did.DID_F32)
+                                            did.DID_BF16 if bf16 else did.DID_F32)
                 live[jid] = (i, X, time.perf_counter() - t0)
                 queued_bytes += 4 * j["M"] * j["N"]
             running, queued, fin = did.did_server_step(srv)
@@ -576,37 +649,123 @@ def run_serve(args, torch, did):
         used, peak = did.did_server_memory(srv)
     finally:
         did.did_server_free(srv)
+    torch.cuda.empty_cache()
     lat = np.array(lat)
+    iters = np.array(iters)
     flops = sum(8.0 * jobs[i]["M"] * jobs[i]["N"] * jobs[i]["K"] for i in range(n_jobs))
+    return {"jobs": n_jobs, "slots": slots, "x_storage": "bf16" if bf16 else "f32",
+            "x_layout": "tile order" if (bf16 or tiled) else "as given (column-major)",
+            "solves_per_s": round(n_jobs / wall, 2), "wall_s": round(wall, 3), "steps": steps,
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+            "latency_mean_s": round(float(lat.mean()), 4),
+            "queue_wait_p50_s": round(float(np.percentile(qwait, 50)), 4),
+            "iterations_mean": round(float(np.mean(iters)), 2),
+            "share_stopped_by_rel_tol": round(float(np.mean(iters < max_iter)), 4),
+            "rel_tol": rel_tol, "max_iter": max_iter,
+            "arrival_span_s": round(jobs[-1]["t"], 3),
+            "max_queue_depth": max_queue,
+            "mean_running": round(float(np.mean(occ)), 2),
+            "peak_budget_bytes": peak,
+            "offered_tflops_fp32_equiv_at_mean_iters": round(flops / len(jobs) * float(np.mean(iters)) * 200.0 / 1e12,
+                                                             1)}
+
+
+def run_serve(args, torch, did):
+    cfg = WORKLOADS["serve"]
+    n_jobs = args.serve_jobs or cfg["jobs"]
+    r = serve_measure(torch, did, n_jobs, args.serve_slots, args.serve_bf16, args.serve_tiled)
     line = {
         "metric": METRIC,
-        "value": round(n_jobs / wall, 2),
+        "value": r["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": r["steps"],
         "warmup": 0,
-        "ms_per_step": round(wall * 1e3 / max(steps, 1), 4),
+        "ms_per_step": round(r["wall_s"] * 1e3 / max(r["steps"], 1), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": cfg["desc"] + ("; X stored as bf16" if args.serve_bf16 else ""), "jobs": n_jobs,
-                   "slots": so.max_active, "x_storage": "bf16" if args.serve_bf16 else "f32",
-                   "x_layout": "tile order" if (args.serve_bf16 or args.serve_tiled) else "as given (column-major)"},
-        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
-        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
-        "latency_mean_s": round(float(lat.mean()), 4),
-        "queue_wait_p50_s": round(float(np.percentile(qwait, 50)), 4),
-        "iterations_mean": round(float(np.mean(iters)), 2),
-        "arrival_span_s": round(jobs[-1]["t"], 3),
-        "wall_s": round(wall, 3),
-        "max_queue_depth": max_queue,
-        "mean_running": round(float(np.mean(occ)), 2),
-        "peak_budget_bytes": peak,
-        "offered_tflops_fp32_equiv_at_mean_iters": round(flops / len(jobs) * np.mean(iters) * 200.0 / 1e12, 1),
+                   "slots": r["slots"], "x_storage": r["x_storage"], "x_layout": r["x_layout"]},
     }
+    line.update({k: v for k, v in r.items() if k not in ("jobs", "slots", "x_storage", "x_layout", "steps")})
     emit(torch, line)
+
+
+def precision_form(torch, did, X, M, N, K, n_blocks, plain_ms, steps):
+    """The precision form on the large workload: X stored as bf16, the residual refreshed
+    every iteration (refresh_every 1) or carried with a refresh every 10 iterations
+    (refresh_every 10); iterations/s and speedup over the plain float32 form.  Per run, the
+    objective error against the FP64 oracle is taken on the workload's first column block
+    (5000 x 15625) over 50 iterations from the oracle's initial factors: against the
+    oracle on the original X and on bf16(X), from the trajectories that
+    tests/golden/make_trajectories.py stored (oracle/ only)."""
+    import json
+
+    import numpy as np
+
+    from workloads import large_halfnormal, to_f32_colmajor, uniform_init
+
+    out = {"x_storage": "bf16 (round to nearest even), two tiled copies", "residual": "float32",
+           "objective": "float64"}
+    stream = torch.cuda.Stream()
+    for r in (1, 10):
+        o = did.did_default_opts()
+        o.n_blocks = n_blocks
+        o.x_dtype = did.DID_BF16
+        o.refresh_every = r
+        o.stream = stream.cuda_stream
+        log(f"precision form: bf16 X, refresh_every={r}")
+        h = did.did_init_ex(X, M, N, K, 12345, o)
+        try:
+            ms, stages, n_it = timed_iterations(torch, did, h, stream, 10 if r > 1 else 2, steps, profile_iters=0)
+        finally:
+            did.did_free(h)
+        torch.cuda.empty_cache()
+        out[f"refresh_every_{r}"] = {"iter_s": round(1000.0 / ms, 3), "ms_per_iter": round(ms, 4),
+                                     "speedup_vs_plain_f32": round(plain_ms / ms, 3)}
+    # objective error against the oracle on a slice, from the stored oracle trajectories
+    gdir = os.path.join(ROOT, "tests", "golden")
+    try:
+        g_bf = json.load(open(os.path.join(gdir, "traj_large_slice_b1_bf16.json")))
+        g_32 = json.load(open(os.path.join(gdir, "traj_large_slice_b1.json")))
+    except OSError:
+        out["objective_error_vs_fp64_oracle"] = None
+        return out
+    Xs = to_f32_colmajor(large_halfnormal(M, N, K, seed=3, n_blocks=64, take_blocks=1)[0])
+    Ms, Ns = Xs.shape
+    B0, C0 = uniform_init(Ms, Ns, K, 12345)
+    Xd = torch.from_numpy(np.ascontiguousarray(Xs.T)).to("cuda")
+    Bd = torch.from_numpy(np.ascontiguousarray(B0.astype(np.float32).T)).to("cuda")
+    Cd = torch.from_numpy(np.ascontiguousarray(C0.astype(np.float32).T)).to("cuda")
+    torch.cuda.synchronize()
+    T = g_bf["T"]
+    fo_bf, fo_32 = np.array(g_bf["f"]), np.array(g_32["f"])
+    errs = {}
+    for name, dtype, r in (("plain_f32", did.DID_F32, 1), ("bf16_refresh_every_1", did.DID_BF16, 1),
+                           ("bf16_refresh_every_10", did.DID_BF16, 10)):
+        o = did.did_default_opts()
+        o.x_dtype = dtype
+        o.refresh_every = r
+        h = did.did_init_from_factors(Xd, Ms, Ns, K, Bd, Cd, o)
+        try:
+            did.did_iterate(h, T)
+            fg = np.append(did.did_history(h), did.did_objective(h))
+        finally:
+            did.did_free(h)
+        errs[name] = {"vs_oracle_on_x_max_over_t": float(np.max(np.abs(fg - fo_32) / fo_32)),
+                      "vs_oracle_on_x_at_T": float(abs(fg[-1] - fo_32[-1]) / fo_32[-1]),
+                      "vs_oracle_on_bf16x_max_over_t": float(np.max(np.abs(fg - fo_bf) / fo_bf)),
+                      "vs_oracle_on_bf16x_at_T": float(abs(fg[-1] - fo_bf[-1]) / fo_bf[-1])}
+    out["objective_error_vs_fp64_oracle"] = {
+        "slice": f"first column block {Ms}x{Ns}, K={K}, {T} iterations from uniform_init(12345) factors",
+        **errs}
+    del Xd, Bd, Cd
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -616,6 +775,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="large workload: skip the precision, batched and served forms (profiling runs)")
     ap.add_argument("--paper-max-n", type=float, default=1e8, help="paper workload: largest N")
     ap.add_argument("--no-table", action="store_true", help="paper workload: skip the runs to the stopping rule")
     ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")
@@ -667,23 +828,10 @@ def main():
     t0 = time.perf_counter()
     h = did.did_init_ex(X, M, N, K, 12345, opts)
     init_s = time.perf_counter() - t0
-    log(f"init {init_s:.2f} s; warmup {args.warmup}")
+    log(f"init {init_s:.2f} s; warmup {args.warmup}; timing {args.steps} steps")
     assert opts.stream, "engine stream must be explicit"
     try:
-        did.did_iterate(h, args.warmup)
-        did.did_sync(h)
-        did.did_profile(h, True)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        log(f"timing {args.steps} steps")
-        ev0.record(stream)
-        did.did_iterate(h, args.steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_total = ev0.elapsed_time(ev1)
-        stages, n_it = did.did_profile_read(h)
-        did.did_profile(h, False)
+        ms, stages, n_it = timed_iterations(torch, did, h, stream, args.warmup, args.steps, profile_iters=3)
         f_last = did.did_objective(h)
         hist = did.did_history(h)
         n_total = did.did_iterations(h)
@@ -692,7 +840,7 @@ def main():
     f32_ref = None
     if cfg.get("x_bf16"):
         # the plain float32 form from the same initial factors and iteration count, for the
-        # objective error of the bf16 storage form
+        # objective gap of the bf16 storage form
         o2 = did.did_default_opts()
         o2.n_blocks = cfg["n_blocks"]
         o2.borrow_x = 1
@@ -703,11 +851,10 @@ def main():
             f32_ref = did.did_objective(h2)
         finally:
             did.did_free(h2)
-    ms = ms_total / args.steps
     it_s = 1000.0 / ms
     cnt = algorithmic_counts(M, N, K, 2 if cfg.get("x_bf16") else 4)
     dom = max(("column_pass", "row_pass"), key=lambda k: stages[k])
-    dom_ms = stages[dom] / max(n_it, 1)
+    dom_ms = stages[dom] / n_it
     secs = dom_ms * 1e-3
     traffic = measured_traffic(dom, args.workload)
     KP = 32 if K <= 32 else 64
@@ -722,7 +869,17 @@ def main():
     else:
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(tflops, 3), "peak": round(PEAK_SPLIT_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(tflops / PEAK_SPLIT_TFLOPS, 4), "traffic": traffic}
+    # the whole iteration against the same roof: its algorithmic bytes (X once, C read and
+    # written, B read) over the measured time per iteration
+    iter_gbs = cnt["iter_bytes"] / (ms * 1e-3) / 1e9
     roof.update({
+        "iter_frac": round(iter_gbs / PEAK_HBM_GBS, 4), "iter_bytes": cnt["iter_bytes"],
+        "iter_note": "iteration algorithmic bytes / ms_per_step / 8 TB/s; the two passes read X twice per "
+                     "iteration (the sweep needs whole columns, the W messages whole rows)",
+        "limiter": sq_limiter(dom),
+        "bound_note": "bound = the roof whose time floor is larger for the pass's algorithmic work; limiter = "
+                      "what the committed SQ counters show stalls the pass (null when they were taken on other "
+                      "kernel sources)",
         "kernel_ms": round(dom_ms, 4), "bytes_per_launch": cnt["pass_bytes"], "flops_per_launch": cnt["pass_flops"],
         "f32_accurate_tflops": round(tflops, 3), "f32_accurate_peak_tflops": round(PEAK_SPLIT_TFLOPS, 2),
         "f32_accurate_frac": round(tflops / PEAK_SPLIT_TFLOPS, 4),
@@ -745,13 +902,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "M": M, "N": N, "K": K, "n_blocks": cfg["n_blocks"],
                    "x_layout": "as given (column-major)" if args.x_given and not cfg.get("x_bf16") else
                                "two copies in 32x32 tile order (one per pass), made once at init (x_tiled=1)"},
-        "hbm_gbs_algorithmic": round(cnt["iter_bytes"] * it_s / 1e9, 2),
-        "stage_ms_per_iter": {k: round(v / max(n_it, 1), 4) for k, v in stages.items()},
+        "hbm_gbs_algorithmic": round(iter_gbs, 2),
+        "stage_ms_per_iter": {k: round(v / n_it, 4) for k, v in stages.items()},
         "objective_last": f_last,
         "objective_ratio": (f_last / hist[0]) if hist else None,
         "init_s": round(init_s, 3),
@@ -761,10 +918,21 @@ def main():
         line["config"]["x_storage"] = "bf16"
         line["objective_f32_form_same_iterations"] = f32_ref
         line["objective_rel_diff_vs_f32_form"] = (f_last - f32_ref) / f32_ref
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
+    if args.workload == "large" and not args.no_forms:
+        # the other forms of the metric on the same GPU: precision (bf16 X, refresh every
+        # iteration or every 10), batched, served
+        line["precision_form"] = precision_form(torch, did, X, M, N, K, cfg["n_blocks"], ms, 20)
         del X
         torch.cuda.empty_cache()
+        line["batched_form"] = batch_measure(torch, did, WORKLOADS["batch"]["jobs"], 10, 2, args.x_given)
+        line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, False)
+        line["served_form"]["note"] = ("a shortened run of the served workload: the first jobs of the same "
+                                       "Poisson schedule (200 jobs/s), 200 GB budget, X read as given")
+    else:
+        del X
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg)
     emit(torch, line)
 

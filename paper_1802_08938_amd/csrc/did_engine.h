@@ -60,6 +60,11 @@ struct did_ctx {
   int64_t dev_bytes = 0;  // device memory held by the engine for this instance
   did_batch_ctx* batch = nullptr;
   std::vector<void*> allocs;
+  // one captured iteration of the MFMA path, replayed by did_iterate (not in the carried
+  // form, not while profiling; never by did_iterate_static, which must not allocate)
+  bool use_graph = true;
+  bool graph_failed = false;
+  hipGraphExec_t gexec = nullptr;
   // per-stage timing: kStages+1 events per profiled iteration
   bool profiling = false;
   std::vector<hipEvent_t> prof_events;

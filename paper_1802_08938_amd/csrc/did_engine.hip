@@ -116,6 +116,7 @@ void release(did_ctx* h) {
   if (h->ev_v) (void)hipEventDestroy(h->ev_v);
   if (h->st2) (void)hipStreamDestroy(h->st2);
   h->prof_events.clear();
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
@@ -484,12 +485,104 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
   return DID_OK;
 }
 
-// Iterations of the MFMA path on the buffers of h (shared by did_iterate and the
-// allocation-free did_iterate_static).  With a second stream (h->st2) the V partials and
-// their reduction overlap the row pass; without one they run in order on h->st.
-int iterate_mfma(did_ctx* h, int32_t n) {
+// One iteration of the MFMA path on the buffers of h, enqueued on h->st (and h->st2), with
+// a profiling event before the first and after every stage when ev is given.  The
+// objective goes to fhist at the device iteration counter tdev, so the launches carry no
+// host iteration index (the same launches can be captured once and replayed).
+static int enqueue_iteration(did_ctx* h, hipEvent_t* ev) {
   const Shape& s = h->s;
   hipError_t e;
+#define DID_MARK(q) \
+  if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
+  // carried residual (refresh_every > 1): the column pass refreshes R from X every
+  // refresh_every iterations and otherwise carries it (E = R - delta B C)
+  const bool carry = h->refresh > 1;
+  DID_MARK(0);
+  if (carry)
+    e = didk::colpass_carry(s, h->X, h->t % h->refresh == 0, h->Cq, h->Bq, h->BqD, h->Bsc, h->H, h->fpart, h->Rres,
+                            h->st);
+  else
+    e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st);
+  if (e != hipSuccess) return dev_fail(h, e, "column pass");
+  DID_MARK(1);
+  if ((e = didk::reduce_f_hist(h->fpart, didk::colpass_blocks(s), h->fhist, h->hist_cap, h->tdev, 0.5, h->st)) !=
+      hipSuccess)
+    return dev_fail(h, e, "objective reduce");
+  DID_MARK(2);
+  if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st, carry ? h->CqD : nullptr)) != hipSuccess)
+    return dev_fail(h, e, "sweep");
+  // V = tril(C'C'^T), on the second stream when there is one (overlapped with the row pass
+  // and the W reduction; the B update waits for it)
+  hipStream_t sv = h->st;
+  if (h->st2) {
+    if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess ||
+        (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
+      return dev_fail(h, e, "stream order");
+    sv = h->st2;
+  }
+  if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, sv)) != hipSuccess) return dev_fail(h, e, "V partials");
+  if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, sv)) != hipSuccess)
+    return dev_fail(h, e, "V reduce");
+  if (h->st2 && (e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
+  DID_MARK(3);
+  DID_MARK(4);
+  if (carry)
+    e = didk::rowpass_carry(s, h->Rres, h->Cq, h->CqD, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
+  else
+    e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
+  if (e != hipSuccess) return dev_fail(h, e, "row pass");
+  DID_MARK(5);
+  if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
+  DID_MARK(6);
+  if (h->st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
+  if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st, carry ? h->BqD : nullptr)) !=
+      hipSuccess)
+    return dev_fail(h, e, "B update");
+  DID_MARK(7);
+  if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
+    return dev_fail(h, e, "G reduce");
+  DID_MARK(8);
+#undef DID_MARK
+  return DID_OK;
+}
+
+// Iterations of the MFMA path on the buffers of h (shared by did_iterate and the
+// allocation-free did_iterate_static).  With a second stream (h->st2) the V partials and
+// their reduction overlap the row pass; without one they run in order on h->st.  Without
+// profiling, two or more iterations of the refresh-every-iteration form replay one
+// captured iteration (a hipGraph kept by the handle), which removes the host launch cost
+// that bounds small shapes.
+int iterate_mfma(did_ctx* h, int32_t n) {
+  hipError_t e;
+  if (n <= 0) return DID_OK;
+  if (h->use_graph && !h->profiling && h->refresh == 1 && n >= 2) {
+    if (!h->gexec && !h->graph_failed) {
+      hipGraph_t g = nullptr;
+      if ((e = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_failed = true;
+      } else {
+        const int rc = enqueue_iteration(h, nullptr);
+        e = hipStreamEndCapture(h->st, &g);
+        if (rc) {
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+        if (e != hipSuccess || !g || hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          h->gexec = nullptr;
+          h->graph_failed = true;
+        }
+        if (g) (void)hipGraphDestroy(g);
+      }
+    }
+    if (h->gexec) {
+      for (int32_t it = 0; it < n; ++it)
+        if ((e = hipGraphLaunch(h->gexec, h->st)) != hipSuccess) return dev_fail(h, e, "iteration graph launch");
+      h->t += n;
+      return DID_OK;
+    }
+  }
   for (int32_t it = 0; it < n; ++it) {
     hipEvent_t* ev = nullptr;
     if (h->profiling) {
@@ -499,57 +592,8 @@ int iterate_mfma(did_ctx* h, int32_t n) {
         if ((e = hipEventCreate(&h->prof_events[base + q])) != hipSuccess) return dev_fail(h, e, "profile event");
       ev = h->prof_events.data() + base;
     }
-#define DID_MARK(q) \
-  if (ev && (e = hipEventRecord(ev[q], h->st)) != hipSuccess) return dev_fail(h, e, "profile record")
-    // carried residual (refresh_every > 1): the column pass refreshes R from X every
-    // refresh_every iterations and otherwise carries it (E = R - delta B C)
-    const bool carry = h->refresh > 1;
-    DID_MARK(0);
-    if (carry)
-      e = didk::colpass_carry(s, h->X, h->t % h->refresh == 0, h->Cq, h->Bq, h->BqD, h->Bsc, h->H, h->fpart, h->Rres,
-                              h->st);
-    else
-      e = didk::colpass(s, h->X, h->Cq, h->Bq, h->Bsc, h->H, h->fpart, 1, h->st);
-    if (e != hipSuccess) return dev_fail(h, e, "column pass");
-    DID_MARK(1);
-    if ((e = didk::reduce_f(h->fpart, didk::colpass_blocks(s), h->fhist + (h->t % h->hist_cap), 0.5, h->st)) !=
-        hipSuccess)
-      return dev_fail(h, e, "objective reduce");
-    DID_MARK(2);
-    if ((e = didk::sweep(s, h->H, h->C, h->Cq, h->Csc, h->G, h->st, carry ? h->CqD : nullptr)) != hipSuccess)
-      return dev_fail(h, e, "sweep");
-    // V = tril(C'C'^T), on the second stream when there is one (overlapped with the row pass
-    // and the W reduction; the B update waits for it)
-    hipStream_t sv = h->st;
-    if (h->st2) {
-      if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess ||
-          (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
-        return dev_fail(h, e, "stream order");
-      sv = h->st2;
-    }
-    if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, sv)) != hipSuccess) return dev_fail(h, e, "V partials");
-    if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, sv)) != hipSuccess)
-      return dev_fail(h, e, "V reduce");
-    if (h->st2 && (e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
-    DID_MARK(3);
-    DID_MARK(4);
-    if (carry)
-      e = didk::rowpass_carry(s, h->Rres, h->Cq, h->CqD, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
-    else
-      e = didk::rowpass(s, h->XR, h->Cq, h->Csc, h->Bq, h->Wpart, h->rbounds, h->R, h->st);
-    if (e != hipSuccess) return dev_fail(h, e, "row pass");
-    DID_MARK(5);
-    if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
-    DID_MARK(6);
-    if (h->st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
-    if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st, carry ? h->BqD : nullptr)) !=
-        hipSuccess)
-      return dev_fail(h, e, "B update");
-    DID_MARK(7);
-    if ((e = didk::reduce_sym(h->Gpart, didk::bupdate_blocks(s), s.KP, h->G, h->st)) != hipSuccess)
-      return dev_fail(h, e, "G reduce");
-    DID_MARK(8);
-#undef DID_MARK
+    const int rc = enqueue_iteration(h, ev);
+    if (rc) return rc;
     ++h->t;
   }
   return DID_OK;

@@ -154,6 +154,11 @@ hipError_t reduce_w(const Shape& s, const float* Wpart, int R, double* W, hipStr
 hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_full(const double* part, int64_t P, int KP, double* full, hipStream_t st);
 hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hipStream_t st);
+// scale * sum of the partials into fhist[*tdev % cap], then *tdev += 1 (replayable)
+hipError_t reduce_f_hist(const double* part, int64_t P, double* fhist, int64_t cap, int64_t* tdev, double scale,
+                         hipStream_t st);
+// *p = v from a kernel (no memset node, no host memory)
+hipError_t set_i64(int64_t* p, int64_t v, hipStream_t st);
 
 // ---- batched form: grouped persistent kernels over a device-resident instance table ----
 // One group holds instances of one (KP, X storage) pair.  Every stage of an iteration is a

@@ -1635,6 +1635,35 @@ hipError_t reduce_f(const double* part, int64_t P, double* out, double scale, hi
   return hipGetLastError();
 }
 
+// The objective of an iteration into the history ring at the device iteration counter,
+// which then advances: no host value is baked into the launch, so a captured iteration
+// can be replayed.
+__global__ __launch_bounds__(256) void k_reduce_f_hist(const double* __restrict__ part, int64_t P,
+                                                       double* __restrict__ fhist, int64_t cap,
+                                                       int64_t* __restrict__ tdev, double scale) {
+  const double r = reduce_f_body(part, P, scale);
+  if (threadIdx.x == 0) {
+    const int64_t t = *tdev;
+    fhist[t % cap] = r;
+    *tdev = t + 1;
+  }
+}
+
+hipError_t reduce_f_hist(const double* part, int64_t P, double* fhist, int64_t cap, int64_t* tdev, double scale,
+                         hipStream_t st) {
+  k_reduce_f_hist<<<1, 256, 0, st>>>(part, P, fhist, cap, tdev, scale);
+  return hipGetLastError();
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
+hipError_t set_i64(int64_t* p, int64_t v, hipStream_t st) {
+  k_set_i64<<<1, 64, 0, st>>>(p, v);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ batched form
 // Grouped persistent kernels: block b takes items b, b + grid, b + 2 grid, ... of the
 // stage's concatenated item list, finds the owning instance by binary search over the

@@ -79,6 +79,7 @@ int64_t carve_static(did_ctx& c, unsigned char* base, int64_t R) {
   c.rbounds = w.take<int64_t>(R + 1);
   c.fpart = w.take<double>(didk::colpass_blocks(s));
   c.fobj = w.take<double>(1);  // objective slot when the caller passes no f
+  c.tdev = w.take<int64_t>(1);  // device iteration counter (index into the history)
   return w.off;
 }
 
@@ -115,6 +116,7 @@ int did_iterate_static(const float* X, int64_t M, int64_t N, int32_t K, float* B
   (void)carve_static(c, base, R);
   c.st = static_cast<hipStream_t>(o.stream);
   c.own_stream = false;
+  c.use_graph = false;  // a graph would allocate
   c.X = const_cast<float*>(X);
   c.XR = c.X;
   c.s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
@@ -134,6 +136,7 @@ int did_iterate_static(const float* X, int64_t M, int64_t N, int32_t K, float* B
       (e = didk::zero16(c.V, (int64_t)s.KP * s.KP * 8, c.st)) != hipSuccess ||
       (e = didk::zero16(c.W, (int64_t)s.KP * s.Mpad * 8, c.st)) != hipSuccess ||
       (e = didk::ranges_on_device(c.rbounds, T, P, S, c.st)) != hipSuccess ||
+      (e = didk::set_i64(c.tdev, 0, c.st)) != hipSuccess ||
       (e = refresh_b_derived(&c)) != hipSuccess || (e = pack_c(&c)) != hipSuccess)
     return dev_fail(nullptr, e, "did_iterate_static setup");
   rc = iterate_mfma(&c, n);

@@ -632,3 +632,33 @@ def test_carried_residual_rejections():
     with pytest.raises(did.DidError) as ei:
         did.did_init_ex(X2, 64, 300, 3, 1, o)
     assert ei.value.code == did.DID_EINVAL
+
+
+def test_graph_replays_equal_eager_iterations():
+    """did_iterate(h, n >= 2) replays one captured iteration (a hipGraph); did_iterate(h, 1)
+    launches the kernels directly.  With eager work and synchronisations between the
+    replays (objective passes, factor reads), every replay's result equals the eager one
+    bit for bit."""
+    torch = require_gpu()
+    rng = np.random.default_rng(23)
+    M, N, K = 300, 2500, 24
+    X32 = to_f32_colmajor(rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N))))
+    announce("graph replays vs eager iterations")
+    Xd = device_x(torch, X32)
+    he = did.did_init(Xd, M, N, K, 99)
+    hg = did.did_init(Xd, M, N, K, 99)
+    try:
+        for step in range(4):
+            for _ in range(3):
+                did.did_iterate(he, 1)
+            did.did_iterate(hg, 3)
+            fe, fg = did.did_objective(he), did.did_objective(hg)
+            a, b = read_factors(he, M, N, K), read_factors(hg, M, N, K)
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[1], b[1])
+            assert fe == fg
+        np.testing.assert_array_equal(np.array(did.did_history(he)), np.array(did.did_history(hg)))
+        assert did.did_iterations(hg) == 12
+    finally:
+        did.did_free(he)
+        did.did_free(hg)
