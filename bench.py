@@ -175,10 +175,18 @@ def sq_limiter(kernel):
         clk = float(vals["implied clock, GHz (busy cycles / duration)"])
     except (KeyError, ValueError):
         return None
-    # one wave64 VALU instruction occupies the SIMD 4 cycles, an MFMA 32x32x16 32 cycles
+    # one wave64 VALU instruction occupies the SIMD 4 cycles, an MFMA 32x32x16 32 cycles;
+    # the two overlap only in part (a wave's VALU work runs beside an MFMA in flight)
     valu_busy = mfma * valu * 4.0 / 32.0
-    kind = "issue (MFMA + VALU work)" if mfma + valu_busy >= 0.8 else "latency (waves waiting)"
+    issue = mfma + valu_busy
+    if issue >= 0.9:
+        kind = "issue (MFMA and VALU pipes saturated)"
+    elif wait >= 0.25:
+        kind = "latency and issue (waves wait on memory/LDS while MFMA+VALU fill part of the cycles)"
+    else:
+        kind = "mixed"
     return {"label": kind, "mfma_busy": mfma, "valu_per_mfma": valu, "valu_busy_est": round(valu_busy, 3),
+            "mfma_plus_valu_est": round(issue, 3),
             "wait_frac": wait, "clock_ghz": clk, "source": "profiles/sq_counters_large.md"}
 
 

@@ -79,13 +79,38 @@ struct Split2 {
   f16x8 p[2];
 };
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// y - hi for the low (SEL = 0) or high (SEL = 1) fp16 half of hp, in one mixed-precision
+// fma (v_fma_mix_f32 widens the fp16 operand inside the instruction).  Exact: y - hi is a
+// float32 number, so this is the same value as y - (float)hi.
+template <int SEL>
+__device__ __forceinline__ float sub_f16(float y, f16x2 hp) {
+  float r;
+  const unsigned u = __builtin_bit_cast(unsigned, hp);
+  if constexpr (SEL == 0)
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(y));
+  else
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(y));
+  return r;
+}
+
+// hi: two values per packed conversion; lo = fp16(y - hi) with y - hi formed from the
+// packed hi directly, so a value costs two instructions (rather than a scalar conversion
+// and its inverse, a subtraction and a share of two packings).
 __device__ __forceinline__ Split2 split2(const float (&v)[8]) {
   Split2 r;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const _Float16 h = (_Float16)v[t];
-    r.p[0][t] = h;
-    r.p[1][t] = (_Float16)(v[t] - (float)h);
+  for (int t = 0; t < 8; t += 2) {
+    f16x2 hp;
+    hp.x = (_Float16)v[t];
+    hp.y = (_Float16)v[t + 1];
+    const float l0 = sub_f16<0>(v[t], hp);
+    const float l1 = sub_f16<1>(v[t + 1], hp);
+    r.p[0][t] = hp.x;
+    r.p[0][t + 1] = hp.y;
+    r.p[1][t] = (_Float16)l0;
+    r.p[1][t + 1] = (_Float16)l1;
   }
   return r;
 }
@@ -687,7 +712,9 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   constexpr int UCE0 = CqL<KP>::E0;   // the tile's inverse column scales
   __shared__ f32x4 sb[2][U];
   __shared__ double fw[4];
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
+  // the wave index is uniform: from a scalar register, so that wave-based addresses stay scalar
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, half = l >> 5,
+            lc = l & 31;
   const int64_t T = bid * 4 + wave;  // this wave's 32-column tile
   const int64_t j0 = T * 32;
   const int64_t col = j0 + lc;
@@ -1171,7 +1198,9 @@ __device__ __forceinline__ void vgram_body(const f32x4* __restrict__ Cq, const f
   constexpr int NBL = NB * (NB + 1) / 2;  // lower blocks (b1 >= b2)
   constexpr int NP = KP * (KP + 1) / 2;
   __shared__ double Vs[4][NP];
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
+  // the wave index is uniform: from a scalar register, so that wave-based addresses stay scalar
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, half = l >> 5,
+            lc = l & 31;
   const int64_t per = (ntiles + nblk - 1) / nblk;
   const int64_t t0 = bid * per;
   const int64_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
@@ -1256,8 +1285,8 @@ hipError_t vgram(const Shape& s, const void* Cq, const float* Csc, double* Vpart
 // scale of the column pass's H: chosen per tile from the tile's largest |E'| in the row and
 // never raised, the running WT being rescaled exactly when it drops.  The packed C' tile
 // (both operand orders, already split and scaled) is copied into LDS for the next tile
-// (double buffer shared by the four waves) and X of the next tile is prefetched into
-// registers.
+// (double buffer shared by the four waves; straight from global memory into LDS, with no
+// staging registers) and X of the next tile is prefetched into registers.
 // Blocks map to (range, slab group) so that all slab groups of a range run on one XCD
 // (blocks are dealt to the eight XCDs round-robin): the range's C' tiles are then fetched
 // into a single L2.
@@ -1285,7 +1314,9 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   const int id = (int)bid, xcd = id & 7, local = id >> 3;
   const int r = xcd + 8 * (local / nsg), sg = local % nsg;
   if (r >= R) return;  // whole block
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, half = l >> 5, lc = l & 31;
+  // the wave index is uniform: from a scalar register, so that wave-based addresses stay scalar
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, half = l >> 5,
+            lc = l & 31;
   const int64_t c = (int64_t)sg * 4 + wave;
   const bool active = c < nchunks;  // inactive waves still take part in staging and barriers
   const int64_t tlo = tb[r], thi = tb[r + 1];
@@ -1310,22 +1341,20 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     for (int i = 0; i < 16; ++i) WT[b][i] = 0.0f;
   int vcur = 126;  // current scale exponent of this row's E' operand (never raised)
 
-  f32x4 stg[NV];
-  auto cload = [&](int64_t T) {
+  // tile T's packed C units straight from global memory into LDS buffer buf (no staging
+  // registers): lane l of wave w writes unit w*64 + 256 v + l, the unit it loads
+  auto cdma = [&](int64_t T, int buf) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int u = tid + 256 * v;
-      if constexpr (RW)
-        stg[v] = u < UE ? CqE[T * UE + u] : Cq[T * UT + (u < UT ? u : UT - 1)];
-      else
-        stg[v] = Cq[T * UT + (u < UT ? u : UT - 1)];
-    }
-  };
-  auto cstore = [&](int buf) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int u = tid + 256 * v;
-      if (u < UT) sc[buf][u] = stg[v];
+      if (u < UT) {
+        const f32x4* src = Cq + T * UT + u;
+        if constexpr (RW)
+          if (u < UE) src = CqE + T * UE + u;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)&sc[buf][wave * 64 + 256 * v], 16, 0,
+                                         0);
+      }
     }
   };
   const uint32_t loff = (uint32_t)(4 * half * M + mrow);  // lane offset within a tile
@@ -1356,7 +1385,7 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
   // into xn.
   auto step = [&](int64_t T, int buf, f32x16& acc, f32x16& xn) {
     const int64_t Tn = T + 1 < thi ? T + 1 : T;
-    cload(Tn);
+    cdma(Tn, buf ^ 1);
     xn = xload(Tn);
     if (active) {
       {
@@ -1444,14 +1473,12 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
         }
       }
     }
-    cstore(buf ^ 1);
     __syncthreads();
   };
 
   if (tlo < thi) {
     f32x16 x0 = xload(tlo);
-    cload(tlo);
-    cstore(0);
+    cdma(tlo, 0);
     __syncthreads();
     f32x16 x1;
     for (int64_t T = tlo; T < thi; T += 2) {
