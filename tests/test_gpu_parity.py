@@ -86,7 +86,7 @@ def _sampled_golden_factors(g, out):
     check_factors(out[1][0][rows], B1o, out[1][1][:, cols], C1o, label=f"{g['case']}, sampled, 1 iteration")
 
 
-@pytest.mark.parametrize("case", ["image_like_p4", "large_slice_b1"])
+@pytest.mark.parametrize("case", ["image_like_p4", "large_slice_b1", "large_slice_b4"])
 def test_named_workloads_parity_50_iterations(case):
     """The image-like workload (784 x 70000, K = 16, 4 blocks) and slices of the large one
     (5000 x 15625 and 5000 x 62500, K = 50, 1 and 4 blocks) from the same initial factors as
