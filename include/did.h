@@ -105,6 +105,12 @@ enum {
  *                  full-width loads.  Costs 8 * Mpad * Npad bytes of device memory and one
  *                  conversion pass at init; borrow_x does not apply.  Results are the same
  *                  bit for bit.  Not accepted on the thin-matrix path.
+ *   col_waves      tile shape of the column pass: 4 or 8 waves per block, each wave one
+ *                  32-column tile, the block's columns sharing one staged copy of B.
+ *                  0 takes the value did_autotune recorded for the instance's shape class,
+ *                  else 4.  The carried form (refresh_every > 1) runs 4 (8 is DID_EINVAL);
+ *                  ignored on the thin-matrix path.  Any other value is DID_EINVAL.  B, C
+ *                  and H do not depend on it; the objective does through summation order.
  *   stream         hipStream_t to order all work on; NULL = a stream owned by the handle.
  *
  * Shapes with M <= 16, K <= 8 and M <= 8 or K <= 4 (such as the experiments' synthetic
@@ -120,11 +126,12 @@ typedef struct did_opts {
   int32_t algorithm;
   int32_t row_blocks;
   int32_t x_tiled;
+  int32_t col_waves;
   void* stream;
 } did_opts;
 
 /* Fill *opts with the defaults: n_blocks 0, DID_F32, refresh_every 1, init_scale 0,
- * borrow_x 0, DID_ALG_DID, row_blocks 0, stream NULL.  Returns DID_EINVAL for a NULL
+ * borrow_x 0, DID_ALG_DID, row_blocks 0, x_tiled 0, col_waves 0, stream NULL.  Returns DID_EINVAL for a NULL
  * pointer. */
 int did_default_opts(did_opts* opts);
 
@@ -226,23 +233,26 @@ int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int3
                      int64_t* bytes);
 
 /*
- * Row-pass autotuner.  Times one DID iteration (after one warm-up) of a synthetic
- * U[0,1) instance of shape (M, N, K) and X storage x_dtype for each candidate row_blocks
- * value (512, 1024, 2048, 4096, 8192), records the fastest for the shape class
- * (K <= 32 or not, X storage, ceil(log2 M), ceil(log2 N)) in a process-wide table used
- * by every later instance created with row_blocks = 0, and returns it in *row_blocks
- * (and its time in *ms_per_iter if not NULL).  Allocates the tuning input (4MN bytes) for
- * the duration of the call.  Thin-matrix shapes return DID_EINVAL.
- * did_autotune_clear() empties the table.
+ * Tile autotuner.  Times DID iterations (three, after one warm-up) of a synthetic
+ * U[0,1) instance of shape (M, N, K) and X storage (x_dtype, and x_tiled for DID_F32;
+ * ignored for DID_BF16) for each pair of column-pass block waves (4, 8) and row_blocks
+ * value (512, 1024, 2048, 4096, 8192), records the fastest pair for the shape class
+ * (K <= 32 or not, X storage: float32 as given, float32 tiled or bf16, ceil(log2 M),
+ * ceil(log2 N)) in a process-wide table used by every later instance of the class
+ * created with row_blocks = 0 or col_waves = 0, and returns it in *row_blocks and
+ * *col_waves (and its time in *ms_per_iter if not NULL).  Allocates the tuning input
+ * (4MN bytes) and the instance's own storage for the duration of the call.
+ * Thin-matrix shapes, NULL row_blocks or col_waves and x_tiled outside {0, 1} return
+ * DID_EINVAL.  did_autotune_clear() empties the table.
  */
-int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t* row_blocks,
-                 double* ms_per_iter);
+int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t x_tiled,
+                 int32_t* row_blocks, int32_t* col_waves, double* ms_per_iter);
 int did_autotune_clear(void);
 
 /*
  * Batched form: many instances of uneven (M, N, K) advanced together.
  * Members are grouped by (K <= 32 or not, X storage: float32 as given, float32 tiled or
- * bf16); each stage of an iteration is one
+ * bf16, column-pass block waves); each stage of an iteration is one
  * launch per group of a persistent kernel that walks the work items of all the group's
  * members from a device-resident table, and the launches of one iteration are captured
  * once in a hipGraph that each iteration replays.  A member runs exactly the work of its

@@ -76,6 +76,7 @@ class did_opts(ctypes.Structure):
         ("algorithm", ctypes.c_int32),
         ("row_blocks", ctypes.c_int32),
         ("x_tiled", ctypes.c_int32),
+        ("col_waves", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -87,6 +88,7 @@ class did_server_opts(ctypes.Structure):
         ("max_iter", ctypes.c_int32),
         ("rel_tol", ctypes.c_double),
         ("x_tiled", ctypes.c_int32),
+        ("col_waves", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -120,7 +122,8 @@ def lib():
         "did_profile_read": [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "did_mem_bytes": [vp, ctypes.POINTER(i64)],
         "did_mem_estimate": [i64, i64, i32, ctypes.POINTER(did_opts), i32, ctypes.POINTER(i64)],
-        "did_autotune": [i64, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+        "did_autotune": [i64, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                         ctypes.POINTER(ctypes.c_double)],
         "did_autotune_clear": [],
         "did_batch_create": [vp, ctypes.POINTER(vp)],
         "did_batch_add": [vp, vp],
@@ -273,12 +276,14 @@ def did_mem_estimate(M, N, K, opts=None, x_on_device=True) -> int:
     return b.value
 
 
-def did_autotune(M, N, K, x_dtype=DID_F32):
-    """Tune the row pass for the shape class of (M, N, K); returns (row_blocks, ms per iteration)."""
+def did_autotune(M, N, K, x_dtype=DID_F32, x_tiled=0):
+    """Tune the pass tiles for the shape class of (M, N, K) and X storage; returns
+    (row_blocks, col_waves, ms per iteration)."""
     rb = ctypes.c_int32()
+    cw = ctypes.c_int32()
     ms = ctypes.c_double()
-    _check(lib().did_autotune(M, N, K, x_dtype, ctypes.byref(rb), ctypes.byref(ms)))
-    return rb.value, ms.value
+    _check(lib().did_autotune(M, N, K, x_dtype, x_tiled, ctypes.byref(rb), ctypes.byref(cw), ctypes.byref(ms)))
+    return rb.value, cw.value, ms.value
 
 
 def did_autotune_clear():

@@ -35,13 +35,17 @@ using didk::GInst;
 using didk::GS_N;
 using didk::GTable;
 using didk::kMaxBatch;
-constexpr int kGroups = 2 * didk::XK_N;  // (K class, X storage kind)
+constexpr int kGroups = 2 * didk::XK_N * 2;  // (K class, X storage kind, column-pass block waves)
 
 // ------------------------------------------------------------------ autotuned row pass
 namespace {
 
 std::mutex g_tune_mu;
-std::map<uint64_t, int> g_tuned;  // shape class -> row_blocks
+struct Tuned {
+  int row_blocks;
+  int col_waves;
+};
+std::map<uint64_t, Tuned> g_tuned;  // shape class -> tile choice
 
 int log2_class(int64_t v) {
   int c = 0;
@@ -52,22 +56,29 @@ int log2_class(int64_t v) {
   return c;
 }
 
-// Shape class: KP, X storage, ceil(log2 M), ceil(log2 N).
-uint64_t shape_class(int64_t M, int64_t N, int KP, int xbf16) {
-  return ((uint64_t)(KP == 64) << 40) | ((uint64_t)(xbf16 != 0) << 32) | ((uint64_t)log2_class(M) << 16) |
+// Shape class: KP, X storage kind, ceil(log2 M), ceil(log2 N).
+uint64_t shape_class(int64_t M, int64_t N, int KP, int xkind) {
+  return ((uint64_t)(KP == 64) << 40) | ((uint64_t)xkind << 32) | ((uint64_t)log2_class(M) << 16) |
          (uint64_t)log2_class(N);
 }
 
 constexpr int kRowCandidates[] = {512, 1024, 2048, 4096, 8192};
+constexpr int kColCandidates[] = {4, 8};
 
 }  // namespace
 
 namespace didengine {
 
-int tuned_row_blocks(int64_t M, int64_t N, int KP, int xbf16) {
+int tuned_row_blocks(int64_t M, int64_t N, int KP, int xkind) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tuned.find(shape_class(M, N, KP, xbf16));
-  return it == g_tuned.end() ? 4096 : it->second;
+  auto it = g_tuned.find(shape_class(M, N, KP, xkind));
+  return it == g_tuned.end() ? 4096 : it->second.row_blocks;
+}
+
+int tuned_col_waves(int64_t M, int64_t N, int KP, int xkind) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(shape_class(M, N, KP, xkind));
+  return it == g_tuned.end() ? 4 : it->second.col_waves;
 }
 
 }  // namespace didengine
@@ -97,7 +108,12 @@ struct did_batch_ctx {
 
 namespace {
 
-int group_of(const did_ctx* h) { return (h->s.KP == 64 ? didk::XK_N : 0) + didk::x_kind(h->s); }
+int group_of(const did_ctx* h) {
+  return 2 * ((h->s.KP == 64 ? didk::XK_N : 0) + didk::x_kind(h->s)) + (h->s.cwpb == 8 ? 1 : 0);
+}
+int group_kp(int g) { return g / 2 >= didk::XK_N ? 64 : 32; }
+int group_xkind(int g) { return (g / 2) % didk::XK_N; }
+int group_cwpb(int g) { return g % 2 ? 8 : 4; }
 
 int bdev_fail(did_batch_ctx* b, hipError_t e, const char* what) {
   if (b) b->sticky = 1;
@@ -174,7 +190,7 @@ int rebuild(did_batch_ctx* b) {
       G.dtab = static_cast<GTable*>(p);
     }
     if (!G.have_grids) {
-      if ((e = didk::group_grids(g >= didk::XK_N ? 64 : 32, g % didk::XK_N, G.grids)) != hipSuccess)
+      if ((e = didk::group_grids(group_kp(g), group_xkind(g), group_cwpb(g), G.grids)) != hipSuccess)
         return bdev_fail(b, e, "occupancy of the grouped kernels");
       G.have_grids = true;
     }
@@ -206,7 +222,7 @@ int rebuild(did_batch_ctx* b) {
       for (int g = 0; g < kGroups; ++g) {
         auto& G = b->groups[g];
         if (!(mask & (1u << g))) continue;
-        hipError_t r = didk::group_iteration(g >= didk::XK_N ? 64 : 32, g % didk::XK_N, G.dtab, G.grids, b->st);
+        hipError_t r = didk::group_iteration(group_kp(g), group_xkind(g), group_cwpb(g), G.dtab, G.grids, b->st);
         if (r != hipSuccess && le == hipSuccess) le = r;
       }
       if ((e = hipStreamEndCapture(b->st, &b->graph)) != hipSuccess) return bdev_fail(b, e, "graph capture");
@@ -273,7 +289,7 @@ int did_batch_add(did_batch b, did_handle h) {
   if (h->profiling) return fail(DID_ESTATE, "disable profiling before adding a handle to a batch");
   int n_in_group = 0;
   for (did_ctx* m : b->members) n_in_group += group_of(m) == group_of(h);
-  if (n_in_group >= kMaxBatch) return fail(DID_ESTATE, "batch group is full (64 instances per (K class, X storage))");
+  if (n_in_group >= kMaxBatch) return fail(DID_ESTATE, "batch group is full (64 instances per (K class, X storage, column-pass block waves))");
   const int slot = free_slot(b);
   if (slot < 0) return fail(DID_ESTATE, "batch is full");
   DeviceGuard g(b->dev);
@@ -365,10 +381,13 @@ int did_batch_free(did_batch b) {
 }
 
 // ------------------------------------------------------------------ autotuner
-int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t* row_blocks, double* ms_per_iter) {
-  if (!row_blocks) return fail(DID_EINVAL, "row_blocks must not be NULL");
+int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t x_tiled, int32_t* row_blocks,
+                 int32_t* col_waves, double* ms_per_iter) {
+  if (!row_blocks || !col_waves) return fail(DID_EINVAL, "row_blocks and col_waves must not be NULL");
   *row_blocks = 0;
+  *col_waves = 0;
   if (x_dtype != DID_F32 && x_dtype != DID_BF16) return fail(DID_EINVAL, "x_dtype must be DID_F32 or DID_BF16");
+  if (x_tiled != 0 && x_tiled != 1) return fail(DID_EINVAL, "x_tiled must be 0 or 1");
   if (M <= 16 && K <= 8 && (M <= 8 || K <= 4))
     return fail(DID_EINVAL, "thin-matrix shapes have no row pass to tune");
   // a synthetic X of the shape: U[0,1) entries from the engine's own generator
@@ -389,29 +408,34 @@ int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t* row_
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  int best = 0;
+  Tuned best{0, 0};
   double best_ms = 0.0;
   int rc = DID_OK;
-  for (int cand : kRowCandidates) {
-    did_opts o;
-    did_default_opts(&o);
-    o.x_dtype = x_dtype;
-    o.borrow_x = 1;
-    o.row_blocks = cand;
-    o.stream = st;
-    did_handle h = nullptr;
-    if ((rc = did_init_ex(X, M, N, K, 1, &o, &h))) break;
-    float ms = 0.0f;
-    if ((rc = did_iterate(h, 1)) == DID_OK && hipEventRecord(e0, st) == hipSuccess && (rc = did_iterate(h, 3)) == DID_OK &&
-        hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-        hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-      const double per = ms / 3.0;
-      if (!best || per < best_ms) {
-        best = cand;
-        best_ms = per;
+  for (int cw : kColCandidates) {
+    for (int cand : kRowCandidates) {
+      did_opts o;
+      did_default_opts(&o);
+      o.x_dtype = x_dtype;
+      o.x_tiled = x_dtype == DID_F32 ? x_tiled : 0;
+      o.borrow_x = 1;
+      o.row_blocks = cand;
+      o.col_waves = cw;
+      o.stream = st;
+      did_handle h = nullptr;
+      if ((rc = did_init_ex(X, M, N, K, 1, &o, &h))) break;
+      float ms = 0.0f;
+      if ((rc = did_iterate(h, 1)) == DID_OK && hipEventRecord(e0, st) == hipSuccess &&
+          (rc = did_iterate(h, 3)) == DID_OK && hipEventRecord(e1, st) == hipSuccess &&
+          hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+        const double per = ms / 3.0;
+        if (!best.row_blocks || per < best_ms) {
+          best = Tuned{cand, cw};
+          best_ms = per;
+        }
       }
+      did_free(h);
+      if (rc) break;
     }
-    did_free(h);
     if (rc) break;
   }
   (void)hipEventDestroy(e0);
@@ -419,12 +443,14 @@ int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t* row_
   (void)hipStreamDestroy(st);
   (void)hipFree(X);
   if (rc) return rc;
-  if (!best) return fail(DID_EDEVICE, "tuning runs failed");
+  if (!best.row_blocks) return fail(DID_EDEVICE, "tuning runs failed");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[shape_class(M, N, K <= 32 ? 32 : 64, x_dtype == DID_BF16)] = best;
+    const int xkind = x_dtype == DID_BF16 ? didk::XK_BF16 : x_tiled ? didk::XK_F32_TILED : didk::XK_F32;
+    g_tuned[shape_class(M, N, K <= 32 ? 32 : 64, xkind)] = best;
   }
-  *row_blocks = best;
+  *row_blocks = best.row_blocks;
+  *col_waves = best.col_waves;
   if (ms_per_iter) *ms_per_iter = best_ms;
   return DID_OK;
 }

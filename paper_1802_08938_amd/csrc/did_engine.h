@@ -83,7 +83,9 @@ int check_free_handle(did_ctx* h);  // check_handle and not a batch member
 
 // Row-pass target recorded by did_autotune for the shape class of (M, N, KP, X storage),
 // else the default (4096).
-int tuned_row_blocks(int64_t M, int64_t N, int KP, int xbf16);
+int tuned_row_blocks(int64_t M, int64_t N, int KP, int xkind);
+// Column-pass waves per block recorded by did_autotune for the shape class, else 4.
+int tuned_col_waves(int64_t M, int64_t N, int KP, int xkind);
 
 // Shared by the single-instance engine and the allocation-free entry point (did_engine.hip).
 int check_shape(int64_t M, int64_t N, int32_t K);

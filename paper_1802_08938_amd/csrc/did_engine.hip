@@ -188,6 +188,13 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
     return fail(DID_EINVAL, "refresh_every > 1 (carried residual) runs the MFMA passes only, not the thin-matrix path");
   if (o.refresh_every > 1 && 32 * M > (int64_t)0xFFFFFFFF)
     return fail(DID_EINVAL, "the carried residual is column-major: refresh_every > 1 needs 32 * M < 2^32");
+  if (o.col_waves != 0 && o.col_waves != 4 && o.col_waves != 8) return fail(DID_EINVAL, "col_waves must be 0, 4 or 8");
+  if (o.col_waves == 8 && o.refresh_every > 1)
+    return fail(DID_EINVAL, "the carried residual form runs the column pass with 4 waves per block");
+  if (s.thin || o.refresh_every > 1)
+    s.cwpb = 4;
+  else
+    s.cwpb = o.col_waves ? o.col_waves : tuned_col_waves(M, N, s.KP, didk::x_kind(s));
   if (s.thin && (s.thin_grid = didk::thin_grid_for(s)) < 1)
     return fail(DID_EDEVICE, "thin path: occupancy query failed");
   return DID_OK;
@@ -197,7 +204,7 @@ int make_shape(Shape& s, int64_t M, int64_t N, int32_t K, const did_opts& o) {
 // else the default.
 int row_target(const Shape& s, const did_opts& o) {
   if (o.row_blocks > 0) return o.row_blocks;
-  return didengine::tuned_row_blocks(s.M, s.N, s.KP, s.xbf16);
+  return didengine::tuned_row_blocks(s.M, s.N, s.KP, didk::x_kind(s));
 }
 
 // Device bytes the engine allocates for an instance (the plan setup follows).

@@ -17,6 +17,7 @@ struct Shape {
   int xbf16;         // X is stored as bf16 (reduced-precision storage form), else float32
   int xtiled;        // X is stored in tile order (always for bf16; float32 on request)
   int thin;          // thin-matrix path (M <= 16, K <= 8, M <= 8 or K <= 4): one fused pass per iteration
+  int cwpb;          // waves per column-pass block (4 or 8): the block's 32 cwpb columns share one staged B
   int64_t thin_grid; // thin path: blocks per launch (one wave of resident blocks)
 };
 
@@ -114,7 +115,7 @@ int bupdate_blocks(const Shape& s);
 // C enters through its packed pieces Cq.
 hipError_t colpass(const Shape& s, const void* X, const void* Cq, const _Float16* Bq, const float* Bsc,
                    float* Hout, double* fpart, int with_h, hipStream_t st);
-int64_t colpass_blocks(const Shape& s);
+int64_t colpass_blocks(const Shape& s);  // blocks of 32 cwpb columns
 
 // Carried-residual form (refresh_every > 1) of the two passes; R is the column-major
 // float32 residual (M x N, ld M), carried across iterations.
@@ -161,7 +162,7 @@ hipError_t reduce_f_hist(const double* part, int64_t P, double* fhist, int64_t c
 hipError_t set_i64(int64_t* p, int64_t v, hipStream_t st);
 
 // ---- batched form: grouped persistent kernels over a device-resident instance table ----
-// One group holds instances of one (KP, X storage) pair.  Every stage of an iteration is a
+// One group holds instances of one (KP, X storage, column-pass block waves) triple.  Every stage of an iteration is a
 // single persistent launch whose blocks walk the concatenated work items of all the
 // group's instances; an instance's items are exactly the blocks of its single-instance
 // launch, run by the same device code, so its results do not depend on the batch.
@@ -206,9 +207,10 @@ void ginst_items(const Shape& s, int R, int64_t items[GS_N]);
 enum { XK_F32 = 0, XK_BF16 = 1, XK_F32_TILED = 2, XK_N = 3 };
 inline int x_kind(const Shape& s) { return s.xbf16 ? XK_BF16 : (s.xtiled ? XK_F32_TILED : XK_F32); }
 // persistent grid of each grouped stage kernel on the current device (resident blocks)
-hipError_t group_grids(int KP, int xkind, int64_t grids[GS_N]);
+hipError_t group_grids(int KP, int xkind, int cwpb, int64_t grids[GS_N]);
 // one iteration of every instance in the group table dtab (device memory)
-hipError_t group_iteration(int KP, int xkind, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st);
+hipError_t group_iteration(int KP, int xkind, int cwpb, const GTable* dtab, const int64_t grids[GS_N],
+                           hipStream_t st);
 
 // ---- thin-matrix path (did_thin.hip) ----
 // mode 0: DID column work (sweep, W/V/f block partials); 1: objective partials only;

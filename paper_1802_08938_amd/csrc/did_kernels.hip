@@ -695,7 +695,7 @@ hipError_t bupdate(const Shape& s, float* B, const double* W, const double* V, _
 // H-order operand comes from Bq, and E is stored to the column-major float32 residual
 // Rout (rvec4: 16-byte stores are aligned), so that the row pass can carry it on.  The
 // source X is then either the data (refresh) or Rout itself (carry: E = R - delta B C).
-template <int KP, bool WITH_H, typename XT, bool RW = false>
+template <int KP, bool WITH_H, typename XT, bool RW = false, int WPB = 4>
 __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M, int64_t N, int K,
                                              const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
                                              const float* __restrict__ Bsc, float* __restrict__ Hout,
@@ -707,15 +707,15 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   constexpr int UE = BqL<KP>::E;      // 16-byte units of the E operand per chunk
   constexpr int US = BqL<KP>::S;      // the chunk's 32 row scales
   constexpr int U = BqL<KP>::C;       // the chunk's whole run
-  constexpr int NV = (U + 255) / 256; // units per thread per chunk
+  constexpr int NV = (U + 64 * WPB - 1) / (64 * WPB);  // units per thread per chunk
   constexpr int UCT = CqL<KP>::T;     // units per packed C tile
   constexpr int UCE0 = CqL<KP>::E0;   // the tile's inverse column scales
   __shared__ f32x4 sb[2][U];
-  __shared__ double fw[4];
+  __shared__ double fw[WPB];
   // the wave index is uniform: from a scalar register, so that wave-based addresses stay scalar
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, half = l >> 5,
             lc = l & 31;
-  const int64_t T = bid * 4 + wave;  // this wave's 32-column tile
+  const int64_t T = bid * WPB + wave;  // this wave's 32-column tile
   const int64_t j0 = T * 32;
   const int64_t col = j0 + lc;
   const bool colok = col < N;
@@ -751,7 +751,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   auto gload = [&](int64_t c) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int u = tid + 256 * v;
+      const int u = tid + 64 * WPB * v;
       const int uu = u < U ? u : U - 1;  // threads past the end reload the last unit
       const _Float16* base = Bq;
       if constexpr (RW) base = (uu < UE || uu >= US) ? BqE : Bq;
@@ -782,7 +782,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int u = tid + 256 * v;
+      const int u = tid + 64 * WPB * v;
       if (u < U) sb[buf][u] = stg[v];
     }
   };
@@ -941,15 +941,21 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
   for (int off = 32; off >= 1; off >>= 1) fsum += __shfl_xor(fsum, off, 64);
   if (l == 0) fw[wave] = fsum;
   __syncthreads();
-  if (tid == 0) fpart[bid] = (fw[0] + fw[1]) + (fw[2] + fw[3]);
+  if (tid == 0) {  // the block's waves in a fixed pairwise order
+    double w4[2];
+#pragma unroll
+    for (int h = 0; h < WPB / 4; ++h) w4[h] = (fw[4 * h] + fw[4 * h + 1]) + (fw[4 * h + 2] + fw[4 * h + 3]);
+    fpart[bid] = WPB == 8 ? w4[0] + w4[1] : w4[0];
+  }
 }
 
-template <int KP, bool WITH_H, typename XT>
-__global__ __launch_bounds__(256, 2) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
-                                                    const f32x4* __restrict__ Cq, const _Float16* __restrict__ Bq,
-                                                    const float* __restrict__ Bsc, float* __restrict__ Hout,
-                                                    double* __restrict__ fpart, int64_t nchunks, int vec4) {
-  colpass_body<KP, WITH_H, XT>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x);
+template <int KP, bool WITH_H, typename XT, int WPB>
+__global__ __launch_bounds__(64 * WPB, 8 / WPB) void k_colpass(const XT* __restrict__ X, int64_t M, int64_t N, int K,
+                                                               const f32x4* __restrict__ Cq,
+                                                               const _Float16* __restrict__ Bq,
+                                                               const float* __restrict__ Bsc, float* __restrict__ Hout,
+                                                               double* __restrict__ fpart, int64_t nchunks, int vec4) {
+  colpass_body<KP, WITH_H, XT, false, WPB>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x);
 }
 
 // The carried-residual form of the column pass (always forms H).
@@ -963,23 +969,35 @@ __global__ __launch_bounds__(256, 2) void k_colpass_rw(const XT* X, int64_t M, i
   colpass_body<KP, true, XT, true>(X, M, N, K, Cq, Bq, Bsc, Hout, fpart, nchunks, vec4, blockIdx.x, BqE, R, rvec4);
 }
 
-int64_t colpass_blocks(const Shape& s) { return (s.N + 127) / 128; }
+int64_t colpass_blocks(const Shape& s) {
+  const int64_t cols = 32 * (int64_t)(s.cwpb == 8 ? 8 : 4);
+  return (s.N + cols - 1) / cols;
+}
+
+template <typename XT, int WPB>
+static void colpass_launch_w(const Shape& s, const XT* X, const f32x4* C, const _Float16* Bq, const float* Bsc,
+                             float* Hout, double* fpart, int with_h, hipStream_t st) {
+  const unsigned g = (unsigned)colpass_blocks(s);
+  if (s.KP == 32) {
+    if (with_h)
+      k_colpass<32, true, XT, WPB><<<g, 64 * WPB, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
+    else
+      k_colpass<32, false, XT, WPB><<<g, 64 * WPB, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
+  } else {
+    if (with_h)
+      k_colpass<64, true, XT, WPB><<<g, 64 * WPB, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
+    else
+      k_colpass<64, false, XT, WPB><<<g, 64 * WPB, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
+  }
+}
 
 template <typename XT>
 static void colpass_launch(const Shape& s, const XT* X, const f32x4* C, const _Float16* Bq, const float* Bsc,
                            float* Hout, double* fpart, int with_h, hipStream_t st) {
-  const unsigned g = (unsigned)colpass_blocks(s);
-  if (s.KP == 32) {
-    if (with_h)
-      k_colpass<32, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
-    else
-      k_colpass<32, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
-  } else {
-    if (with_h)
-      k_colpass<64, true, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
-    else
-      k_colpass<64, false, XT><<<g, 256, 0, st>>>(X, s.M, s.N, s.K, C, Bq, Bsc, Hout, fpart, s.nchunks, s.vec4);
-  }
+  if (s.cwpb == 8)
+    colpass_launch_w<XT, 8>(s, X, C, Bq, Bsc, Hout, fpart, with_h, st);
+  else
+    colpass_launch_w<XT, 4>(s, X, C, Bq, Bsc, Hout, fpart, with_h, st);
 }
 
 template <typename XT>
@@ -1721,11 +1739,11 @@ __device__ __forceinline__ int ginst_find(const GTable* __restrict__ g, int st, 
   __syncthreads();    \
   }
 
-template <int KP, typename XT>
-__global__ __launch_bounds__(256, 2) void kg_colpass(const GTable* __restrict__ g) {
+template <int KP, typename XT, int WPB>
+__global__ __launch_bounds__(64 * WPB, 8 / WPB) void kg_colpass(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_COL)
-  colpass_body<KP, true, XT>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq), d.Bq,
-                             d.Bsc, d.H, d.fpart, d.nchunks, d.vec4, bid);
+  colpass_body<KP, true, XT, false, WPB>(static_cast<const XT*>(d.X), d.M, d.N, d.K, static_cast<const f32x4*>(d.Cq),
+                                         d.Bq, d.Bsc, d.H, d.fpart, d.nchunks, d.vec4, bid);
   DID_GROUP_END
 }
 
@@ -1835,7 +1853,7 @@ void ginst_items(const Shape& s, int R, int64_t items[GS_N]) {
   items[GS_ADV] = 1;
 }
 
-template <int KP, typename XT>
+template <int KP, typename XT, int WPB>
 static hipError_t group_grids_t(int64_t grids[GS_N]) {
   int dev = 0, cus = 0;
   hipError_t e;
@@ -1848,7 +1866,7 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
     *out = ((int64_t)std::max(per, 1) * cus + 7) / 8 * 8;
     return r;
   };
-  if ((e = occ((const void*)kg_colpass<KP, XT>, 256, 0, &grids[GS_COL])) != hipSuccess) return e;
+  if ((e = occ((const void*)kg_colpass<KP, XT, WPB>, 64 * WPB, 0, &grids[GS_COL])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_reduce_f, 256, 0, &grids[GS_REDF])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_sweep<KP>, 256, 256 * KP * sizeof(float), &grids[GS_SWEEP])) != hipSuccess) return e;
   if ((e = occ((const void*)kg_packw<KP>, 256, 0, &grids[GS_PACKW])) != hipSuccess) return e;
@@ -1862,20 +1880,25 @@ static hipError_t group_grids_t(int64_t grids[GS_N]) {
   return hipSuccess;
 }
 
-hipError_t group_grids(int KP, int xkind, int64_t grids[GS_N]) {
-  if (KP == 32) {
-    if (xkind == XK_BF16) return group_grids_t<32, __bf16>(grids);
-    if (xkind == XK_F32_TILED) return group_grids_t<32, xtf32>(grids);
-    return group_grids_t<32, float>(grids);
-  }
-  if (xkind == XK_BF16) return group_grids_t<64, __bf16>(grids);
-  if (xkind == XK_F32_TILED) return group_grids_t<64, xtf32>(grids);
-  return group_grids_t<64, float>(grids);
+template <int KP, typename XT>
+static hipError_t group_grids_k(int cwpb, int64_t grids[GS_N]) {
+  return cwpb == 8 ? group_grids_t<KP, XT, 8>(grids) : group_grids_t<KP, XT, 4>(grids);
 }
 
-template <int KP, typename XT>
+hipError_t group_grids(int KP, int xkind, int cwpb, int64_t grids[GS_N]) {
+  if (KP == 32) {
+    if (xkind == XK_BF16) return group_grids_k<32, __bf16>(cwpb, grids);
+    if (xkind == XK_F32_TILED) return group_grids_k<32, xtf32>(cwpb, grids);
+    return group_grids_k<32, float>(cwpb, grids);
+  }
+  if (xkind == XK_BF16) return group_grids_k<64, __bf16>(cwpb, grids);
+  if (xkind == XK_F32_TILED) return group_grids_k<64, xtf32>(cwpb, grids);
+  return group_grids_k<64, float>(cwpb, grids);
+}
+
+template <int KP, typename XT, int WPB>
 static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st) {
-  kg_colpass<KP, XT><<<(unsigned)gr[GS_COL], 256, 0, st>>>(t);
+  kg_colpass<KP, XT, WPB><<<(unsigned)gr[GS_COL], 64 * WPB, 0, st>>>(t);
   kg_reduce_f<<<(unsigned)gr[GS_REDF], 256, 0, st>>>(t);
   kg_sweep<KP><<<(unsigned)gr[GS_SWEEP], 256, 256 * KP * sizeof(float), st>>>(t);
   kg_packw<KP><<<(unsigned)gr[GS_PACKW], 256, 0, st>>>(t);
@@ -1888,21 +1911,30 @@ static void group_iteration_t(const GTable* t, const int64_t* gr, hipStream_t st
   kg_advance<<<(unsigned)gr[GS_ADV], 64, 0, st>>>(t);
 }
 
-hipError_t group_iteration(int KP, int xkind, const GTable* dtab, const int64_t grids[GS_N], hipStream_t st) {
+template <int KP, typename XT>
+static void group_iteration_k(int cwpb, const GTable* t, const int64_t* gr, hipStream_t st) {
+  if (cwpb == 8)
+    group_iteration_t<KP, XT, 8>(t, gr, st);
+  else
+    group_iteration_t<KP, XT, 4>(t, gr, st);
+}
+
+hipError_t group_iteration(int KP, int xkind, int cwpb, const GTable* dtab, const int64_t grids[GS_N],
+                           hipStream_t st) {
   if (KP == 32) {
     if (xkind == XK_BF16)
-      group_iteration_t<32, __bf16>(dtab, grids, st);
+      group_iteration_k<32, __bf16>(cwpb, dtab, grids, st);
     else if (xkind == XK_F32_TILED)
-      group_iteration_t<32, xtf32>(dtab, grids, st);
+      group_iteration_k<32, xtf32>(cwpb, dtab, grids, st);
     else
-      group_iteration_t<32, float>(dtab, grids, st);
+      group_iteration_k<32, float>(cwpb, dtab, grids, st);
   } else {
     if (xkind == XK_BF16)
-      group_iteration_t<64, __bf16>(dtab, grids, st);
+      group_iteration_k<64, __bf16>(cwpb, dtab, grids, st);
     else if (xkind == XK_F32_TILED)
-      group_iteration_t<64, xtf32>(dtab, grids, st);
+      group_iteration_k<64, xtf32>(cwpb, dtab, grids, st);
     else
-      group_iteration_t<64, float>(dtab, grids, st);
+      group_iteration_k<64, float>(cwpb, dtab, grids, st);
   }
   return hipGetLastError();
 }

@@ -40,9 +40,9 @@ def test_default_opts_and_struct_layout():
     _lib_or_skip()
     o = did.did_default_opts()
     assert (o.n_blocks, o.x_dtype, o.refresh_every, o.init_scale, o.borrow_x) == (0, did.DID_F32, 1, 0, 0)
-    assert (o.algorithm, o.row_blocks, o.x_tiled) == (did.DID_ALG_DID, 0, 0)
+    assert (o.algorithm, o.row_blocks, o.x_tiled, o.col_waves) == (did.DID_ALG_DID, 0, 0, 0)
     assert o.stream is None
-    assert ctypes.sizeof(did.did_opts) == 40
+    assert ctypes.sizeof(did.did_opts) == 48
     so = did.did_server_default_opts()
     assert (so.hbm_budget, so.max_active, so.max_iter, so.rel_tol) == (200 << 30, 64, 50, 1e-4)
     assert ctypes.sizeof(did.did_server_opts) == 40
@@ -195,3 +195,25 @@ def test_carried_residual_options_without_device():
         with pytest.raises(did.DidError) as ei:
             did.did_mem_estimate(M, N, K, o)
         assert ei.value.code == did.DID_EINVAL
+
+
+def test_column_tile_option_without_device():
+    """col_waves picks 4 or 8 waves per column-pass block; the per-block objective
+    partials shrink with 8, and the carried form refuses 8."""
+    _lib_or_skip()
+    M, N, K = 1000, 1_000_000, 20
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    base = did.did_mem_estimate(M, N, K, o)
+    o.col_waves = 4
+    assert did.did_mem_estimate(M, N, K, o) == base
+    o.col_waves = 8
+    # one f64 partial per block: N/128 blocks with 4 waves, N/256 with 8
+    assert base - did.did_mem_estimate(M, N, K, o) == 8 * (N // 128 - N // 256)
+    for cw, r in ((6, 1), (-1, 1), (8, 10)):
+        o.col_waves, o.refresh_every = cw, r
+        with pytest.raises(did.DidError) as ei:
+            did.did_mem_estimate(M, N, K, o)
+        assert ei.value.code == did.DID_EINVAL
+    o.col_waves, o.refresh_every = 4, 10
+    assert did.did_mem_estimate(M, N, K, o) > base

@@ -38,19 +38,20 @@ SHAPES = [(300, 2000, 10, did.DID_F32), (777, 1500, 40, did.DID_F32), (130, 5000
           (611, 3333, 50, TILED)]
 
 
-def _make(torch, M, N, K, xd, seed):
+def _make(torch, M, N, K, xd, seed, cw=4):
     X = to_f32_colmajor(serving_x(M, N, K, seed=seed))
     Xd = device_x(torch, X)
     o = did.did_default_opts()
     o.x_dtype = did.DID_BF16 if xd == did.DID_BF16 else did.DID_F32
     o.x_tiled = 1 if xd == TILED else 0
     o.borrow_x = 1 if xd == did.DID_F32 else 0
+    o.col_waves = cw
     h = did.did_init_ex(Xd, M, N, K, 1000 + seed, o)
     return h, Xd
 
 
-def _alone(torch, M, N, K, xd, seed, iters):
-    h, Xd = _make(torch, M, N, K, xd, seed)
+def _alone(torch, M, N, K, xd, seed, iters, cw=4):
+    h, Xd = _make(torch, M, N, K, xd, seed, cw)
     try:
         did.did_iterate(h, iters)
         B, C = read_factors(h, M, N, K)
@@ -62,11 +63,14 @@ def _alone(torch, M, N, K, xd, seed, iters):
 
 
 def test_batch_equals_alone_bitwise_every_replay():
+    """Every other member runs the column pass with 8 waves per block, so each (K class,
+    X storage) pair is split over two groups of different column tiles."""
     torch = require_gpu()
     T = 5
     announce(f"batch of {len(SHAPES)} vs alone")
-    ref = [_alone(torch, M, N, K, xd, i, T) for i, (M, N, K, xd) in enumerate(SHAPES)]
-    made = [_make(torch, M, N, K, xd, i) for i, (M, N, K, xd) in enumerate(SHAPES)]
+    cws = [8 if i % 2 else 4 for i in range(len(SHAPES))]
+    ref = [_alone(torch, M, N, K, xd, i, T, cws[i]) for i, (M, N, K, xd) in enumerate(SHAPES)]
+    made = [_make(torch, M, N, K, xd, i, cws[i]) for i, (M, N, K, xd) in enumerate(SHAPES)]
     b = did.did_batch_create()
     try:
         for h, _ in made:
@@ -265,15 +269,21 @@ def test_autotune_records_and_applies():
         o = did.did_default_opts()
         o.borrow_x = 1
         before = did.did_mem_estimate(M, N, K, o)
-        rb, ms = did.did_autotune(M, N, K)
-        assert rb in (512, 1024, 2048, 4096, 8192) and ms > 0.0
+        rb, cw, ms = did.did_autotune(M, N, K)
+        assert rb in (512, 1024, 2048, 4096, 8192) and cw in (4, 8) and ms > 0.0
         o2 = did.did_default_opts()
         o2.borrow_x = 1
         o2.row_blocks = rb
+        o2.col_waves = cw
         # instances created afterwards with row_blocks = 0 take the tuned value (their
         # footprint includes the W partials of its column ranges)
         assert did.did_mem_estimate(M, N, K, o) == did.did_mem_estimate(M, N, K, o2)
         assert before > 0
+        # the tiled float32 storage is a shape class of its own: still the defaults
+        ot, od = did.did_default_opts(), did.did_default_opts()
+        ot.x_tiled = od.x_tiled = 1
+        od.row_blocks, od.col_waves = 4096, 4
+        assert did.did_mem_estimate(M, N, K, ot) == did.did_mem_estimate(M, N, K, od)
         X = torch.rand((N, M), device="cuda")
         torch.cuda.synchronize()  # the engine reads X on its own stream
         h = did.did_init_ex(X, M, N, K, 5, o)

@@ -86,17 +86,20 @@ def _sampled_golden_factors(g, out):
     check_factors(out[1][0][rows], B1o, out[1][1][:, cols], C1o, label=f"{g['case']}, sampled, 1 iteration")
 
 
-@pytest.mark.parametrize("case", ["image_like_p4", "large_slice_b1", "large_slice_b4"])
-def test_named_workloads_parity_50_iterations(case):
+@pytest.mark.parametrize("case,cw", [("image_like_p4", 4), ("image_like_p4", 8), ("large_slice_b1", 4),
+                                     ("large_slice_b1", 8), ("large_slice_b4", 4)])
+def test_named_workloads_parity_50_iterations(case, cw):
     """The image-like workload (784 x 70000, K = 16, 4 blocks) and slices of the large one
     (5000 x 15625 and 5000 x 62500, K = 50, 1 and 4 blocks) from the same initial factors as
     the oracle: factors after one iteration (all of them, or for the 4-block slice sampled
-    columns and rows the oracle recorded) and the objective over 50 iterations."""
+    columns and rows the oracle recorded) and the objective over 50 iterations, with both
+    column-pass tiles (4 and 8 waves per block)."""
     torch = require_gpu()
     g, X32, Xo, K, P, T, _, B0, C0 = _golden_case(case)
     o = did.did_default_opts()
     o.n_blocks = P
-    announce(f"{case}: {X32.shape[0]}x{X32.shape[1]} K={K} P={P}, {T} iterations")
+    o.col_waves = cw
+    announce(f"{case}: {X32.shape[0]}x{X32.shape[1]} K={K} P={P} col_waves={cw}, {T} iterations")
     out = run_gpu(torch, X32, K, iters=(1, T), opts=o, B0=B0.astype(np.float32), C0=C0.astype(np.float32))
     np.testing.assert_array_equal(out["init"][0], B0)
     if "sample_cols" in g:
@@ -301,6 +304,31 @@ def test_deterministic_bitwise():
     np.testing.assert_array_equal(a[7][0], b[7][0])
     np.testing.assert_array_equal(a[7][1], b[7][1])
     np.testing.assert_array_equal(a["hist"], b["hist"])
+
+
+@pytest.mark.parametrize("M,N,K,storage", [(300, 1000, 10, "f32"), (130, 777, 40, "tiled"), (97, 1234, 64, "bf16"),
+                                            (64, 200, 7, "f32"), (40, 300, 33, "f32")])
+def test_column_tile_choice_keeps_factors_bitwise(M, N, K, storage):
+    """Each wave of the column pass owns one 32-column tile whatever the block size, so
+    B, C (and H) are the same bit for bit with 4 or 8 waves per block; only the objective's
+    summation order changes (ragged N: 1000, 777, 1234, 200 and 300 columns are not
+    multiples of 256)."""
+    torch = require_gpu()
+    X, _, _ = planted_lowrank(M, N, K, seed=21)
+    X32 = to_f32_colmajor(X)
+    res = []
+    for cw in (4, 8):
+        o = did.did_default_opts()
+        o.x_dtype = did.DID_BF16 if storage == "bf16" else did.DID_F32
+        o.x_tiled = 1 if storage == "tiled" else 0
+        o.col_waves = cw
+        announce(f"{M}x{N} K={K} {storage} col_waves={cw}")
+        res.append(run_gpu(torch, X32, K, iters=(1, 6), opts=o))
+    for t in (1, 6):
+        np.testing.assert_array_equal(res[0][t][0], res[1][t][0])
+        np.testing.assert_array_equal(res[0][t][1], res[1][t][1])
+    np.testing.assert_allclose(res[1]["hist"], res[0]["hist"], rtol=1e-12)
+    assert res[1]["f"] == pytest.approx(res[0]["f"], rel=1e-12)
 
 
 def test_block_count_only_changes_rounding():
