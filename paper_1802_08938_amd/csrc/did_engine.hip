@@ -111,12 +111,12 @@ void release(did_ctx* h) {
   DeviceGuard g(h->dev);
   if (h->st) (void)hipStreamSynchronize(h->st);
   if (h->st2) (void)hipStreamSynchronize(h->st2);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   for (hipEvent_t ev : h->prof_events) (void)hipEventDestroy(ev);
   if (h->ev_c) (void)hipEventDestroy(h->ev_c);
   if (h->ev_v) (void)hipEventDestroy(h->ev_v);
   if (h->st2) (void)hipStreamDestroy(h->st2);
   h->prof_events.clear();
-  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
@@ -492,11 +492,12 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
   return DID_OK;
 }
 
-// One iteration of the MFMA path on the buffers of h, enqueued on h->st (and h->st2), with
-// a profiling event before the first and after every stage when ev is given.  The
-// objective goes to fhist at the device iteration counter tdev, so the launches carry no
-// host iteration index (the same launches can be captured once and replayed).
-static int enqueue_iteration(did_ctx* h, hipEvent_t* ev) {
+// One iteration of the MFMA path on the buffers of h, enqueued on h->st (and, unless
+// one_stream, the V stages on h->st2), with a profiling event before the first and after
+// every stage when ev is given.  The objective goes to fhist at the device iteration
+// counter tdev, so the launches carry no host iteration index (the same launches can be
+// captured once and replayed).
+static int enqueue_iteration(did_ctx* h, hipEvent_t* ev, bool one_stream = false) {
   const Shape& s = h->s;
   hipError_t e;
 #define DID_MARK(q) \
@@ -520,17 +521,18 @@ static int enqueue_iteration(did_ctx* h, hipEvent_t* ev) {
     return dev_fail(h, e, "sweep");
   // V = tril(C'C'^T), on the second stream when there is one (overlapped with the row pass
   // and the W reduction; the B update waits for it)
+  hipStream_t st2 = one_stream ? nullptr : h->st2;
   hipStream_t sv = h->st;
-  if (h->st2) {
+  if (st2) {
     if ((e = hipEventRecord(h->ev_c, h->st)) != hipSuccess ||
-        (e = hipStreamWaitEvent(h->st2, h->ev_c, 0)) != hipSuccess)
+        (e = hipStreamWaitEvent(st2, h->ev_c, 0)) != hipSuccess)
       return dev_fail(h, e, "stream order");
-    sv = h->st2;
+    sv = st2;
   }
   if ((e = didk::vgram(s, h->Cq, h->Csc, h->Vpart, sv)) != hipSuccess) return dev_fail(h, e, "V partials");
   if ((e = didk::reduce_sym(h->Vpart, didk::vgram_blocks(s), s.KP, h->V, sv)) != hipSuccess)
     return dev_fail(h, e, "V reduce");
-  if (h->st2 && (e = hipEventRecord(h->ev_v, h->st2)) != hipSuccess) return dev_fail(h, e, "stream order");
+  if (st2 && (e = hipEventRecord(h->ev_v, st2)) != hipSuccess) return dev_fail(h, e, "stream order");
   DID_MARK(3);
   DID_MARK(4);
   if (carry)
@@ -541,7 +543,7 @@ static int enqueue_iteration(did_ctx* h, hipEvent_t* ev) {
   DID_MARK(5);
   if ((e = didk::reduce_w(s, h->Wpart, h->R, h->W, h->st)) != hipSuccess) return dev_fail(h, e, "W reduce");
   DID_MARK(6);
-  if (h->st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
+  if (st2 && (e = hipStreamWaitEvent(h->st, h->ev_v, 0)) != hipSuccess) return dev_fail(h, e, "stream order");
   if ((e = didk::bupdate(s, h->B, h->W, h->V, h->Bq, h->Bsc, h->Gpart, 1, h->st, carry ? h->BqD : nullptr)) !=
       hipSuccess)
     return dev_fail(h, e, "B update");
@@ -558,7 +560,10 @@ static int enqueue_iteration(did_ctx* h, hipEvent_t* ev) {
 // their reduction overlap the row pass; without one they run in order on h->st.  Without
 // profiling, two or more iterations of the refresh-every-iteration form replay one
 // captured iteration (a hipGraph kept by the handle), which removes the host launch cost
-// that bounds small shapes.
+// that bounds small shapes.  The captured iteration runs on h->st alone: a capture that
+// forks onto a second stream and joins back left the device memory its kernels use
+// allocated after hipGraphExecDestroy and hipFree (measured on ROCm 7.2), so the V stages
+// give up their overlap with the row pass there.
 int iterate_mfma(did_ctx* h, int32_t n) {
   hipError_t e;
   if (n <= 0) return DID_OK;
@@ -569,7 +574,7 @@ int iterate_mfma(did_ctx* h, int32_t n) {
         (void)hipGetLastError();
         h->graph_failed = true;
       } else {
-        const int rc = enqueue_iteration(h, nullptr);
+        const int rc = enqueue_iteration(h, nullptr, true);
         e = hipStreamEndCapture(h->st, &g);
         if (rc) {
           if (g) (void)hipGraphDestroy(g);

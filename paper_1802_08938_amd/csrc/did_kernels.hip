@@ -818,15 +818,18 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     }
   };
 
-  // One chunk: compute chunk c from the X tile in acc (loaded one chunk earlier) and the
+  // One chunk: compute chunk c from the X tile in xc (loaded one chunk earlier) and the
   // staged B operands in LDS buffer c & 1; meanwhile stage chunk c+1's B operands and load
   // its X tile into xn (the two tiles alternate roles from one chunk to the next, so
   // nothing is copied).
-  auto step = [&](int64_t c, f32x16& acc, f32x16& xn) {
+  auto step = [&](int64_t c, const f32x16& xc, f32x16& xn) {
     const int buf = (int)(c & 1);
     const int64_t cn = c + 1 < nchunks ? c + 1 : c;
     gload(cn);
     xn = xload(cn);
+    // E of the chunk, a value of its own (not written over the X tile, which would make the
+    // two alternating tiles cost a copy per chunk)
+    f32x16 acc;
     {  // E = X - B C: KS steps of three MFMAs, operands of step s+1 read from LDS during step s
       const f32x4* ue = &sb[buf][0] + l;
       f16x8 a[2], an[2];
@@ -853,7 +856,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
       for (int q = 0; q < 4; ++q) {
         const f32x4 r4 = rs[2 * q + half];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, acc[4 * q + e]);
+        for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, xc[4 * q + e]);
       }
     }
     if constexpr (RW) rstore(c, acc);
@@ -1398,14 +1401,15 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     }
   };
 
-  // One tile: compute tile T from the X tile in acc (loaded one tile earlier) and the
+  // One tile: compute tile T from the X tile in xc (loaded one tile earlier) and the
   // staged C' operands in LDS buffer buf; meanwhile stage tile T+1 and load its X tile
   // into xn.
-  auto step = [&](int64_t T, int buf, f32x16& acc, f32x16& xn) {
+  auto step = [&](int64_t T, int buf, const f32x16& xc, f32x16& xn) {
     const int64_t Tn = T + 1 < thi ? T + 1 : T;
     cdma(Tn, buf ^ 1);
     xn = xload(Tn);
     if (active) {
+      f32x16 acc;  // E' of the tile (the X tile in xc stays as loaded)
       {
         const f32x4* ue = &sc[buf][0] + l;
         f16x8 a[2], an[2];
@@ -1432,7 +1436,7 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
         for (int q = 0; q < 4; ++q) {
           const f32x4 t4 = ts[2 * q + half];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, acc[4 * q + e]);
+          for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, xc[4 * q + e]);
         }
       }
       if constexpr (RW) {  // E' back into the residual, where it was read

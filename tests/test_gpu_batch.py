@@ -295,6 +295,46 @@ def test_autotune_records_and_applies():
         did.did_autotune_clear()
 
 
+def test_free_returns_device_memory_after_graph_replays():
+    """did_free gives back all of an instance's device memory after replayed iterations (a
+    captured hipGraph), alone and after membership of a batch: three create / iterate /
+    free cycles of a 3.2 GB (tiled X) instance leave the device's free memory where it was."""
+    torch = require_gpu()
+    M, N, K = 2000, 200_000, 20
+    announce("device memory after free, graph replays")
+    X = torch.rand((N, M), device="cuda")
+    torch.cuda.synchronize()
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    o.x_tiled = 1
+    need = did.did_mem_estimate(M, N, K, o)
+    base = torch.cuda.mem_get_info()[0]
+    for cycle in range(3):
+        h = did.did_init_ex(X, M, N, K, 3 + cycle, o)
+        did.did_iterate(h, 3)
+        did.did_sync(h)
+        did.did_free(h)
+        torch.cuda.synchronize()
+        held = base - torch.cuda.mem_get_info()[0]
+        assert held < need / 4, (cycle, held, need)
+    for cycle in range(2):
+        hs = [did.did_init_ex(X, M, N, K, 10 + i, o) for i in range(2)]
+        b = did.did_batch_create()
+        try:
+            for h in hs:
+                did.did_batch_add(b, h)
+            did.did_batch_iterate(b, 3)
+            for h in hs:
+                did.did_batch_remove(b, h)
+        finally:
+            did.did_batch_free(b)
+            for h in hs:
+                did.did_free(h)
+        torch.cuda.synchronize()
+        held = base - torch.cuda.mem_get_info()[0]
+        assert held < need / 4, ("batch", cycle, held, need)
+
+
 @pytest.mark.parametrize("M,N,K,xd,borrow,tiled,refresh", [
     (300, 2000, 10, did.DID_F32, 1, 0, 1), (300, 2000, 10, did.DID_F32, 0, 0, 1),
     (130, 777, 64, did.DID_BF16, 0, 0, 1), (5, 1000, 3, did.DID_F32, 1, 0, 1),
