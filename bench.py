@@ -17,7 +17,8 @@ Prints one JSON line:
                  objective error against the FP64 oracle (original X and bf16(X)) on the
                  first column block over 50 iterations,
   batched_form   48 served-distribution jobs advanced as one batch against one after
-                 another: instance-iterations/s and speedup,
+                 another: instance-iterations/s and speedup, and the batch again with the
+                 tiles did_autotune picks per shape class against the default tiles,
   served_form    a shortened served run (300 jobs of the Poisson schedule): solves/s,
                  p50/p99 latency, queue depth, share of jobs stopped by the 1e-4 rule,
   cpu_baseline   the FP64 oracle timed on a bounded sample of the same workload.
@@ -31,7 +32,8 @@ Table 2 (16 CPU nodes), and iterations/s at N = 10^8 as the line's value.
 distribution (M ~ U{100..4000}, N ~ LogU[1e3, 2e5], K ~ U{5..64}) for --steps
 iterations, once one instance after another (the plain form) and once as one batch
 (grouped persistent kernels replayed from a hipGraph), and reports the batched rate, its
-speedup and the bitwise agreement of the results.  ``--workload serve`` runs the serving
+speedup and the bitwise agreement of the results, then tunes the tiles of each shape
+class among the jobs and reports the tuned batch against the default tiles.  ``--workload serve`` runs the serving
 form: Poisson arrivals at 200 jobs/s, admission by a 200 GB budget, continuous batching,
 each job to 50 iterations or a relative objective change below 1e-4; it reports solves/s
 and p50/p99 latency from the scheduled arrival to retirement.  ``--workload nsweep`` times
@@ -484,7 +486,7 @@ def _job_inputs(torch, jobs, x_dtype):
     return out
 
 
-def batch_measure(torch, did, n_jobs, T, W, x_given):
+def batch_measure(torch, did, n_jobs, T, W, x_given, tune=True):
     """Plain form (instances one after another) against the batched form on the same jobs
     from the served workload's shape distribution; returns a dict of rates."""
     import numpy as np
@@ -541,6 +543,7 @@ def batch_measure(torch, did, n_jobs, T, W, x_given):
         ev1.record(stream)
         torch.cuda.synchronize()
         batch_ms = ev0.elapsed_time(ev1)
+        f_default = np.array(did.did_batch_objectives(b))
         same = True
         for h, j, Cp in zip(hs, jobs, plain_C):
             did.did_batch_remove(b, h)
@@ -551,6 +554,7 @@ def batch_measure(torch, did, n_jobs, T, W, x_given):
         did.did_batch_free(b)
         for h in hs:
             did.did_free(h)
+    tuned = tuned_batch(torch, did, jobs, Xs, stream, T, W, x_given, batch_ms, f_default) if tune else None
     del Xs
     torch.cuda.empty_cache()
     n_it = len(jobs) * T
@@ -562,12 +566,75 @@ def batch_measure(torch, did, n_jobs, T, W, x_given):
             "plain_tflops_fp32_equiv": round(flops_it * T / (plain_ms / 1e3) / 1e12, 2),
             "results_bitwise_equal_to_plain": bool(same),
             "objective_error_vs_plain_form": 0.0 if same else None,
+            "tuned_tiles": tuned,
             "x_layout": "as given (column-major)" if x_given else "tile order (x_tiled=1)"}
+
+
+def _log2_class(v):
+    c = 0
+    while v > 1:
+        v = (v + 1) >> 1
+        c += 1
+    return c
+
+
+def tuned_batch(torch, did, jobs, Xs, stream, T, W, x_given, default_ms, f_default):
+    """The same batch after did_autotune picked the tiles (column-pass block waves, row-pass
+    ranges) of each shape class among the jobs (tuned on the class's first job); against
+    the default tiles.  The tuning table is cleared afterwards."""
+    import time
+
+    import numpy as np
+
+    classes = {}
+    for j in jobs:
+        classes.setdefault((j["K"] <= 32, _log2_class(j["M"]), _log2_class(j["N"])), j)
+    did.did_autotune_clear()
+    picks = {}
+    try:
+        t0 = time.perf_counter()
+        for key, j in classes.items():
+            rb, cw, _ = did.did_autotune(j["M"], j["N"], j["K"], did.DID_F32, 0 if x_given else 1)
+            picks[f"{rb}/{cw}"] = picks.get(f"{rb}/{cw}", 0) + 1
+        tune_s = time.perf_counter() - t0
+        log(f"batch: tuned {len(classes)} shape classes in {tune_s:.1f} s")
+        hs = []
+        for j, X in zip(jobs, Xs):
+            o = did.did_default_opts()
+            o.borrow_x = 1
+            o.x_tiled = 0 if x_given else 1
+            o.stream = stream.cuda_stream
+            hs.append(did.did_init_ex(X, j["M"], j["N"], j["K"], 1000 + j["seed"], o))
+        b = did.did_batch_create(stream.cuda_stream)
+        try:
+            for h in hs:
+                did.did_batch_add(b, h)
+            did.did_batch_iterate(b, W)
+            did.did_batch_sync(b)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            did.did_batch_iterate(b, T)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            f = np.array(did.did_batch_objectives(b))
+        finally:
+            did.did_batch_free(b)
+            for h in hs:
+                did.did_free(h)
+    finally:
+        did.did_autotune_clear()
+    return {"shape_classes": len(classes), "tuning_s": round(tune_s, 2),
+            "choices_row_blocks_col_waves": picks,
+            "ms_per_batched_iteration": round(ms / T, 4),
+            "speedup_vs_default_tiles": round(default_ms / ms, 3),
+            # the tiles change only summation order: the objectives after the same iterations
+            "objective_max_rel_diff_vs_default_tiles": float(np.max(np.abs(f - f_default) / f_default))}
 
 
 def run_batch(args, torch, did):
     cfg = WORKLOADS["batch"]
-    r = batch_measure(torch, did, cfg["jobs"], args.steps, args.warmup, args.x_given)
+    r = batch_measure(torch, did, cfg["jobs"], args.steps, args.warmup, args.x_given, tune=not args.no_tune)
     line = {
         "metric": METRIC,
         "value": r["instance_iter_s"],
@@ -785,6 +852,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="large workload: skip the precision, batched and served forms (profiling runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload and batched form: skip the tuned-tiles leg (profiling runs)")
     ap.add_argument("--paper-max-n", type=float, default=1e8, help="paper workload: largest N")
     ap.add_argument("--no-table", action="store_true", help="paper workload: skip the runs to the stopping rule")
     ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")

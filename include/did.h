@@ -233,7 +233,8 @@ int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int3
                      int64_t* bytes);
 
 /*
- * Tile autotuner.  Times DID iterations (three, after one warm-up) of a synthetic
+ * Tile autotuner.  Times DID iterations (after one warm-up, the better of two runs of
+ * enough iterations to fill about 10 ms, at least three) of a synthetic
  * U[0,1) instance of shape (M, N, K) and X storage (x_dtype, and x_tiled for DID_F32;
  * ignored for DID_BF16) for each pair of column-pass block waves (4, 8) and row_blocks
  * value (512, 1024, 2048, 4096, 8192), records the fastest pair for the shape class

@@ -1,7 +1,7 @@
-// Batched and serving forms of the DID engine, and the row-pass autotuner.
+// Batched and serving forms of the DID engine, and the tile autotuner.
 //
 // Batch: many instances of uneven (M, N, K) advance together.  Members are grouped by
-// (KP, X storage); each group has a device-resident table of instance descriptors and
+// (KP, X storage, column-pass block waves); each group has a device-resident table of instance descriptors and
 // work-item prefixes, and one iteration of every member is one launch per stage and group
 // of a grouped persistent kernel (did_kernels.hip).  The launch sequence is captured once
 // into a hipGraph and replayed per iteration; admitting or removing members only rewrites
@@ -37,7 +37,7 @@ using didk::GTable;
 using didk::kMaxBatch;
 constexpr int kGroups = 2 * didk::XK_N * 2;  // (K class, X storage kind, column-pass block waves)
 
-// ------------------------------------------------------------------ autotuned row pass
+// ------------------------------------------------------------------ autotuned tiles
 namespace {
 
 std::mutex g_tune_mu;
@@ -423,15 +423,26 @@ int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t x_til
       o.stream = st;
       did_handle h = nullptr;
       if ((rc = did_init_ex(X, M, N, K, 1, &o, &h))) break;
-      float ms = 0.0f;
-      if ((rc = did_iterate(h, 1)) == DID_OK && hipEventRecord(e0, st) == hipSuccess &&
-          (rc = did_iterate(h, 3)) == DID_OK && hipEventRecord(e1, st) == hipSuccess &&
-          hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-        const double per = ms / 3.0;
-        if (!best.row_blocks || per < best_ms) {
-          best = Tuned{cand, cw};
-          best_ms = per;
-        }
+      // one warm-up iteration, then the best of two runs of enough iterations to fill about
+      // 10 ms (at least 3), so that short iterations are not timed one launch at a time
+      double per = 0.0;
+      int reps = 3;
+      bool ok = (rc = did_iterate(h, 1)) == DID_OK;
+      for (int run = 0; ok && run < 3; ++run) {
+        float ms = 0.0f;
+        const int n = run == 0 ? 1 : reps;
+        ok = hipEventRecord(e0, st) == hipSuccess && (rc = did_iterate(h, n)) == DID_OK &&
+             hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok) break;
+        if (run == 0)
+          reps = std::max(3, std::min(200, (int)std::ceil(10.0 / std::max(ms, 1e-3f))));
+        else if (run == 1 || ms / reps < per)
+          per = ms / reps;
+      }
+      if (ok && (!best.row_blocks || per < best_ms)) {
+        best = Tuned{cand, cw};
+        best_ms = per;
       }
       did_free(h);
       if (rc) break;
