@@ -388,6 +388,8 @@ int did_autotune(int64_t M, int64_t N, int32_t K, int32_t x_dtype, int32_t x_til
   *col_waves = 0;
   if (x_dtype != DID_F32 && x_dtype != DID_BF16) return fail(DID_EINVAL, "x_dtype must be DID_F32 or DID_BF16");
   if (x_tiled != 0 && x_tiled != 1) return fail(DID_EINVAL, "x_tiled must be 0 or 1");
+  int rc0 = check_shape(M, N, K);  // before the tuning input is sized from M N
+  if (rc0) return rc0;
   if (M <= 16 && K <= 8 && (M <= 8 || K <= 4))
     return fail(DID_EINVAL, "thin-matrix shapes have no row pass to tune");
   // a synthetic X of the shape: U[0,1) entries from the engine's own generator

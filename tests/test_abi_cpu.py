@@ -217,3 +217,15 @@ def test_column_tile_option_without_device():
         assert ei.value.code == did.DID_EINVAL
     o.col_waves, o.refresh_every = 4, 10
     assert did.did_mem_estimate(M, N, K, o) > base
+
+
+def test_autotune_argument_checks_without_device():
+    """The autotuner validates its arguments before it allocates the tuning input."""
+    L = _lib_or_skip()
+    rb, cw = ctypes.c_int32(7), ctypes.c_int32(7)
+    bad = [(0, 10, 1, did.DID_F32, 0), (100, 100, 65, did.DID_F32, 0), (5, 1000, 3, did.DID_F32, 0),
+           (100, 100, 10, 7, 0), (100, 100, 10, did.DID_F32, 2), (1 << 41, 10, 3, did.DID_F32, 1)]
+    for M, N, K, xd, xt in bad:
+        assert L.did_autotune(M, N, K, xd, xt, ctypes.byref(rb), ctypes.byref(cw), None) == did.DID_EINVAL, (M, N, K)
+        assert (rb.value, cw.value) in ((0, 0), (7, 7))
+    assert L.did_autotune(100, 100, 10, did.DID_F32, 0, ctypes.byref(rb), None, None) == did.DID_EINVAL
