@@ -40,6 +40,9 @@ each job to 50 iterations or a relative objective change below 1e-4; it reports 
 and p50/p99 latency from the scheduled arrival to retirement.  ``--workload nsweep`` times
 the large workload's recipe at N = 1.25e5 ... 1e6 (the method's cost per iteration is
 linear in N) and reports the time per iteration and per 10^5 columns at each size.
+``--workload planted`` (500 x 2000, K = 10) and ``--workload image`` (784 x 70000, K = 16)
+time the small shapes, whose iterations are replayed from a captured graph, beside the
+launch floor: the replay time of a graph of as many empty dependent kernels.
 
 The engine keeps float32 X in 32x32 tile order (one copy per pass, made at init) for the
 MFMA-path workloads and the batch; --x-given reads it as given (column-major) instead.
@@ -288,6 +291,36 @@ def device_env(torch):
     except OSError:
         pass
     return env
+
+
+def launch_floor(torch, n_kernels, replays=200):
+    """Time per replay of a captured graph of n_kernels dependent one-element kernels
+    (torch's in-place add): what launching one iteration's kernels costs when they do no
+    work, the floor for shapes whose kernels are short."""
+    x = torch.zeros(1, device="cuda")
+    for _ in range(3):
+        x.add_(1.0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(n_kernels):
+            x.add_(1.0)
+    for _ in range(10):
+        g.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(replays):
+        g.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / replays
+
+
+# kernels one iteration of the MFMA path launches: column pass, f reduction, clearing of
+# the C maxima, sweep, W-order packing, V partials, V reduction, row pass, W reduction,
+# clearing of the B maxima, B update, H-order packing, G reduction
+KERNELS_PER_ITERATION = 13
 
 
 def emit(torch, line):
@@ -992,6 +1025,13 @@ def main():
         "init_s": round(init_s, 3),
         "roofline": roof,
     }
+    if args.workload in ("planted", "image"):
+        floor_ms = launch_floor(torch, KERNELS_PER_ITERATION)
+        line["launch_floor"] = {
+            "kernels_per_iteration": KERNELS_PER_ITERATION, "graph_replay_ms": round(floor_ms, 4),
+            "iter_s_at_floor": round(1000.0 / floor_ms, 1), "ms_per_step_over_floor": round(ms / floor_ms, 2),
+            "note": "a captured graph of as many dependent one-element kernels as one iteration launches, "
+                    "replayed: the iteration's cost if its kernels did no work"}
     if f32_ref is not None:
         line["config"]["x_storage"] = "bf16"
         line["objective_f32_form_same_iterations"] = f32_ref

@@ -1,4 +1,4 @@
-"""GPU tests of the batched and serving forms, the row-pass autotuner and the memory
+"""GPU tests of the batched and serving forms, the tile autotuner and the memory
 accounting, all through the C ABI.
 
 A batch member runs exactly the blocks of its own single-instance launch (through the
