@@ -96,7 +96,8 @@ enum {
  *   row_blocks     tile shape of the row pass along N: about this many (column range,
  *                  32-row slab group) blocks per launch, which sets the number of column
  *                  ranges whose W partials are summed (in ascending order).  0 takes the
- *                  value did_autotune recorded for the instance's shape class, else 4096.
+ *                  value did_autotune recorded for the instance's shape class, else
+ *                  N / 256 clamped to [512, 4096].
  *                  Results depend on it only through summation order.
  *   x_tiled        float32 form only.  0: the passes read X as given (column-major).
  *                  1: the engine keeps X as two float32 copies in 32 x 32 tile order, one

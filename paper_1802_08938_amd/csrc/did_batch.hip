@@ -72,7 +72,7 @@ namespace didengine {
 int tuned_row_blocks(int64_t M, int64_t N, int KP, int xkind) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(shape_class(M, N, KP, xkind));
-  return it == g_tuned.end() ? 4096 : it->second.row_blocks;
+  return it == g_tuned.end() ? 0 : it->second.row_blocks;  // 0: the default target
 }
 
 int tuned_col_waves(int64_t M, int64_t N, int KP, int xkind) {

@@ -82,7 +82,7 @@ int check_handle(did_ctx* h);       // non-NULL and not sticky-failed
 int check_free_handle(did_ctx* h);  // check_handle and not a batch member
 
 // Row-pass target recorded by did_autotune for the shape class of (M, N, KP, X storage),
-// else the default (4096).
+// else 0 (range_params's default).
 int tuned_row_blocks(int64_t M, int64_t N, int KP, int xkind);
 // Column-pass waves per block recorded by did_autotune for the shape class, else 4.
 int tuned_col_waves(int64_t M, int64_t N, int KP, int xkind);

@@ -130,9 +130,12 @@ void release(did_ctx* h) {
 void range_params(int64_t N, int64_t nchunks, int n_blocks, int row_blocks, int64_t* T, int64_t* P, int64_t* S) {
   *T = (N + 31) / 32;
   const int64_t slab_groups = (nchunks + 3) / 4;
-  // about row_blocks blocks of (range, slab group) (default 4096: several rounds of
-  // resident blocks, so the last partial round costs little)
-  const int64_t target = row_blocks > 0 ? row_blocks : 4096;
+  // about row_blocks blocks of (range, slab group).  The default, N / 256 within
+  // [512, 4096], follows measurements across shapes: wide X wants several rounds of
+  // resident blocks (5000 x 10^6: 9.77 ms per iteration at 4096 against 10.98 at 512),
+  // narrower X fewer, longer ranges, whose W partials cost less to write and sum
+  // (500 x 150000: 0.258 ms at 512 against 0.303 at 4096).
+  const int64_t target = row_blocks > 0 ? row_blocks : std::min<int64_t>(4096, std::max<int64_t>(512, N / 256));
   int64_t want = (target + slab_groups - 1) / slab_groups;
   // at least 16 tiles (512 columns) per range: the W partials (R x KP x M floats) then
   // stay below a sixteenth of X for K <= 64

@@ -269,6 +269,9 @@ def test_autotune_records_and_applies():
         o = did.did_default_opts()
         o.borrow_x = 1
         before = did.did_mem_estimate(M, N, K, o)
+        ot = did.did_default_opts()
+        ot.x_tiled = 1
+        tiled_before = did.did_mem_estimate(M, N, K, ot)
         rb, cw, ms = did.did_autotune(M, N, K)
         assert rb in (512, 1024, 2048, 4096, 8192) and cw in (4, 8) and ms > 0.0
         o2 = did.did_default_opts()
@@ -280,10 +283,7 @@ def test_autotune_records_and_applies():
         assert did.did_mem_estimate(M, N, K, o) == did.did_mem_estimate(M, N, K, o2)
         assert before > 0
         # the tiled float32 storage is a shape class of its own: still the defaults
-        ot, od = did.did_default_opts(), did.did_default_opts()
-        ot.x_tiled = od.x_tiled = 1
-        od.row_blocks, od.col_waves = 4096, 4
-        assert did.did_mem_estimate(M, N, K, ot) == did.did_mem_estimate(M, N, K, od)
+        assert did.did_mem_estimate(M, N, K, ot) == tiled_before
         X = torch.rand((N, M), device="cuda")
         torch.cuda.synchronize()  # the engine reads X on its own stream
         h = did.did_init_ex(X, M, N, K, 5, o)
