@@ -229,3 +229,19 @@ def test_autotune_argument_checks_without_device():
         assert L.did_autotune(M, N, K, xd, xt, ctypes.byref(rb), ctypes.byref(cw), None) == did.DID_EINVAL, (M, N, K)
         assert (rb.value, cw.value) in ((0, 0), (7, 7))
     assert L.did_autotune(100, 100, 10, did.DID_F32, 0, ctypes.byref(rb), None, None) == did.DID_EINVAL
+
+
+@pytest.mark.parametrize("M,N,K", [(5000, 1_000_000, 50), (2000, 200_000, 20), (784, 70_000, 16),
+                                   (500, 150_000, 10), (1000, 20_000, 30), (3000, 3_000_000, 40)])
+def test_default_row_target_follows_n(M, N, K):
+    """With no tuned entry, the row pass's default target is N / 256 blocks clamped to
+    [512, 4096]: the footprint (which counts the W partials of the column ranges) equals
+    that of the explicit target."""
+    _lib_or_skip()
+    did.did_autotune_clear()
+    o = did.did_default_opts()
+    o.borrow_x = 1
+    e = did.did_default_opts()
+    e.borrow_x = 1
+    e.row_blocks = min(4096, max(512, N // 256))
+    assert did.did_mem_estimate(M, N, K, o) == did.did_mem_estimate(M, N, K, e)
