@@ -22,7 +22,7 @@ def _dev(torch, a):
     return t
 
 
-def _case(torch, M, N, K, n, n_blocks, seed):
+def _case(torch, M, N, K, n, n_blocks, seed, col_waves=0):
     X32 = to_f32_colmajor(serving_x(M, N, K, seed=seed))
     B0, C0 = uniform_init(M, N, K, seed + 1)
     B0 = B0.astype(np.float32)
@@ -30,6 +30,7 @@ def _case(torch, M, N, K, n, n_blocks, seed):
     Xd = _dev(torch, X32)
     o = did.did_default_opts()
     o.n_blocks = n_blocks
+    o.col_waves = col_waves
     # the existing entry points
     h = did.did_init_from_factors(Xd, M, N, K, _dev(torch, B0), _dev(torch, C0), o)
     try:
@@ -52,10 +53,11 @@ def _case(torch, M, N, K, n, n_blocks, seed):
 
 def test_static_entry_equals_allocating_path_twice():
     torch = require_gpu()
-    cases = [(600, 9000, 40, 6, 4, 31), (300, 2500, 12, 4, 0, 32)]  # second call: smaller
-    for i, (M, N, K, n, P, seed) in enumerate(cases):
-        announce(f"did_iterate_static call {i + 1}: M={M} N={N} K={K} n={n}")
-        X32, B0, C0, ref, got = _case(torch, M, N, K, n, P, seed)
+    # second call: smaller; third: the column pass with 8 waves per block
+    cases = [(600, 9000, 40, 6, 4, 31, 0), (300, 2500, 12, 4, 0, 32, 0), (500, 3000, 20, 3, 0, 33, 8)]
+    for i, (M, N, K, n, P, seed, cw) in enumerate(cases):
+        announce(f"did_iterate_static call {i + 1}: M={M} N={N} K={K} n={n} col_waves={cw}")
+        X32, B0, C0, ref, got = _case(torch, M, N, K, n, P, seed, cw)
         np.testing.assert_array_equal(got[0], ref[0])
         np.testing.assert_array_equal(got[1], ref[1])
         np.testing.assert_array_equal(got[2], ref[2])
