@@ -422,9 +422,10 @@ def test_batch_members_match_oracle():
             did.did_free(m[0])
 
 
-def _served_vs_oracle(X32, M, N, K, seed, it, B, C, f_last, tiled):
+def _served_vs_oracle(X32, M, N, K, seed, it, B, C, f_last, tiled, bf16=False):
     """A served job's result against the oracle after the same number of iterations from
-    the job's initial factors (read from a solo instance with the same seed)."""
+    the job's initial factors (read from a solo instance with the same seed); a job whose X
+    is stored as bf16 against the oracle on bf16(X)."""
     torch = require_gpu()
     o = did.did_default_opts()
     o.borrow_x = 1
@@ -434,7 +435,8 @@ def _served_vs_oracle(X32, M, N, K, seed, it, B, C, f_last, tiled):
         B0, C0 = read_factors(h, M, N, K)
     finally:
         did.did_free(h)
-    Xo = as_oracle_input(X32.cpu().numpy().T)
+    Xh = X32.cpu().numpy().T
+    Xo = round_to_bf16(Xh) if bf16 else as_oracle_input(Xh)
     Bo, Co, fo = oracle.did_run(Xo, B0, C0, it)
     eb, ec = rel_fro(B, Bo), rel_fro(C, Co)
     lb, lc = worst_line(B, Bo, axis=1), worst_line(C, Co, axis=0)
@@ -498,6 +500,61 @@ def test_server_early_stop_matches_oracle():
         fo = _served_vs_oracle(X[i], M, N, K, 800 + i, it, B, C, f, 0)
         if it >= 2:  # the oracle's relative change at the retirement iteration is near the tolerance
             assert abs(fo[it - 2] - fo[it - 1]) <= 1.01 * so.rel_tol * fo[it - 1]
+
+
+def test_server_mixed_storage_jobs_match_solo_and_oracle():
+    """Jobs with X stored as float32 and as bf16 served together (they fall in different
+    batch groups): each equals its solo run with the same storage bit for bit, and the
+    oracle (on X, or on bf16(X)) after the same number of iterations."""
+    torch = require_gpu()
+    jobs = [(300, 2000, 10, did.DID_F32), (500, 1200, 40, did.DID_BF16), (200, 3000, 24, did.DID_BF16),
+            (350, 2500, 48, did.DID_F32), (128, 1800, 12, did.DID_BF16)]
+    so = did.did_server_default_opts()
+    so.max_active = 8
+    so.max_iter = 6
+    so.rel_tol = 0.0
+    announce("server, float32 and bf16 jobs together")
+    s = did.did_server_create(so)
+    X, ids, res = {}, [], {}
+    try:
+        for i, (M, N, K, xd) in enumerate(jobs):
+            X[i] = device_x(torch, to_f32_colmajor(serving_x(M, N, K, seed=120 + i)))
+            ids.append(did.did_server_submit(s, X[i], M, N, K, 900 + i, xd))
+        steps = 0
+        while len(res) < len(jobs):
+            did.did_server_step(s)
+            steps += 1
+            for i, j in enumerate(ids):
+                if i in res:
+                    continue
+                st, it, f, _, _ = did.did_server_poll(s, j)
+                assert st != did.DID_JOB_FAILED
+                if st == did.DID_JOB_DONE:
+                    M, N, K, _ = jobs[i]
+                    Bt = np.empty((K, M), np.float32)
+                    Ct = np.empty((N, K), np.float32)
+                    did.did_server_result(s, j, Bt, Ct)
+                    res[i] = (it, Bt.T.copy(), Ct.T.copy(), f)
+                    did.did_server_release(s, j)
+            assert steps < 200
+    finally:
+        did.did_server_free(s)
+    for i, (M, N, K, xd) in enumerate(jobs):
+        it, B, C, f = res[i]
+        assert it == so.max_iter
+        o = did.did_default_opts()
+        o.borrow_x = 1
+        o.x_dtype = xd
+        h = did.did_init_ex(X[i], M, N, K, 900 + i, o)
+        try:
+            did.did_iterate(h, it)
+            Bs, Cs = read_factors(h, M, N, K)
+        finally:
+            did.did_free(h)
+        np.testing.assert_array_equal(B, Bs)
+        np.testing.assert_array_equal(C, Cs)
+        _served_vs_oracle(X[i], M, N, K, 900 + i, it, B.astype(np.float64), C.astype(np.float64), f, 0,
+                          bf16=xd == did.DID_BF16)
 
 
 def test_batch_rejects_carried_residual_form():
