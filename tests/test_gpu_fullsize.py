@@ -24,11 +24,12 @@ pytestmark = pytest.mark.gpu
 TOL_FACTORS = 1e-5
 
 
-def _run_one_iteration(torch, Xt, M, N, K, n_blocks, tiled=0):
+def _run_one_iteration(torch, Xt, M, N, K, n_blocks, tiled=0, x_dtype=did.DID_F32):
     o = did.did_default_opts()
     o.n_blocks = n_blocks
     o.borrow_x = 1
     o.x_tiled = tiled
+    o.x_dtype = x_dtype
     h = did.did_init_ex(Xt, M, N, K, 12345, o)
     try:
         B0, C0 = read_factors(h, M, N, K)
@@ -94,6 +95,33 @@ def test_large_workload_full_size_sampled():
     print(f"full-size large: sampled C columns rel err {ec:.2e}, sampled B rows rel err {eb:.2e}")
     assert eb <= TOL_FACTORS, eb
     del Xt
+    torch.cuda.empty_cache()
+
+
+def test_large_workload_full_size_bf16_sampled():
+    """The precision form at full size: the large workload with X stored as bf16 (two
+    tiled copies), one iteration, sampled columns of C and rows of B against the oracle's
+    halves on bf16(X) (round to nearest even, as the engine stores it)."""
+    from workloads import large_halfnormal_device
+
+    torch = require_gpu()
+    M, N, K = 5000, 1_000_000, 50
+    announce("full-size large workload, X stored as bf16, one iteration")
+    Xt = large_halfnormal_device(torch, M=M, N=N, K=K, seed=3, n_blocks=64)
+    torch.cuda.synchronize()
+    B0, C0, B1, C1 = _run_one_iteration(torch, Xt, M, N, K, 64, x_dtype=did.DID_BF16)
+    Xb = Xt.to(torch.bfloat16)  # the values the engine iterates on
+    del Xt
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(10)
+    cols = sorted(set(rng.choice(N, 96, replace=False).tolist()) | {0, 31, 32, N - 33, N - 1})
+    ec = _check_c_columns(Xb, B0, C0, C1, cols)
+    rows = sorted(set(rng.choice(M, 12, replace=False).tolist()) | {0, 31, 32, M - 1})
+    Bexp = _check_b_rows_chunked(Xb, B0, C1, rows, 200_000)
+    eb = rel_fro(B1[rows], Bexp)
+    print(f"full-size large, bf16 X: sampled C columns rel err {ec:.2e}, sampled B rows rel err {eb:.2e}")
+    assert eb <= TOL_FACTORS, eb
+    del Xb
     torch.cuda.empty_cache()
 
 
