@@ -144,6 +144,10 @@ __device__ __forceinline__ int scale_exp(float x) {
 }
 __device__ __forceinline__ float pow2f(int s) { return ldexpf(1.0f, s); }
 
+// Largest spread of scale exponents at which a group of rows of B (a 32-row chunk) or of
+// columns of C (a 32-column tile) shares one scale, that of its largest member.
+constexpr int kUniformSpread = 2;
+
 // Element types of X as the passes read it: float (column-major, as given), or one of the
 // two tiled storages (layout in did_kernels.h), bf16 or float32 (xtf32, a distinct type so
 // that the tiled loads are selected at compile time).
@@ -193,7 +197,22 @@ __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __rest
     float mx = 0.0f;
     if (tid < nv)
       for (int kk = 0; kk < K; ++kk) mx = fmaxf(mx, DELTA ? fabsf(Ct[tid * K + kk]) : Ct[tid * K + kk]);
-    cs[tid] = scale_exp(mx);
+    int sc = scale_exp(mx);
+    if constexpr (!DELTA) {
+      // a tile's 32 columns are 32 consecutive lanes: when the scales of its nonzero columns
+      // lie within kUniformSpread of each other, every column takes the smallest, so that
+      // the passes scale the tile's products with one multiplier (the tile is then flagged
+      // by the sign of its first inverse scale, below)
+      const bool has = tid < nv && mx > 0.0f;
+      int smin = has ? sc : INT_MAX, smax = has ? sc : INT_MIN;
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) {
+        smin = min(smin, __shfl_xor(smin, off, 64));
+        smax = max(smax, __shfl_xor(smax, off, 64));
+      }
+      if (smin <= smax && smax - smin <= kUniformSpread) sc = smin;
+    }
+    cs[tid] = sc;
   }
   if (!DELTA && tid < K) {  // row maxima over the block's columns (C >= 0: integer order = float order)
     float mx = 0.0f;
@@ -224,6 +243,11 @@ __device__ __forceinline__ void pack_block(f32x4* __restrict__ Cq, float* __rest
       f32x4 w;
 #pragma unroll
       for (int e = 0; e < 4; ++e) w[e] = pow2f(-cs[32 * tb + 4 * u + e]);
+      if (!DELTA && u == 0) {  // all 32 columns on one scale: the sign of the first flags it
+        bool same = true;
+        for (int j = 1; j < 32; ++j) same = same && cs[32 * tb + j] == cs[32 * tb];
+        if (same) w[0] = -w[0];
+      }
       Cq[(T0 + tb) * UT + UE0 + u] = w;
     }
   }
@@ -500,6 +524,26 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
       Bt[tid * (KP + 1) + i] = bnew;
       mx = fmaxf(mx, bnew);
     }
+    // Scale of row m's E-order operand.  A chunk's 32 rows are 32 consecutive lanes of this
+    // wave; when the scales of its nonzero rows lie within kUniformSpread of each other,
+    // every row takes the smallest (the largest row's), so that the passes scale the
+    // chunk's products with one multiplier: a row then sits at most 2^kUniformSpread below
+    // the top of the fp16 range, and its values keep full accuracy down to
+    // 2^-(17 - kUniformSpread) of its maximum.  Row 0's stored inverse scale then carries
+    // the sign bit as the chunk's flag.
+    int sm = scale_exp(mx);
+    bool uniform = false;
+    {
+      const bool has = ok && mx > 0.0f;
+      int smin = has ? sm : INT_MAX, smax = has ? sm : INT_MIN;
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) {  // within the lane's half of the wave
+        smin = min(smin, __shfl_xor(smin, off, 64));
+        smax = max(smax, __shfl_xor(smax, off, 64));
+      }
+      uniform = smin <= smax && smax - smin <= kUniformSpread;
+      if (uniform) sm = smin;
+    }
     if constexpr (RW) {  // E-order units of -delta B for row m, scaled per row, and the inverse scale
       if (ok) {
         float dm = 0.0f;
@@ -524,7 +568,6 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
       }
     }
     if (Bq && ok) {  // E-order units of row m and its inverse scale
-      const int sm = scale_exp(mx);
       const float sc = pow2f(sm);
       const int64_t c = m >> 5;
       const int r = (int)(m & 31);
@@ -539,7 +582,7 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
           Bq[(c * UC + (sq * 2 + 1) * 64 + l) * 8 + t] = lo;
         }
       }
-      reinterpret_cast<float*>(Bq + (c * UC + US) * 8)[r] = pow2f(-sm);
+      reinterpret_cast<float*>(Bq + (c * UC + US) * 8)[r] = (uniform && r == 0) ? -pow2f(-sm) : pow2f(-sm);
     }
   }
   __syncthreads();
@@ -732,7 +775,7 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int p = 0; p < 2; ++p) cP[s][p] = as_f16x8(ctile[(s * 2 + p) * 64 + l]);
-    ct = reinterpret_cast<const float*>(ctile + UCE0)[lc];
+    ct = fabsf(reinterpret_cast<const float*>(ctile + UCE0)[lc]);  // column 0's may carry the tile's flag
   } else {
 #pragma unroll
     for (int s = 0; s < KS; ++s)
@@ -850,13 +893,23 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
           for (int p = 0; p < 2; ++p) a[p] = an[p];
         }
       }
-      // rows row32(4q + e, half) = 8q + 4 half + e: their inverse scales are unit 2q + half
+      // rows row32(4q + e, half) = 8q + 4 half + e: their inverse scales are unit 2q + half.
+      // A negative first scale flags a chunk whose rows share one scale (the B update):
+      // one multiplier for the whole tile.
       const f32x4* rs = &sb[buf][US];
+      const float s0 =
+          __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, rs[0][0])));
+      if (s0 < 0.0f) {
+        const float mu = -s0 * ct;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const f32x4 r4 = rs[2 * q + half];
+        for (int i = 0; i < 16; ++i) acc[i] = fmaf(P[i], mu, xc[i]);
+      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, xc[4 * q + e]);
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 r4 = rs[2 * q + half];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], r4[e] * ct, xc[4 * q + e]);
+        }
       }
     }
     if constexpr (RW) rstore(c, acc);
@@ -1353,7 +1406,7 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int p = 0; p < 2; ++p) bP[s][p] = as_f16x8(pe[(s * 2 + p) * 64 + l]);
-    bs = reinterpret_cast<const float*>(pe + UBS)[lc];
+    bs = fabsf(reinterpret_cast<const float*>(pe + UBS)[lc]);  // row 0's may carry the uniform flag
   }
   f32x16 WT[NB];
 #pragma unroll
@@ -1430,13 +1483,23 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
             for (int p = 0; p < 2; ++p) a[p] = an[p];
           }
         }
-        // rows row32(4q + e, half) = 8q + 4 half + e of the tile: inverse scales in unit 2q + half
+        // rows row32(4q + e, half) = 8q + 4 half + e of the tile: inverse scales in unit 2q + half.
+        // A negative first scale flags a tile whose columns share one scale (the C packing):
+        // one multiplier for the whole tile.
         const f32x4* ts = &sc[buf][UE0];
+        const float t0 =
+            __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, ts[0][0])));
+        if (t0 < 0.0f) {
+          const float mu = -t0 * bs;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const f32x4 t4 = ts[2 * q + half];
+          for (int i = 0; i < 16; ++i) acc[i] = fmaf(P[i], mu, xc[i]);
+        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, xc[4 * q + e]);
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 t4 = ts[2 * q + half];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(P[4 * q + e], t4[e] * bs, xc[4 * q + e]);
+          }
         }
       }
       if constexpr (RW) {  // E' back into the residual, where it was read
