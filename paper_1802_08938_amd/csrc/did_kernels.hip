@@ -941,8 +941,6 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
       }
       const f32x4* uh = &sb[buf][UE] + l;
       f16x8 h[2], hn[2];
-#pragma unroll
-      for (int p = 0; p < 2; ++p) h[p] = as_f16x8(uh[p * 64]);
       f16x8 eP[2][2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -953,14 +951,19 @@ __device__ __forceinline__ void colpass_body(const XT* __restrict__ X, int64_t M
 #pragma unroll
         for (int p = 0; p < 2; ++p) eP[q][p] = sp.p[p];
       }
+      // accumulators alternate: (b, q) = (0, 0), (1, 0), ..., (0, 1), (1, 1), ...; each H[b]
+      // still takes q = 0 before q = 1
+      auto hunit = [&](int gg) { return ((gg % NB) * 2 + gg / NB) * 2; };
 #pragma unroll
-      for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
-        if (g + 1 < NB * 2) {
+      for (int p = 0; p < 2; ++p) h[p] = as_f16x8(uh[(hunit(0) + p) * 64]);
 #pragma unroll
-          for (int p = 0; p < 2; ++p) hn[p] = as_f16x8(uh[((g + 1) * 2 + p) * 64]);
+      for (int gg = 0; gg < NB * 2; ++gg) {
+        if (gg + 1 < NB * 2) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p) hn[p] = as_f16x8(uh[(hunit(gg + 1) + p) * 64]);
         }
-        H[g >> 1] = mfma_x3(h, eP[g & 1], H[g >> 1]);
-        if (g + 1 < NB * 2) {
+        H[gg % NB] = mfma_x3(h, eP[gg / NB], H[gg % NB]);
+        if (gg + 1 < NB * 2) {
 #pragma unroll
           for (int p = 0; p < 2; ++p) h[p] = hn[p];
         }
@@ -1546,13 +1549,14 @@ __device__ __forceinline__ void rowpass_body(const XT* __restrict__ X, int64_t M
         for (int p = 0; p < 2; ++p) eP[q][p] = sp.p[p];
       }
 #pragma unroll
-      for (int g = 0; g < NB * 2; ++g) {  // g = b*2 + q
-        if (g + 1 < NB * 2) {
+      for (int gg = 0; gg < NB * 2; ++gg) {  // accumulators alternate, as in the column pass
+        if (gg + 1 < NB * 2) {
+          const int un = (((gg + 1) % NB) * 2 + (gg + 1) / NB) * 2;
 #pragma unroll
-          for (int p = 0; p < 2; ++p) wn[p] = as_f16x8(uw[((g + 1) * 2 + p) * 64]);
+          for (int p = 0; p < 2; ++p) wn[p] = as_f16x8(uw[(un + p) * 64]);
         }
-        WT[g >> 1] = mfma_x3(w, eP[g & 1], WT[g >> 1]);
-        if (g + 1 < NB * 2) {
+        WT[gg % NB] = mfma_x3(w, eP[gg / NB], WT[gg % NB]);
+        if (gg + 1 < NB * 2) {
 #pragma unroll
           for (int p = 0; p < 2; ++p) w[p] = wn[p];
         }
