@@ -331,6 +331,32 @@ def test_column_tile_choice_keeps_factors_bitwise(M, N, K, storage):
     assert res[1]["f"] == pytest.approx(res[0]["f"], rel=1e-12)
 
 
+@pytest.mark.parametrize("spread", [3.0, 10.0, 1e3])
+def test_shared_scale_groups_parity(spread):
+    """Rows of B and columns of C whose magnitudes vary by a factor `spread` inside each
+    32-row chunk / 32-column tile: within a factor 4 they share one fp16 scale per group
+    (one multiplier per tile in the passes), beyond it each keeps its own.  Both ways the
+    factors after one and five iterations match the oracle, normwise and line by line."""
+    torch = require_gpu()
+    M, N, K = 200, 1500, 12
+    rng = np.random.default_rng(int(spread) + 5)
+    rs = spread ** (np.arange(M) % 2)           # alternate rows 1 and `spread` within chunks
+    cs = spread ** ((np.arange(N) // 3) % 2)    # runs of three columns at 1 and `spread`
+    B0p = rs[:, None] * (0.2 + rng.random((M, K)))
+    C0p = (0.2 + rng.random((K, N))) * cs[None, :]
+    X32 = to_f32_colmajor(B0p @ C0p + np.abs(0.01 * rng.standard_normal((M, N))))
+    B0 = (B0p * (1 + 0.1 * rng.random((M, K)))).astype(np.float32)
+    C0 = (C0p * (1 + 0.1 * rng.random((K, N)))).astype(np.float32)
+    announce(f"shared scale groups, spread {spread}")
+    out = run_gpu(torch, X32, K, iters=(1, 5), B0=B0, C0=C0)
+    Bi, Ci = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, Bi, Ci, 1)
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"spread {spread}, 1 iteration")
+    B5o, C5o, fo = _oracle_from(X32, Bi, Ci, 5)
+    check_factors(out[5][0], B5o, out[5][1], C5o, tol=1e-4, tol_line=1e-3, label=f"spread {spread}, 5 iterations")
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"spread {spread}")
+
+
 def test_block_count_only_changes_rounding():
     torch = require_gpu()
     X, _, _ = planted_lowrank(200, 6400, 8, seed=13)
