@@ -474,7 +474,6 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   // descriptor table) stage it in LDS.
   __shared__ double Vs[V_IN_LDS ? KP * (KP + 1) / 2 : 1];  // lower triangle, row-major pairs
   __shared__ float Bt[kBupRows * (KP + 1)];
-  __shared__ double dbs[KP * kBupRows];  // delta b of the block's rows, [i][row]
   const int tid = threadIdx.x;
   if constexpr (V_IN_LDS) {
     if (update)
@@ -488,41 +487,59 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
     if constexpr (V_IN_LDS)
       return Vs[a * (a + 1) / 2 + b];
     else
-      return V[a * KP + b];
+      return V[b * KP + a];  // row b of the symmetric V: contiguous in a
   };
   __syncthreads();
   const int64_t m = bid * kBupRows + tid;
   const bool ok = m < M;
   if (tid < kBupRows) {  // the row update, one thread per row of B
-    double* db = dbs + tid;  // db[i * kBupRows]: in LDS, as a private array would go to scratch
     float mx = 0.0f;
+    // s[q] = w_q - sum_{k < i} v_qk delta b_k for the coordinates q not yet updated: once
+    // coordinate i has moved, every later s[q] takes its term at once, so the terms still
+    // arrive in ascending k (the order of the sum in the update rule) while the dependent
+    // chain per coordinate is one division and one FMA.  A skipped coordinate (v_ii = 0: a
+    // zero row of C, whose row of V is zero too) moves by delta b_i = +0.
+    // The coordinates run to KQ, K rounded up to a multiple of 8 (a compile-time bound, so
+    // that sq stays in registers and no FMA is spent on the padding up to KP).
+    auto rows = [&](auto kq) {
+      constexpr int KQ = decltype(kq)::value;
+      double sq[KP];
+      if (update) {
 #pragma unroll
-    for (int i = 0; i < KP; ++i) {
-      db[i * kBupRows] = 0.0;
-      float bnew = 0.0f;
-      if (i < K && ok) {
-        const double bold = (double)B[(int64_t)i * M + m];
-        double bn = bold;
-        if (update) {
-          const double vii = vv(i, i);
-          if (vii > 0.0) {
-            double s = W[(int64_t)i * Mpad + m];
-#pragma unroll
-            for (int k = 0; k < KP; ++k)
-              if (k < i) s -= vv(i, k) * db[k * kBupRows];
-            bn = bold + s / vii;
-            bn = bn > 0.0 ? bn : 0.0;
-          }
-          db[i * kBupRows] = bn - bold;
-        }
-        bnew = (float)bn;
-        if (update) B[(int64_t)i * M + m] = bnew;
-        if constexpr (RW) dfl[i * kBupRows + tid] = (float)((double)bnew - bold);
-      } else if constexpr (RW) {
-        dfl[i * kBupRows + tid] = 0.0f;
+        for (int q = 0; q < KQ; ++q) sq[q] = (q < K && ok) ? W[(int64_t)q * Mpad + m] : 0.0;
       }
-      Bt[tid * (KP + 1) + i] = bnew;
-      mx = fmaxf(mx, bnew);
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        float bnew = 0.0f;
+        if (i < KQ && i < K && ok) {
+          const double bold = (double)B[(int64_t)i * M + m];
+          double bn = bold;
+          if (update) {
+            const double vii = vv(i, i);
+            if (vii > 0.0) {
+              bn = bold + sq[i] / vii;
+              bn = bn > 0.0 ? bn : 0.0;
+            }
+            const double d = bn - bold;
+#pragma unroll
+            for (int q = i + 1; q < KQ; ++q) sq[q] -= vv(q, i) * d;
+          }
+          bnew = (float)bn;
+          if (update) B[(int64_t)i * M + m] = bnew;
+          if constexpr (RW) dfl[i * kBupRows + tid] = (float)((double)bnew - bold);
+        } else if constexpr (RW) {
+          dfl[i * kBupRows + tid] = 0.0f;
+        }
+        Bt[tid * (KP + 1) + i] = bnew;
+        mx = fmaxf(mx, bnew);
+      }
+    };
+    // K <= 32 runs with KP = 32 and 32 < K <= 64 with KP = 64
+    switch ((K + 7) >> 3) {
+      case 1: case 5: rows(std::integral_constant<int, KP == 32 ? 8 : 40>{}); break;
+      case 2: case 6: rows(std::integral_constant<int, KP == 32 ? 16 : 48>{}); break;
+      case 3: case 7: rows(std::integral_constant<int, KP == 32 ? 24 : 56>{}); break;
+      default: rows(std::integral_constant<int, KP>{}); break;
     }
     // Scale of row m's E-order operand.  A chunk's 32 rows are 32 consecutive lanes of this
     // wave; when the scales of its nonzero rows lie within kUniformSpread of each other,
