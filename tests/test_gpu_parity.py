@@ -257,6 +257,47 @@ def test_zero_column_of_b_is_skipped_on_gpu():
     check_factors(out[1][0], B1o, out[1][1], C1o, label="zero column of B")
 
 
+@pytest.mark.parametrize("K", [8, 9, 16, 17, 24, 25, 40, 41, 48, 49, 56, 57])
+def test_every_k_class_parity(K):
+    """K on both sides of each multiple of 8: the B update's coordinate loops are bounded by K
+    rounded up to a multiple of 8 (a compile-time bound chosen per call), so each class runs
+    its own code; every one matches the oracle."""
+    torch = require_gpu()
+    M, N = 90, 200
+    rng = np.random.default_rng(500 + K)
+    X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
+    X32 = to_f32_colmajor(X)
+    announce(f"K class: M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 3))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"K={K}, 1 iteration")
+    B3o, C3o, fo = _oracle_from(X32, B0, C0, 3)
+    check_factors(out[3][0], B3o, out[3][1], C3o, tol=1e-4, tol_line=1e-3, label=f"K={K}, 3 iterations")
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"K={K}")
+
+
+@pytest.mark.parametrize("K", [4, 40])
+def test_zero_row_of_c_keeps_b_column_mid_order(K):
+    """A zero column of B and the matching zero row of C at coordinate 2: the sweep skips
+    c_2 (n_2 = 0) and the B update skips b_2 (v_22 = 0) while the coordinates after it
+    still move; B's column 2 and C's row 2 stay zero and the rest matches the oracle."""
+    torch = require_gpu()
+    rng = np.random.default_rng(14 + K)
+    M, N = 60, 90
+    X32 = to_f32_colmajor(rng.random((M, K)) @ rng.random((K, N)))
+    B0, C0 = rng.random((M, K)), rng.random((K, N))
+    B0[:, 2] = 0.0
+    C0[2, :] = 0.0
+    announce(f"zero row of C, K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 2), B0=B0.astype(np.float32), C0=C0.astype(np.float32))
+    for t in (1, 2):
+        assert np.all(out[t][0][:, 2] == 0.0) and np.all(out[t][1][2] == 0.0)
+    B2o, C2o, fo = _oracle_from(X32, out["init"][0], out["init"][1], 2)
+    check_factors(out[2][0], B2o, out[2][1], C2o, label=f"zero row of C, K={K}")
+    check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"zero row of C, K={K}")
+
+
 def test_rejects_negative_and_nonfinite_x():
     torch = require_gpu()
     for bad in (-1.0, np.nan, np.inf):
