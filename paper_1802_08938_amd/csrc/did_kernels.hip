@@ -177,6 +177,23 @@ struct x_is_tiled {
 // depend on the order), and k_packw writes the W order afterwards, storing 2^-w_kk into
 // Csc[KP + kk].
 //
+// dst[e] = src[e] for e = threadIdx.x, threadIdx.x + 256, ... < n (a block of 256 threads
+// copying between global memory and LDS): each thread issues G loads before their stores,
+// so that it waits for one memory round trip per G elements (a plain strided loop is
+// compiled as load, wait, store).
+template <int G = 16>
+__device__ __forceinline__ void block_copy(float* dst, const float* src, int n) {
+  int e = threadIdx.x;
+  for (; e + (G - 1) * 256 < n; e += G * 256) {
+    float v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) v[u] = src[e + u * 256];
+#pragma unroll
+    for (int u = 0; u < G; ++u) dst[e + u * 256] = v[u];
+  }
+  for (; e < n; e += 256) dst[e] = src[e];
+}
+
 // pack_block takes the (up to) eight tiles of columns j0 .. j0 + nv - 1, whose values sit
 // in LDS as Ct[j * K + kk] (j relative to j0); every thread builds whole 16-byte units, so
 // the global stores are coalesced.  All threads of the block call it, after Ct is
@@ -264,6 +281,7 @@ __device__ __forceinline__ void packw_body(const float* __restrict__ C, f32x4* _
   constexpr int UE = CqL<KP>::E;
   constexpr int UT = CqL<KP>::T;
   constexpr int GW = 8 * NB * 128;  // W groups per block: (tile, b, q, lane)
+  static_assert(GW % 512 == 0, "two groups per thread and step");
   __shared__ float ws[KP];
   const int tid = threadIdx.x;
   const int64_t j0 = bid * 256, T0 = bid * 8, ntiles = (N + 31) / 32;
@@ -273,22 +291,38 @@ __device__ __forceinline__ void packw_body(const float* __restrict__ C, f32x4* _
     if (bid == 0) Csc[KP + tid] = pow2f(-w);
   }
   __syncthreads();
-  for (int g = tid; g < GW; g += 256) {
-    const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
-    const int b = bq >> 1, q = bq & 1;
-    if (T0 + tb >= ntiles) continue;
-    const int kk = 32 * b + (l & 31), h = l >> 5;
-    const float sc = ws[kk];
-    float v[8];
+  // two groups per step (g and g + 256; GW is a multiple of 512): their sixteen loads are
+  // issued before either group is split and stored
+  for (int g0 = tid; g0 < GW; g0 += 512) {
+    float v[2][8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t j = j0 + 32 * tb + row32(8 * q + t, h);
-      v[t] = (j < N && kk < K) ? C[j * K + kk] * sc : 0.0f;
+    for (int r = 0; r < 2; ++r) {
+      const int g = g0 + 256 * r;
+      const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
+      const int b = bq >> 1, q = bq & 1;
+      const int kk = 32 * b + (l & 31), h = l >> 5;
+      const bool ok = T0 + tb < ntiles && kk < K;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t j = j0 + 32 * tb + row32(8 * q + t, h);
+        v[r][t] = (ok && j < N) ? C[j * K + kk] : 0.0f;
+      }
     }
-    const Split2 sp = split2(v);
-    f32x4* tile = Cq + (T0 + tb) * UT;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) tile[UE + ((b * 2 + q) * 2 + p) * 64 + l] = f16_as_f32x4(sp.p[p]);
+    for (int r = 0; r < 2; ++r) {
+      const int g = g0 + 256 * r;
+      const int tb = g / (NB * 128), rem = g % (NB * 128), bq = rem >> 6, l = rem & 63;
+      const int b = bq >> 1, q = bq & 1;
+      if (T0 + tb >= ntiles) continue;
+      const int kk = 32 * b + (l & 31);
+      const float sc = ws[kk];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[r][t] *= sc;
+      const Split2 sp = split2(v[r]);
+      f32x4* tile = Cq + (T0 + tb) * UT;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) tile[UE + ((b * 2 + q) * 2 + p) * 64 + l] = f16_as_f32x4(sp.p[p]);
+    }
   }
 }
 
@@ -1162,13 +1196,19 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
   const int64_t j0 = bid * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
   const int ne = nv * K;
-  for (int e = tid; e < ne; e += 256) Ct[e] = C[j0 * K + e];
-  __syncthreads();
   const int64_t col = j0 + tid;
+  // the column's h, loaded while the block stages its columns of C
+  float hf[KP];
+  if (tid < nv) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) hf[k] = Hin[(int64_t)k * N + col];
+  }
+  block_copy(Ct, C + j0 * K, ne);
+  __syncthreads();
   if (tid < nv) {
     double h[KP];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) h[k] = (double)Hin[(int64_t)k * N + col];
+    for (int k = 0; k < KP; ++k) h[k] = (double)hf[k];
     float* cl = Ct + tid * K;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -1193,7 +1233,20 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
   if (CqD) {  // carried-residual form: C' packed, then Ct := C' - C packed into CqD
     pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
     __syncthreads();
-    for (int e = tid; e < ne; e += 256) {
+    constexpr int G = 16;  // loads of the old values issued ahead, as in block_copy
+    int e = tid;
+    for (; e + (G - 1) * 256 < ne; e += G * 256) {
+      float co[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) co[u] = C[j0 * K + e + u * 256];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const float cn = Ct[e + u * 256];
+        C[j0 * K + e + u * 256] = cn;
+        Ct[e + u * 256] = cn - co[u];
+      }
+    }
+    for (; e < ne; e += 256) {
       const float cn = Ct[e], co = C[j0 * K + e];
       C[j0 * K + e] = cn;
       Ct[e] = cn - co;
@@ -1202,7 +1255,7 @@ __device__ __forceinline__ void sweep_body(const float* __restrict__ Hin, float*
     pack_block<KP, true>(CqD, nullptr, j0, nv, Ct, K, (N + 31) / 32, cs);
     return;
   }
-  for (int e = tid; e < ne; e += 256) C[j0 * K + e] = Ct[e];
+  block_copy(C + j0 * K, Ct, ne);
   pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
 
@@ -1222,7 +1275,7 @@ __device__ __forceinline__ void packc_body(const float* __restrict__ C, f32x4* _
   const int64_t j0 = bid * 256;
   const int nv = (int)((N - j0) < 256 ? (N - j0) : 256);
   const int ne = nv * K;
-  for (int e = threadIdx.x; e < ne; e += 256) Ct[e] = C[j0 * K + e];
+  block_copy(Ct, C + j0 * K, ne);
   __syncthreads();
   pack_block<KP>(Cq, Csc, j0, nv, Ct, K, (N + 31) / 32, cs);
 }
@@ -1663,13 +1716,28 @@ hipError_t rowpass(const Shape& s, const void* X, const void* Cqv, const float* 
 }
 
 // ------------------------------------------------------------------ reductions
+// The fixed-order sums below issue the loads of their terms in groups ahead of the
+// additions, which still take the terms one at a time in order: a thread then waits for one
+// memory round trip per group instead of one per term (a plain loop over a run-time count
+// is compiled as load, wait, add).
+
 // W[kk][m] = sum_r Wpart[r][kk][m], r ascending, float64 (blocks of 256 entries).
 __device__ __forceinline__ void reduce_w_body(const float* __restrict__ Wpart, int R, int64_t n,
                                               double* __restrict__ W, int64_t bid) {
   const int64_t i = bid * 256 + threadIdx.x;
   if (i >= n) return;
+  constexpr int G = 16;
+  const float* wp = Wpart + i;
   double s = 0.0;
-  for (int r = 0; r < R; ++r) s += (double)Wpart[(int64_t)r * n + i];
+  int r = 0;
+  for (; r + G <= R; r += G) {
+    float v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) v[u] = wp[(int64_t)(r + u) * n];
+#pragma unroll
+    for (int u = 0; u < G; ++u) s += (double)v[u];
+  }
+  for (; r < R; ++r) s += (double)wp[(int64_t)r * n];
   W[i] = s;
 }
 
@@ -1712,8 +1780,19 @@ __device__ __forceinline__ void reduce_sym_body(const double* __restrict__ part,
   const int tid = threadIdx.x, qi = tid & (kSymPairs - 1), t = tid / kSymPairs, wave = tid >> 6;
   const int q = (int)bid * kSymPairs + qi;
   double s = 0.0;
-  if (q < NP)
-    for (int64_t p = t; p < P; p += 256 / kSymPairs) s += part[p * NP + q];
+  if (q < NP) {
+    constexpr int64_t D = 256 / kSymPairs;  // stride between a thread's partials
+    constexpr int G = 8;
+    int64_t p = t;
+    for (; p + (G - 1) * D < P; p += G * D) {
+      double v[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) v[u] = part[(p + u * D) * NP + q];
+#pragma unroll
+      for (int u = 0; u < G; ++u) s += v[u];
+    }
+    for (; p < P; p += D) s += part[p * NP + q];
+  }
   // lanes qi + 8 t' of a wave (t' = t % 8) hold the same pair
   s += __shfl_xor(s, 8, 64);
   s += __shfl_xor(s, 16, 64);
@@ -1744,8 +1823,17 @@ hipError_t reduce_sym(const double* part, int64_t P, int KP, double* full, hipSt
 // the block; the result is returned to every thread.
 __device__ __forceinline__ double reduce_f_body(const double* __restrict__ part, int64_t P, double scale) {
   __shared__ double s[256];
+  constexpr int G = 8;
   double a = 0.0;
-  for (int64_t p = threadIdx.x; p < P; p += 256) a += part[p];
+  int64_t p = threadIdx.x;
+  for (; p + (G - 1) * 256 < P; p += G * 256) {
+    double v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) v[u] = part[p + u * 256];
+#pragma unroll
+    for (int u = 0; u < G; ++u) a += v[u];
+  }
+  for (; p < P; p += 256) a += part[p];
   s[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {

@@ -183,10 +183,20 @@ __global__ __launch_bounds__(256) void k_thin(const float* __restrict__ X, int64
 }
 
 // Sum of slot q over the P block partials (stride NS), by one wave: lane l adds partials
-// l, l + 64, ... in order, then a fixed butterfly.  Same result on every call.
+// l, l + 64, ... in order (their loads issued eight at a time ahead of the additions), then
+// a fixed butterfly.  Same result on every call.
 __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int64_t P, int NS, int q, int lane) {
+  constexpr int G = 8;
   double s = 0.0;
-  for (int64_t p = lane; p < P; p += 64) s += part[p * NS + q];
+  int64_t p = lane;
+  for (; p + (G - 1) * 64 < P; p += G * 64) {
+    double v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) v[u] = part[(p + u * 64) * NS + q];
+#pragma unroll
+    for (int u = 0; u < G; ++u) s += v[u];
+  }
+  for (; p < P; p += 64) s += part[p * NS + q];
   return wave_sum(s);
 }
 
