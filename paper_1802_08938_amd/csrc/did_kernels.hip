@@ -495,7 +495,7 @@ constexpr int kBupThreads = 256;  // threads per block (all of them form the G p
 // RW (the carried-residual form): the change delta B = B^{t+1} - B^t of the stored float32
 // values is also packed, as E-order units of -delta B scaled per row with the row's inverse
 // scale, into BqD (the layout of Bq), for the next column pass's update of the residual.
-template <int KP, bool V_IN_LDS, bool RW = false>
+template <int KP, bool RW = false>
 __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
                                              int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
                                              float* __restrict__ bmax, double* __restrict__ Gpart, int update,
@@ -503,26 +503,20 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   constexpr int64_t UC = BqL<KP>::C;
   constexpr int US = BqL<KP>::S;
   __shared__ float dfl[RW ? KP * kBupRows : 1];  // delta B of the stored values, [i][row]
-  // V is the same for every row.  The single-instance kernel reads it with uniform loads,
-  // which the compiler serves from scalar registers; the grouped kernels (pointers from the
-  // descriptor table) stage it in LDS.
-  __shared__ double Vs[V_IN_LDS ? KP * (KP + 1) / 2 : 1];  // lower triangle, row-major pairs
+  // V is the same for every row.  It is staged in LDS by all threads at once (one memory
+  // round trip), since the update's dependent chain would otherwise wait on a load of V at
+  // every coordinate: V was just written by another kernel, on whichever XCD, and a scalar
+  // load of it misses this XCD's caches.
+  __shared__ double Vs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
   __shared__ float Bt[kBupRows * (KP + 1)];
   const int tid = threadIdx.x;
-  if constexpr (V_IN_LDS) {
-    if (update)
-      for (int q = tid; q < KP * (KP + 1) / 2; q += kBupThreads) {
-        int a, b;
-        pair_of(q, a, b);
-        Vs[q] = V[a * KP + b];
-      }
-  }
-  auto vv = [&](int a, int b) -> double {  // V[a][b] for a >= b
-    if constexpr (V_IN_LDS)
-      return Vs[a * (a + 1) / 2 + b];
-    else
-      return V[b * KP + a];  // row b of the symmetric V: contiguous in a
-  };
+  if (update)
+    for (int q = tid; q < KP * (KP + 1) / 2; q += kBupThreads) {
+      int a, b;
+      pair_of(q, a, b);
+      Vs[q] = V[a * KP + b];
+    }
+  auto vv = [&](int a, int b) -> double { return Vs[a * (a + 1) / 2 + b]; };  // V[a][b] for a >= b
   __syncthreads();
   const int64_t m = bid * kBupRows + tid;
   const bool ok = m < M;
@@ -538,6 +532,9 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
     auto rows = [&](auto kq) {
       constexpr int KQ = decltype(kq)::value;
       double sq[KP];
+      float bo[KP];  // the row's current values, all loaded before the first coordinate moves
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) bo[q] = (q < K && ok) ? B[(int64_t)q * M + m] : 0.0f;
       if (update) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) sq[q] = (q < K && ok) ? W[(int64_t)q * Mpad + m] : 0.0;
@@ -546,7 +543,7 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
       for (int i = 0; i < KP; ++i) {
         float bnew = 0.0f;
         if (i < KQ && i < K && ok) {
-          const double bold = (double)B[(int64_t)i * M + m];
+          const double bold = (double)bo[i];
           double bn = bold;
           if (update) {
             const double vii = vv(i, i);
@@ -662,7 +659,7 @@ __global__ __launch_bounds__(kBupThreads) void k_bupdate(float* __restrict__ B, 
                                                  const double* __restrict__ V, _Float16* __restrict__ Bq,
                                                  float* __restrict__ bmax, double* __restrict__ Gpart,
                                                  int update, _Float16* __restrict__ BqD) {
-  bupdate_body<KP, false, RW>(B, M, K, W, Mpad, V, Bq, bmax, Gpart, update, blockIdx.x, BqD);
+  bupdate_body<KP, RW>(B, M, K, W, Mpad, V, Bq, bmax, Gpart, update, blockIdx.x, BqD);
 }
 
 // H-order units of the two chunks 2*bid, 2*bid + 1 from B and the column maxima in
@@ -1986,7 +1983,7 @@ __global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g)
 template <int KP>
 __global__ __launch_bounds__(kBupThreads) void kg_bupdate(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_BUP)
-  bupdate_body<KP, true>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.Bq, d.Bsc, d.Gpart, 1, bid);
+  bupdate_body<KP>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.Bq, d.Bsc, d.Gpart, 1, bid);
   DID_GROUP_END
 }
 
