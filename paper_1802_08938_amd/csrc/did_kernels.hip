@@ -495,7 +495,10 @@ constexpr int kBupThreads = 256;  // threads per block (all of them form the G p
 // RW (the carried-residual form): the change delta B = B^{t+1} - B^t of the stored float32
 // values is also packed, as E-order units of -delta B scaled per row with the row's inverse
 // scale, into BqD (the layout of Bq), for the next column pass's update of the residual.
-template <int KP, bool RW = false>
+// HOIST: the row's values of B are all loaded before the first coordinate moves (the
+// single-instance kernel); the grouped kernel loads each as it goes, which keeps it at two
+// waves per SIMD (with the hoisted loads it needs 256 VGPRs).
+template <int KP, bool RW = false, bool HOIST = true>
 __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, int K, const double* __restrict__ W,
                                              int64_t Mpad, const double* __restrict__ V, _Float16* __restrict__ Bq,
                                              float* __restrict__ bmax, double* __restrict__ Gpart, int update,
@@ -532,9 +535,11 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
     auto rows = [&](auto kq) {
       constexpr int KQ = decltype(kq)::value;
       double sq[KP];
-      float bo[KP];  // the row's current values, all loaded before the first coordinate moves
+      float bo[KP];  // the row's current values (HOIST)
+      if constexpr (HOIST) {
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) bo[q] = (q < K && ok) ? B[(int64_t)q * M + m] : 0.0f;
+        for (int q = 0; q < KQ; ++q) bo[q] = (q < K && ok) ? B[(int64_t)q * M + m] : 0.0f;
+      }
       if (update) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) sq[q] = (q < K && ok) ? W[(int64_t)q * Mpad + m] : 0.0;
@@ -543,7 +548,11 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
       for (int i = 0; i < KP; ++i) {
         float bnew = 0.0f;
         if (i < KQ && i < K && ok) {
-          const double bold = (double)bo[i];
+          double bold;
+          if constexpr (HOIST)
+            bold = (double)bo[i];
+          else
+            bold = (double)B[(int64_t)i * M + m];
           double bn = bold;
           if (update) {
             const double vii = vv(i, i);
@@ -1983,7 +1992,7 @@ __global__ __launch_bounds__(256) void kg_reduce_w(const GTable* __restrict__ g)
 template <int KP>
 __global__ __launch_bounds__(kBupThreads) void kg_bupdate(const GTable* __restrict__ g) {
   DID_GROUP_LOOP(GS_BUP)
-  bupdate_body<KP>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.Bq, d.Bsc, d.Gpart, 1, bid);
+  bupdate_body<KP, false, false>(d.B, d.M, d.K, d.W, d.Mpad, d.V, d.Bq, d.Bsc, d.Gpart, 1, bid);
   DID_GROUP_END
 }
 
