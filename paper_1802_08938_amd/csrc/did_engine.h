@@ -60,6 +60,10 @@ struct did_ctx {
   int64_t dev_bytes = 0;  // device memory held by the engine for this instance
   did_batch_ctx* batch = nullptr;
   std::vector<void*> allocs;
+  // one device allocation sized at setup from which the instance's buffers are carved (a
+  // release is then one hipFree, which waits for the device, instead of one per buffer)
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
   // one captured iteration of the MFMA path, replayed by did_iterate (not in the carried
   // form, not while profiling; never by did_iterate_static, which must not allocate)
   bool use_graph = true;

@@ -47,6 +47,15 @@ int dev_fail(did_ctx* h, hipError_t e, const char* what) {
 int dalloc_bytes(did_ctx* h, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 1;
+  if (h->arena) {  // carve from the arena, 256-byte aligned, while it has room
+    const size_t off = (h->arena_off + 255) & ~size_t(255);
+    if (off <= h->arena_cap && bytes <= h->arena_cap - off) {
+      h->arena_off = off + bytes;
+      h->dev_bytes += (int64_t)bytes;
+      *p = h->arena + off;
+      return DID_OK;
+    }
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) {
@@ -239,6 +248,21 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = make_shape(s, M, N, K, o))) return rc;
   h->algorithm = o.algorithm;
   if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
+  {  // the arena: the engine's bytes for this instance plus alignment slack per buffer
+    const bool xdev0 = is_device_ptr(Xv);
+    const bool x_copied = !s.xtiled && !(xdev0 && o.borrow_x);
+    const int R0 = s.thin ? 1 : (int)make_ranges(N, s.nchunks, o.n_blocks, row_target(s, o)).size() - 1;
+    const size_t cap = (size_t)engine_bytes(s, R0, x_copied, o.refresh_every) + 64 * 256;
+    void* q = nullptr;
+    if (hipMalloc(&q, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DID_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    h->allocs.push_back(q);
+    h->arena = static_cast<unsigned char*>(q);
+    h->arena_cap = cap;
+    h->arena_off = 0;
+  }
   if (o.stream) {
     h->st = static_cast<hipStream_t>(o.stream);
   } else {
