@@ -231,7 +231,7 @@ int64_t engine_bytes(const Shape& s, int R, bool x_copied, int refresh) {
   t += b(M * K * 4) + b(K * N * 4) + b(didk::packed_b_elems(s) * 2) + b(didk::bsc_floats(s.KP) * 4) + b(KP * KP * 8) +
        b((int64_t)didk::bupdate_blocks(s) * NP * 8) + b(KP * KP * 8) + b(KP * s.Mpad * 8);
   if (s.thin) {
-    t += b(didk::thin_blocks(s) * didk::thin_slots(16, 4) * 8);
+    t += b(didk::thin_blocks(s) * didk::thin_slots_for(s) * 8);
   } else {
     t += b(didk::vgram_blocks(s) * NP * 8) + b(KP * N * 4) + b(didk::cq_bytes(s)) + b(didk::bsc_floats(s.KP) * 4) + b((int64_t)R * KP * s.Mpad * 4) +
          b((int64_t)(R + 1) * 8) + b(didk::colpass_blocks(s) * 8);
@@ -345,7 +345,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   if ((rc = dalloc(h, &h->V, (int64_t)s.KP * s.KP))) return rc;
   if ((rc = dalloc(h, &h->W, (int64_t)s.KP * s.Mpad))) return rc;
   if (s.thin) {
-    if ((rc = dalloc(h, &h->tpart, didk::thin_blocks(s) * didk::thin_slots(16, 4)))) return rc;
+    if ((rc = dalloc(h, &h->tpart, didk::thin_blocks(s) * didk::thin_slots_for(s)))) return rc;
   } else {
     if ((rc = dalloc(h, &h->Vpart, didk::vgram_blocks(s) * NP))) return rc;
     if ((rc = dalloc(h, &h->H, (int64_t)s.KP * N))) return rc;

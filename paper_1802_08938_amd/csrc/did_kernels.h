@@ -228,5 +228,8 @@ int64_t thin_blocks(const Shape& s);
 // blocks for the thin kernels on the current device (< 0: the runtime query failed)
 int64_t thin_grid_for(const Shape& s);
 int thin_slots(int MM, int KK);
+// slots per block of the instance that runs shape s (the block partials hold thin_blocks(s)
+// times as many doubles)
+int thin_slots_for(const Shape& s);
 
 }  // namespace didk

@@ -340,6 +340,15 @@ int64_t thin_blocks(const Shape& s) { return s.thin_grid; }
   else if (s.M <= 8) { X_(8, 8, false); }              \
   else { X_(16, 4, false); }
 
+// Partial slots per block of the instance the shape runs (the size of its block partials).
+int thin_slots_for(const Shape& s) {
+  int n = 0;
+#define DID_THIN_NS(MM, KK, EX) n = thin_slots(MM, KK);
+  DID_THIN_SHAPES(DID_THIN_NS)
+#undef DID_THIN_NS
+  return n;
+}
+
 // One full wave of resident blocks of the DID column kernel (blocks per CU from the
 // occupancy calculator times the CU count), at most one block per 256 columns.
 int64_t thin_grid_for(const Shape& s) {
