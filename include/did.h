@@ -315,7 +315,10 @@ int did_batch_free(did_batch b);
  *                      retirement (-1 while not retired) and from submission to admission
  *                      (-1 while queued).
  *   did_server_result  copy a done job's B (M x K) and C (K x N) out, as did_factors.
- *   did_server_release free a retired job's device memory and forget the job.
+ *   did_server_release forget a retired job and return its memory to the budget; the
+ *                      device memory itself is freed at the next did_server_step (once
+ *                      the iteration in flight has ended) or by did_server_free.  X is
+ *                      not read after the job retired, so the caller may free it.
  *   did_server_memory  bytes charged to the budget now and at most so far.
  * A server, like a handle, is driven from one thread.  Admission is strictly first-in
  * first-out: a head job that does not fit yet (budget, slots, or 64 running jobs of its

@@ -511,6 +511,10 @@ struct did_server_ctx {
   bool inflight = false;          // an iteration of the running jobs has been launched
   int64_t used = 0;               // bytes charged by admitted, unreleased jobs
   int64_t peak_used = 0;
+  // handles of released jobs, freed at the next step once the batch stream has drained (a
+  // device free waits for the device: called between steps it would hold the host until
+  // the iteration in flight ends and leave the device idle afterwards)
+  std::vector<did_handle> retired;
 };
 
 namespace {
@@ -643,6 +647,10 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
     }
     s->running.swap(keep);
   }
+  // the iteration in flight has ended (its objectives were read back): free the handles
+  // released since, before any admission counts on their memory
+  for (did_handle h : s->retired) did_free(h);
+  s->retired.clear();
   for (int64_t id : s->admitted) {
     Job& j = s->jobs[id];
     if ((rc = did_batch_add(s->b, j.h))) {
@@ -735,7 +743,7 @@ int did_server_release(did_server s, int64_t job) {
   Job& j = it->second;
   if (j.state == DID_JOB_QUEUED || j.state == DID_JOB_RUNNING) return fail(DID_ESTATE, "job is still in progress");
   if (j.h) {
-    did_free(j.h);
+    s->retired.push_back(j.h);
     j.h = nullptr;
     s->used -= j.bytes;
   }
@@ -759,6 +767,7 @@ int did_server_free(did_server s) {
   }
   for (auto& kv : s->jobs)
     if (kv.second.h) did_free(kv.second.h);
+  for (did_handle h : s->retired) did_free(h);
   did_batch_free(s->b);
   if (s->adm_st) (void)hipStreamDestroy(s->adm_st);
   if (s->own_stream) (void)hipStreamDestroy(s->st);
