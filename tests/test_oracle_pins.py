@@ -52,7 +52,7 @@ def test_worked_example_one_iteration(name):
         np.testing.assert_allclose(E, _mat(g["E1"]), rtol=0, atol=1e-14)
     f1 = float(Fraction(g["f1"]))
     assert 0.5 * np.sum(E * E) == pytest.approx(f1, rel=1e-13)
-    # the same through the driver
+    # the same through the whole iteration (did_run)
     Bd, Cd, f = oracle.did_run(X, B0, C0, 1, check=True)
     assert f[1] == pytest.approx(f1, rel=1e-13)
 
