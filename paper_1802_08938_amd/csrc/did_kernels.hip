@@ -506,10 +506,10 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   constexpr int64_t UC = BqL<KP>::C;
   constexpr int US = BqL<KP>::S;
   __shared__ float dfl[RW ? KP * kBupRows : 1];  // delta B of the stored values, [i][row]
-  // V is the same for every row.  It is staged in LDS by all threads at once (one memory
-  // round trip), since the update's dependent chain would otherwise wait on a load of V at
-  // every coordinate: V was just written by another kernel, on whichever XCD, and a scalar
-  // load of it misses this XCD's caches.
+  // V is the same for every row.  The whole block stages it in LDS before the update (a
+  // few memory round trips in all), since the update's dependent chain would otherwise wait
+  // on a load of V at every coordinate: V was just written by another kernel, on whichever
+  // XCD, and a scalar load of it misses this XCD's caches.
   __shared__ double Vs[KP * (KP + 1) / 2];  // lower triangle, row-major pairs
   __shared__ float Bt[kBupRows * (KP + 1)];
   const int tid = threadIdx.x;
@@ -525,8 +525,8 @@ __device__ __forceinline__ void bupdate_body(float* __restrict__ B, int64_t M, i
   const bool ok = m < M;
   if (tid < kBupRows) {  // the row update, one thread per row of B
     float mx = 0.0f;
-    // s[q] = w_q - sum_{k < i} v_qk delta b_k for the coordinates q not yet updated: once
-    // coordinate i has moved, every later s[q] takes its term at once, so the terms still
+    // sq[q] = w_q - sum_{k < i} v_qk delta b_k for the coordinates q not yet updated: once
+    // coordinate i has moved, every later sq[q] takes its term at once, so the terms still
     // arrive in ascending k (the order of the sum in the update rule) while the dependent
     // chain per coordinate is one division and one FMA.  A skipped coordinate (v_ii = 0: a
     // zero row of C, whose row of V is zero too) moves by delta b_i = +0.
