@@ -67,6 +67,9 @@ struct did_ctx {
   // one captured iteration of the MFMA path, replayed by did_iterate (not in the carried
   // form, not while profiling; never by did_iterate_static, which must not allocate)
   bool use_graph = true;
+  // whether eager iterations may create the second stream (not in did_iterate_static,
+  // whose context lives on the caller's stack and must not create resources)
+  bool may_create_st2 = true;
   bool graph_failed = false;
   hipGraphExec_t gexec = nullptr;
   // per-stage timing: kStages+1 events per profiled iteration

@@ -353,10 +353,6 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     if ((rc = dalloc(h, &cq, didk::cq_bytes(s)))) return rc;
     h->Cq = cq;
     if ((rc = dalloc(h, &h->Csc, didk::bsc_floats(s.KP)))) return rc;
-    if ((e = hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&h->ev_c, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&h->ev_v, hipEventDisableTiming)) != hipSuccess)
-      return dev_fail(h, e, "second stream");
     if ((rc = dalloc(h, &h->Wpart, (int64_t)h->R * s.KP * s.Mpad))) return rc;
     if ((rc = dalloc(h, &h->rbounds, (int64_t)rb.size()))) return rc;
     if ((rc = dalloc(h, &h->fpart, didk::colpass_blocks(s)))) return rc;
@@ -621,6 +617,14 @@ int iterate_mfma(did_ctx* h, int32_t n) {
       h->t += n;
       return DID_OK;
     }
+  }
+  // the second stream and its events, made on the first eager iteration (a handle that only
+  // replays its graph or runs inside a batch never needs them)
+  if (!h->st2 && h->may_create_st2) {
+    if ((e = hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->ev_c, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->ev_v, hipEventDisableTiming)) != hipSuccess)
+      return dev_fail(h, e, "second stream");
   }
   for (int32_t it = 0; it < n; ++it) {
     hipEvent_t* ev = nullptr;

@@ -117,6 +117,7 @@ int did_iterate_static(const float* X, int64_t M, int64_t N, int32_t K, float* B
   c.st = static_cast<hipStream_t>(o.stream);
   c.own_stream = false;
   c.use_graph = false;  // a graph would allocate
+  c.may_create_st2 = false;
   c.X = const_cast<float*>(X);
   c.XR = c.X;
   c.s.vec4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
