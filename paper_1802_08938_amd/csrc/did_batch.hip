@@ -92,13 +92,13 @@ struct did_batch_ctx {
   struct Group {
     std::vector<did_ctx*> m;
     GTable* dtab = nullptr;  // device copy
-    GTable htab;             // host image
+    GTable* htab = nullptr;  // host image, in pinned memory (a direct copy to the device)
     int64_t grids[GS_N] = {0};
     bool have_grids = false;
   } groups[kGroups];
   double* dfcur = nullptr;  // device: latest objective per slot
   std::vector<int> slot_of;  // parallel to members
-  std::vector<double> hf;
+  double* hf = nullptr;  // pinned: the objectives read back each step
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   unsigned captured_mask = 0;  // groups present when the graph was captured
@@ -189,12 +189,20 @@ int rebuild(did_batch_ctx* b) {
       }
       G.dtab = static_cast<GTable*>(p);
     }
+    if (!G.htab) {
+      void* p = nullptr;
+      if ((e = hipHostMalloc(&p, sizeof(GTable), hipHostMallocDefault)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DID_ENOMEM, "pinned host allocation of a batch table failed");
+      }
+      G.htab = static_cast<GTable*>(p);
+    }
     if (!G.have_grids) {
       if ((e = didk::group_grids(group_kp(g), group_xkind(g), group_cwpb(g), G.grids)) != hipSuccess)
         return bdev_fail(b, e, "occupancy of the grouped kernels");
       G.have_grids = true;
     }
-    GTable& t = G.htab;
+    GTable& t = *G.htab;
     memset(&t, 0, sizeof(t));
     t.n = (int)G.m.size();
     for (int st = 0; st < GS_N; ++st) t.begin[st][0] = 0;
@@ -273,6 +281,14 @@ int did_batch_create(void* stream, did_batch* out) {
     return fail(DID_ENOMEM, "device allocation failed");
   }
   b->dfcur = static_cast<double*>(p);
+  if ((e = hipHostMalloc(&p, sizeof(double) * kGroups * kMaxBatch, hipHostMallocDefault)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(b->dfcur);
+    if (b->own_stream) (void)hipStreamDestroy(b->st);
+    delete b;
+    return fail(DID_ENOMEM, "pinned host allocation failed");
+  }
+  b->hf = static_cast<double*>(p);
   *out = b;
   return DID_OK;
 }
@@ -345,9 +361,8 @@ int did_batch_objectives(did_batch b, double* f, int32_t cap, int32_t* n) {
   if (rc) return rc;
   if (!n || (cap > 0 && !f) || cap < 0) return fail(DID_EINVAL, "bad output arguments");
   DeviceGuard g(b->dev);
-  b->hf.resize(kGroups * kMaxBatch);
   hipError_t e;
-  if ((e = hipMemcpyAsync(b->hf.data(), b->dfcur, sizeof(double) * kGroups * kMaxBatch, hipMemcpyDeviceToHost, b->st)) !=
+  if ((e = hipMemcpyAsync(b->hf, b->dfcur, sizeof(double) * kGroups * kMaxBatch, hipMemcpyDeviceToHost, b->st)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(b->st)) != hipSuccess)
     return bdev_fail(b, e, "objective readback");
@@ -371,9 +386,12 @@ int did_batch_free(did_batch b) {
   for (did_ctx* h : b->members) h->batch = nullptr;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (auto& G : b->groups)
+  for (auto& G : b->groups) {
     if (G.dtab) (void)hipFree(G.dtab);
+    if (G.htab) (void)hipHostFree(G.htab);
+  }
   if (b->dfcur) (void)hipFree(b->dfcur);
+  if (b->hf) (void)hipHostFree(b->hf);
   if (b->own_stream) (void)hipStreamDestroy(b->st);
   (void)hipGetLastError();
   delete b;
