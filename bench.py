@@ -47,7 +47,8 @@ launch floor: the replay time of a graph of as many empty dependent kernels.
 
 The engine keeps float32 X in 32x32 tile order (one copy per pass, made at init) for the
 MFMA-path workloads and the batch; --x-given reads it as given (column-major) instead.
-The serve workload reads it as given unless --serve-tiled is passed.
+The served form and the serve workload read it as given (--serve-tiled: tile order for
+the serve workload; the tiled copies triple each job's X memory).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--x-given]
                        [--workload large|large_bf16|image|planted|nsweep|paper|batch|serve]
@@ -1063,13 +1064,19 @@ def main():
         del X
         torch.cuda.empty_cache()
         line["batched_form"] = batch_measure(torch, did, WORKLOADS["batch"]["jobs"], 10, 2, args.x_given)
-        line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, False)
+        # float32 X read as given: with each job's two tiled copies made at admission the
+        # served rate swung between runs (100-119 solves/s alone, 87.5 after the other legs,
+        # and 55 for the early-stop leg), the copies' allocation and tiling competing with
+        # the iterations
+        tiled = False
+        line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled)
         line["served_form"]["note"] = ("a shortened run of the served workload: the first jobs of the same "
-                                       "Poisson schedule (200 jobs/s), 200 GB budget, X read as given, all "
-                                       "inputs resident in HBM before the clock starts")
+                                       "Poisson schedule (200 jobs/s), 200 GB budget, all inputs resident in "
+                                       "HBM before the clock starts; " +
+                                       ("X kept in tile order, copied at admission" if tiled else "X read as given"))
         # the same jobs with a stopping rule loose enough to fire: retirements free slots
         # mid-mix and the queue is admitted as they do
-        es = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, False, rel_tol=1e-2)
+        es = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled, rel_tol=1e-2)
         line["served_form"]["early_stop"] = {k: es[k] for k in (
             "rel_tol", "solves_per_s", "latency_p50_s", "latency_p99_s", "iterations_mean",
             "share_stopped_by_rel_tol", "max_queue_depth")}
