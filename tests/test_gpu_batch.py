@@ -335,6 +335,46 @@ def test_free_returns_device_memory_after_graph_replays():
         assert held < need / 4, ("batch", cycle, held, need)
 
 
+def test_server_released_jobs_return_device_memory():
+    """A released job's device memory is freed at the server's next step (after the
+    iteration in flight has ended) or when the server is freed: device free memory comes
+    back to where it was, and the server's charge drops at the release itself."""
+    torch = require_gpu()
+    jobs = [(1500, 60000, 20), (900, 40000, 40), (1200, 50000, 12)]
+    X = [device_x(torch, to_f32_colmajor(serving_x(M, N, K, seed=90 + i))) for i, (M, N, K) in enumerate(jobs)]
+    torch.cuda.synchronize()
+    announce("server release returns device memory")
+    base = torch.cuda.mem_get_info()[0]
+    so = did.did_server_default_opts()
+    so.max_iter = 3
+    s = did.did_server_create(so)
+    try:
+        ids = [did.did_server_submit(s, X[i], M, N, K, 90 + i) for i, (M, N, K) in enumerate(jobs)]
+        done = set()
+        steps = 0
+        while len(done) < len(ids):
+            did.did_server_step(s)
+            steps += 1
+            for j in ids:
+                if j not in done and did.did_server_poll(s, j)[0] == did.DID_JOB_DONE:
+                    did.did_server_release(s, j)
+                    done.add(j)
+            assert steps < 100
+        assert did.did_server_memory(s)[0] == 0
+        held_before = base - torch.cuda.mem_get_info()[0]
+        did.did_server_step(s)  # frees the handles released since the last step
+        torch.cuda.synchronize()
+        held_after = base - torch.cuda.mem_get_info()[0]
+        o = did.did_default_opts()
+        o.borrow_x = 1  # the server adopts each job's X
+        need = sum(did.did_mem_estimate(M, N, K, o, x_on_device=True) for M, N, K in jobs)
+        assert held_after < need / 4, (held_before, held_after, need)
+    finally:
+        did.did_server_free(s)
+    torch.cuda.synchronize()
+    assert base - torch.cuda.mem_get_info()[0] < need / 4
+
+
 @pytest.mark.parametrize("M,N,K,xd,borrow,tiled,refresh", [
     (300, 2000, 10, did.DID_F32, 1, 0, 1), (300, 2000, 10, did.DID_F32, 0, 0, 1),
     (130, 777, 64, did.DID_BF16, 0, 0, 1), (5, 1000, 3, did.DID_F32, 1, 0, 1),
