@@ -389,6 +389,20 @@ const char* did_last_error(void);
  * DID_EINVAL for NULL. */
 int did_debug_inject_fault(did_handle h);
 
+/* Debugging aid for out-of-bounds writes: with the environment variable
+ * DID_DEBUG_GUARD_ZONES set to a nonzero integer when a handle is created, each of the
+ * handle's device buffers is followed by a guard zone of DID_GUARD_ZONE_BYTES bytes
+ * filled with the byte DID_GUARD_BYTE.  did_debug_check_guards synchronises the handle's
+ * stream (a batch member's writes are on the batch's stream: call did_batch_sync first)
+ * and stores in *bad the number of guard bytes that no longer hold the pattern
+ * (0: no buffer was written past its end), and in *zones (if not NULL) the number of
+ * zones checked (0 for a handle made without them); the message of the first damaged zone
+ * names the buffer and is kept for did_last_error.  Returns DID_EINVAL for NULL h or bad,
+ * DID_EDEVICE if the copies fail. */
+#define DID_GUARD_ZONE_BYTES 4096
+#define DID_GUARD_BYTE 0xA5
+int did_debug_check_guards(did_handle h, int64_t* bad, int32_t* zones);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ __all__ = [
     "did_server_opts", "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step",
     "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
     "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED", "did_debug_inject_fault",
-    "did_iterate_static", "DID_STATIC_SCRATCH_BYTES",
+    "did_debug_check_guards", "did_iterate_static", "DID_STATIC_SCRATCH_BYTES", "DID_GUARD_ZONE_BYTES",
 ]
 
 DID_OK, DID_EINVAL, DID_ENOMEM, DID_EDEVICE, DID_ESTATE = 0, -1, -2, -3, -4
@@ -35,6 +35,7 @@ DID_F32, DID_BF16 = 0, 1
 DID_ALG_DID, DID_ALG_DBCD = 0, 1
 DID_MAX_K = 64
 DID_STATIC_SCRATCH_BYTES = 128 << 20
+DID_GUARD_ZONE_BYTES = 4096
 DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED = 0, 1, 2, 3
 
 EXPORTED_SYMBOLS = (
@@ -46,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step", "did_server_poll",
     "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
-    "did_debug_inject_fault", "did_iterate_static",
+    "did_debug_inject_fault", "did_debug_check_guards", "did_iterate_static",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -144,6 +145,7 @@ def lib():
         "did_server_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "did_server_free": [vp],
         "did_debug_inject_fault": [vp],
+        "did_debug_check_guards": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)],
         "did_iterate_static": [vp, i64, i64, i32, vp, vp, i32, ctypes.POINTER(did_opts), vp],
     }
     for name, args in sig.items():
@@ -395,3 +397,12 @@ def did_iterate_static(X, M, N, K, B, C, n, opts=None, f=None):
 def did_debug_inject_fault(h):
     """Make the next checked call on h fail as a device error would (sticky DID_EDEVICE)."""
     _check(lib().did_debug_inject_fault(h))
+
+
+def did_debug_check_guards(h):
+    """(changed guard bytes past the ends of h's buffers, guard zones checked): handles made
+    with the environment variable DID_DEBUG_GUARD_ZONES=1 have a zone after each buffer."""
+    bad = ctypes.c_int64(0)
+    zones = ctypes.c_int32(0)
+    _check(lib().did_debug_check_guards(h, ctypes.byref(bad), ctypes.byref(zones)))
+    return bad.value, zones.value

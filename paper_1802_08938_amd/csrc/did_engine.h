@@ -64,6 +64,9 @@ struct did_ctx {
   // release is then one hipFree, which waits for the device, instead of one per buffer)
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_off = 0;
+  // DID_DEBUG_GUARD_ZONES: a patterned zone after each buffer carved from the arena
+  bool guards = false;
+  std::vector<std::pair<unsigned char*, int>> guard_zones;  // zone start, buffer index
   // one captured iteration of the MFMA path, replayed by did_iterate (not in the carried
   // form, not while profiling; never by did_iterate_static, which must not allocate)
   bool use_graph = true;

@@ -8,6 +8,7 @@
 
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -49,10 +50,19 @@ int dalloc_bytes(did_ctx* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 1;
   if (h->arena) {  // carve from the arena, 256-byte aligned, while it has room
     const size_t off = (h->arena_off + 255) & ~size_t(255);
-    if (off <= h->arena_cap && bytes <= h->arena_cap - off) {
-      h->arena_off = off + bytes;
+    const size_t span = bytes + (h->guards ? (size_t)DID_GUARD_ZONE_BYTES : 0);
+    if (off <= h->arena_cap && span <= h->arena_cap - off) {
+      h->arena_off = off + span;
       h->dev_bytes += (int64_t)bytes;
       *p = h->arena + off;
+      if (h->guards) {
+        unsigned char* z = h->arena + off + bytes;
+        if (hipMemsetAsync(z, DID_GUARD_BYTE, DID_GUARD_ZONE_BYTES, h->st) != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(DID_EDEVICE, "guard zone fill failed");
+        }
+        h->guard_zones.emplace_back(z, (int)h->guard_zones.size());
+      }
       return DID_OK;
     }
   }
@@ -249,10 +259,13 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
   h->algorithm = o.algorithm;
   if (hipGetDevice(&h->dev) != hipSuccess) return fail(DID_EDEVICE, "no HIP device");
   {  // the arena: the engine's bytes for this instance plus alignment slack per buffer
+    const char* gz = getenv("DID_DEBUG_GUARD_ZONES");
+    h->guards = gz && atoi(gz) != 0;
     const bool xdev0 = is_device_ptr(Xv);
     const bool x_copied = !s.xtiled && !(xdev0 && o.borrow_x);
     const int R0 = s.thin ? 1 : (int)make_ranges(N, s.nchunks, o.n_blocks, row_target(s, o)).size() - 1;
-    const size_t cap = (size_t)engine_bytes(s, R0, x_copied, o.refresh_every) + 64 * 256;
+    const size_t cap = (size_t)engine_bytes(s, R0, x_copied, o.refresh_every) +
+                       64 * (256 + (h->guards ? (size_t)DID_GUARD_ZONE_BYTES : 0));
     void* q = nullptr;
     if (hipMalloc(&q, cap) != hipSuccess) {
       (void)hipGetLastError();
@@ -860,6 +873,32 @@ int did_mem_estimate(int64_t M, int64_t N, int32_t K, const did_opts* opts, int3
 int did_mem_bytes(did_handle h, int64_t* bytes) {
   if (!h || !bytes) return fail(DID_EINVAL, "NULL argument");
   *bytes = h->dev_bytes;
+  return DID_OK;
+}
+
+int did_debug_check_guards(did_handle h, int64_t* bad, int32_t* zones) {
+  if (!h || !bad) return fail(DID_EINVAL, "NULL argument");
+  *bad = 0;
+  if (zones) *zones = (int32_t)h->guard_zones.size();
+  if (h->guard_zones.empty()) return DID_OK;
+  DeviceGuard g(h->dev);
+  std::vector<unsigned char> z(DID_GUARD_ZONE_BYTES);
+  std::string first;
+  for (const auto& gzone : h->guard_zones) {
+    hipError_t e;
+    if ((e = hipMemcpyAsync(z.data(), gzone.first, z.size(), hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->st)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DID_EDEVICE, std::string("guard zone read failed: ") + hipGetErrorString(e));
+    }
+    int64_t n = 0;
+    for (unsigned char c : z) n += c != (unsigned char)DID_GUARD_BYTE;
+    if (n && first.empty())
+      first = "buffer " + std::to_string(gzone.second) + " (in allocation order) was written past its end (" +
+              std::to_string(n) + " guard bytes changed)";
+    *bad += n;
+  }
+  if (!first.empty()) g_err = first;
   return DID_OK;
 }
 
