@@ -46,9 +46,9 @@ time the small shapes, whose iterations are replayed from a captured graph, besi
 launch floor: the replay time of a graph of as many empty dependent kernels.
 
 The engine keeps float32 X in 32x32 tile order (one copy per pass, made at init) for the
-MFMA-path workloads and the batch; --x-given reads it as given (column-major) instead.
-The served form and the serve workload read it as given (--serve-tiled: tile order for
-the serve workload; the tiled copies triple each job's X memory).
+MFMA-path workloads, the batch and the default line's served form; --x-given reads it as
+given (column-major) instead.  The 1000-job serve workload reads it as given unless
+--serve-tiled is passed (the tiled copies triple each job's X memory).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--x-given]
                        [--workload large|large_bf16|image|planted|nsweep|paper|batch|serve]
@@ -1064,11 +1064,9 @@ def main():
         del X
         torch.cuda.empty_cache()
         line["batched_form"] = batch_measure(torch, did, WORKLOADS["batch"]["jobs"], 10, 2, args.x_given)
-        # float32 X read as given: with each job's two tiled copies made at admission the
-        # served rate swung between runs (100-119 solves/s alone, 87.5 after the other legs,
-        # and 55 for the early-stop leg), the copies' allocation and tiling competing with
-        # the iterations
-        tiled = False
+        # float32 jobs keep X in tile order like the other forms (each job's two tiled copies
+        # are made at its admission, inside the timed region), unless --x-given
+        tiled = not args.x_given
         line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled)
         line["served_form"]["note"] = ("a shortened run of the served workload: the first jobs of the same "
                                        "Poisson schedule (200 jobs/s), 200 GB budget, all inputs resident in "

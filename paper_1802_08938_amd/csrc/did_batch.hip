@@ -533,6 +533,7 @@ struct did_server_ctx {
   // device free waits for the device: called between steps it would hold the host until
   // the iteration in flight ends and leave the device idle afterwards)
   std::vector<did_handle> retired;
+  ArenaPool pool;  // arenas of released jobs, reused by later admissions
 };
 
 namespace {
@@ -671,7 +672,9 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
   s->retired.clear();
   for (int64_t id : s->admitted) {
     Job& j = s->jobs[id];
-    if ((rc = did_batch_add(s->b, j.h))) {
+    // the job's set-up ran on the admission stream beside the last iteration; X's check
+    // is read here (an X that is not finite and nonnegative fails the job)
+    if ((rc = didengine::check_deferred(j.h)) || (rc = did_batch_add(s->b, j.h))) {
       j.state = DID_JOB_FAILED;
       j.error = g_err;
       did_free(j.h);
@@ -707,7 +710,7 @@ int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t
     o.stream = s->adm_st;
     s->queue.pop_front();
     j.t_start = std::chrono::steady_clock::now();
-    if ((rc = did_init_ex(j.X, j.M, j.N, j.K, j.seed, &o, &j.h))) {
+    if ((rc = didengine::init_deferred(j.X, j.M, j.N, j.K, j.seed, &o, &j.h, &s->pool))) {
       j.state = DID_JOB_FAILED;
       j.error = g_err;
       j.h = nullptr;
@@ -786,6 +789,7 @@ int did_server_free(did_server s) {
   for (auto& kv : s->jobs)
     if (kv.second.h) did_free(kv.second.h);
   for (did_handle h : s->retired) did_free(h);
+  didengine::pool_free_all(&s->pool);
   did_batch_free(s->b);
   if (s->adm_st) (void)hipStreamDestroy(s->adm_st);
   if (s->own_stream) (void)hipStreamDestroy(s->st);

@@ -13,6 +13,15 @@
 struct did_batch_ctx;
 
 // One NMF instance: its device buffers and stream.
+// Device arenas kept for reuse by the handles of one serving loop: a handle made with a
+// pool carves its buffers from the smallest pooled arena that fits (wasting at most half of
+// it) and gives its arena back at release; the pool frees its largest arenas beyond limit.
+struct ArenaPool {
+  std::vector<std::pair<void*, size_t>> free;  // (pointer, capacity)
+  size_t bytes = 0;
+  size_t limit = size_t(48) << 30;
+};
+
 struct did_ctx {
   int dev = 0;
   hipStream_t st = nullptr;
@@ -64,6 +73,11 @@ struct did_ctx {
   // release is then one hipFree, which waits for the device, instead of one per buffer)
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_off = 0;
+  ArenaPool* pool = nullptr;  // the serving loop's pool the arena comes from and returns to
+  // made by a serving loop: X's validation result and the set-up work stay queued on the
+  // stream (no host wait); check_deferred reads the result once the stream has drained
+  bool defer_checks = false;
+  bool x_check_pending = false;
   // DID_DEBUG_GUARD_ZONES: a patterned zone after each buffer carved from the arena
   bool guards = false;
   std::vector<std::pair<unsigned char*, int>> guard_zones;  // zone start, buffer index
@@ -105,6 +119,14 @@ void range_params(int64_t N, int64_t nchunks, int n_blocks, int row_blocks, int6
 hipError_t refresh_b_derived(did_ctx* h);  // pack B and form G = B^T B
 hipError_t pack_c(did_ctx* h);             // pack C after it was set from outside the sweep
 int iterate_mfma(did_ctx* h, int32_t n);   // n iterations of the MFMA path on h's buffers
+// did_init_ex for a serving loop: X is validated on the device without a host wait (a
+// device X only) and the set-up stays queued on the handle's stream; check_deferred waits
+// for that stream and returns DID_EINVAL (with the message) if X was not finite and
+// nonnegative, DID_OK otherwise (also for handles made without deferral).
+int init_deferred(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const did_opts* opts,
+                  did_handle* out, ArenaPool* pool = nullptr);
+void pool_free_all(ArenaPool* pool);  // free every pooled arena
+int check_deferred(did_ctx* h);
 
 // Make a device current for the duration of a call.
 struct DeviceGuard {

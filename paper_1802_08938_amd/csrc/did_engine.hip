@@ -138,6 +138,19 @@ void release(did_ctx* h) {
   h->prof_events.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+  if (h->pool && h->arena) {  // back to the serving loop's pool; trim its largest beyond the limit
+    ArenaPool& P = *h->pool;
+    P.free.emplace_back(h->arena, h->arena_cap);
+    P.bytes += h->arena_cap;
+    while (P.bytes > P.limit && !P.free.empty()) {
+      size_t bi = 0;
+      for (size_t i = 1; i < P.free.size(); ++i)
+        if (P.free[i].second > P.free[bi].second) bi = i;
+      (void)hipFree(P.free[bi].first);
+      P.bytes -= P.free[bi].second;
+      P.free.erase(P.free.begin() + (ptrdiff_t)bi);
+    }
+  }
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
   (void)hipGetLastError();
   delete h;
@@ -267,13 +280,27 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     const size_t cap = (size_t)engine_bytes(s, R0, x_copied, o.refresh_every) +
                        64 * (256 + (h->guards ? (size_t)DID_GUARD_ZONE_BYTES : 0));
     void* q = nullptr;
-    if (hipMalloc(&q, cap) != hipSuccess) {
+    size_t qcap = cap;
+    if (h->pool) {  // the smallest pooled arena that fits without wasting more than half of it
+      size_t bi = h->pool->free.size();
+      for (size_t i = 0; i < h->pool->free.size(); ++i) {
+        const size_t c = h->pool->free[i].second;
+        if (c >= cap && c <= cap + cap / 2 && (bi == h->pool->free.size() || c < h->pool->free[bi].second)) bi = i;
+      }
+      if (bi < h->pool->free.size()) {
+        q = h->pool->free[bi].first;
+        qcap = h->pool->free[bi].second;
+        h->pool->bytes -= qcap;
+        h->pool->free.erase(h->pool->free.begin() + (ptrdiff_t)bi);
+      }
+    }
+    if (!q && hipMalloc(&q, cap) != hipSuccess) {
       (void)hipGetLastError();
       return fail(DID_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
     }
-    h->allocs.push_back(q);
+    if (!h->pool) h->allocs.push_back(q);  // a pooled arena goes back to the pool at release
     h->arena = static_cast<unsigned char*>(q);
-    h->arena_cap = cap;
+    h->arena_cap = qcap;
     h->arena_off = 0;
   }
   if (o.stream) {
@@ -311,7 +338,13 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     }
     xin = xtmp;
   }
-  {  // X must be finite and nonnegative
+  if (h->defer_checks && !xtmp) {  // X must be finite and nonnegative: checked later
+    const int v4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xin) & 15) == 0);
+    if ((e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
+        (e = didk::validate(xin, M * N, v4, h->flag, h->st)) != hipSuccess)
+      return dev_fail(h, e, "validate X");
+    h->x_check_pending = true;
+  } else {  // X must be finite and nonnegative
     const int v4 = (M % 4 == 0) && ((reinterpret_cast<uintptr_t>(xin) & 15) == 0);
     int flag = 0;
     if ((e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
@@ -334,7 +367,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       return rc;
     }
     e = didk::tile_x(s, xin, xb, xb + te * esz, h->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e == hipSuccess && (xtmp || !h->defer_checks)) e = hipStreamSynchronize(h->st);
     if (xtmp) (void)hipFree(xtmp);
     if (e != hipSuccess) return dev_fail(h, e, "tiled storage of X");
     h->X = xb;
@@ -389,7 +422,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       (e = hipMemsetAsync(h->Bsc, 0, (size_t)didk::bsc_floats(s.KP) * 4, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->V, 0, (size_t)s.KP * s.KP * 8, h->st)) != hipSuccess ||
       (e = hipMemsetAsync(h->W, 0, (size_t)s.KP * s.Mpad * 8, h->st)) != hipSuccess ||
-      (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess ||
+      (!h->x_check_pending && (e = hipMemsetAsync(h->flag, 0, sizeof(int), h->st)) != hipSuccess) ||
       (e = hipMemsetAsync(h->tdev, 0, sizeof(int64_t), h->st)) != hipSuccess)
     return dev_fail(h, e, "buffer setup");
   if (!s.thin &&
@@ -463,7 +496,7 @@ int apply_init_scale(did_ctx* h) {
 }
 
 int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const float* B0, const float* C0,
-                const did_opts* opts, did_handle* out) {
+                const did_opts* opts, did_handle* out, bool defer = false, ArenaPool* pool = nullptr) {
   if (!out) return fail(DID_EINVAL, "out must not be NULL");
   *out = nullptr;
   if (!X) return fail(DID_EINVAL, "X must not be NULL");
@@ -474,6 +507,8 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
   if (opts) o = *opts;
   did_ctx* h = new (std::nothrow) did_ctx();
   if (!h) return fail(DID_ENOMEM, "host allocation failed");
+  h->defer_checks = defer && !B0;
+  h->pool = pool;
   if ((rc = setup(h, X, M, N, K, o))) {
     release(h);
     return rc;
@@ -518,13 +553,41 @@ int init_common(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, c
       return rc;
     }
   }
-  if ((e = hipStreamSynchronize(h->st)) != hipSuccess) {
+  // deferred: the draw and packing stay queued ahead of everything the handle does next
+  if ((e = h->defer_checks ? hipGetLastError() : hipStreamSynchronize(h->st)) != hipSuccess) {
     rc = dev_fail(h, e, "init");
     release(h);
     return rc;
   }
   *out = h;
   g_err.clear();
+  return DID_OK;
+}
+
+int init_deferred(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const did_opts* opts,
+                  did_handle* out, ArenaPool* pool) {
+  return init_common(X, M, N, K, seed, nullptr, nullptr, opts, out, true, pool);
+}
+
+void pool_free_all(ArenaPool* pool) {
+  if (!pool) return;
+  for (auto& a : pool->free) (void)hipFree(a.first);
+  pool->free.clear();
+  pool->bytes = 0;
+}
+
+int check_deferred(did_ctx* h) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceGuard g(h->dev);
+  hipError_t e;
+  if ((e = hipStreamSynchronize(h->st)) != hipSuccess) return dev_fail(h, e, "set-up");
+  if (!h->x_check_pending) return DID_OK;
+  int flag = 0;
+  if ((e = hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return dev_fail(h, e, "validate X");
+  h->x_check_pending = false;
+  if (flag) return fail(DID_EINVAL, "X must be finite and nonnegative");
   return DID_OK;
 }
 
