@@ -405,6 +405,72 @@ def test_server_released_jobs_return_device_memory():
     assert base - torch.cuda.mem_get_info()[0] < need / 4
 
 
+@pytest.mark.parametrize("tiled", [0, 1])
+def test_server_reused_arenas_give_the_same_results(tiled):
+    """One job at a time, two shapes in turn, the second a little smaller: from the third
+    job on, each admission takes the device memory a released job left behind (still
+    holding that job's values), so every buffer must be set before it is read.  Each result
+    equals the same job run alone, bitwise, and the server holds about two jobs' memory at
+    the end instead of one per job."""
+    torch = require_gpu()
+    shapes = [(400, 3000, 40), (380, 2900, 36)] * 4
+    X = [device_x(torch, to_f32_colmajor(serving_x(M, N, K, seed=120 + i))) for i, (M, N, K) in enumerate(shapes)]
+    torch.cuda.synchronize()
+    announce(f"server arena reuse, tiled={tiled}")
+    base = torch.cuda.mem_get_info()[0]
+    so = did.did_server_default_opts()
+    so.x_tiled = tiled
+    so.max_active = 1
+    so.max_iter = 3
+    so.rel_tol = 0.0
+    s = did.did_server_create(so)
+    res = {}
+    try:
+        ids = [did.did_server_submit(s, X[i], M, N, K, 130 + i) for i, (M, N, K) in enumerate(shapes)]
+        steps = 0
+        while len(res) < len(ids):
+            did.did_server_step(s)
+            steps += 1
+            for i, j in enumerate(ids):
+                if i in res:
+                    continue
+                st, it, _, _, _ = did.did_server_poll(s, j)
+                assert st != did.DID_JOB_FAILED, did.did_last_error()
+                if st == did.DID_JOB_DONE:
+                    M, N, K = shapes[i]
+                    Bt = np.empty((K, M), np.float32)
+                    Ct = np.empty((N, K), np.float32)
+                    did.did_server_result(s, j, Bt, Ct)
+                    res[i] = (it, Bt, Ct)
+                    did.did_server_release(s, j)
+            assert steps < 200
+        did.did_server_step(s)  # releases the last job's handle into the pool
+        torch.cuda.synchronize()
+        o = did.did_default_opts()
+        o.borrow_x = 1
+        o.x_tiled = tiled
+        need = max(did.did_mem_estimate(M, N, K, o, x_on_device=True) for M, N, K in shapes)
+        held = base - torch.cuda.mem_get_info()[0]
+        assert held < 3 * need, (held, need)  # eight jobs, about two arenas
+    finally:
+        did.did_server_free(s)
+    for i, (M, N, K) in enumerate(shapes):
+        it, Bs, Cs = res[i]
+        assert it == so.max_iter
+        o = did.did_default_opts()
+        o.borrow_x = 1
+        h = did.did_init_ex(X[i], M, N, K, 130 + i, o)
+        try:
+            did.did_iterate(h, it)
+            Bt = np.empty((K, M), np.float32)
+            Ct = np.empty((N, K), np.float32)
+            did.did_factors(h, Bt, Ct)
+        finally:
+            did.did_free(h)
+        np.testing.assert_array_equal(Bs, Bt)
+        np.testing.assert_array_equal(Cs, Ct)
+
+
 @pytest.mark.parametrize("M,N,K,xd,borrow,tiled,refresh", [
     (300, 2000, 10, did.DID_F32, 1, 0, 1), (300, 2000, 10, did.DID_F32, 0, 0, 1),
     (130, 777, 64, did.DID_BF16, 0, 0, 1), (5, 1000, 3, did.DID_F32, 1, 0, 1),
