@@ -296,7 +296,18 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
     }
     if (!q && hipMalloc(&q, cap) != hipSuccess) {
       (void)hipGetLastError();
-      return fail(DID_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
+      q = nullptr;
+      // pooled arenas are idle (their handles' streams were drained at release) and are not
+      // charged to the serving budget: give them back to the device and try once more, so
+      // that the pool never makes an admission fail that would succeed without it
+      if (h->pool && !h->pool->free.empty()) {
+        pool_free_all(h->pool);
+        if (hipMalloc(&q, cap) != hipSuccess) {
+          (void)hipGetLastError();
+          q = nullptr;
+        }
+      }
+      if (!q) return fail(DID_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
     }
     if (!h->pool) h->allocs.push_back(q);  // a pooled arena goes back to the pool at release
     h->arena = static_cast<unsigned char*>(q);
