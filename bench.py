@@ -48,7 +48,7 @@ launch floor: the replay time of a graph of as many empty dependent kernels.
 The engine keeps float32 X in 32x32 tile order (one copy per pass, made at init, or at a
 served job's admission) for the MFMA-path workloads, the batch and both served workloads;
 --x-given reads it as given (column-major) instead.  The tiled copies triple each served
-job's X memory, and serving is faster with them (1000 jobs: 87 against 68 solves/s).
+job's X memory, and serving is faster with them (1000 jobs: 87–93 against 68 solves/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--x-given]
                        [--workload large|large_bf16|image|planted|nsweep|paper|batch|serve]
@@ -716,7 +716,10 @@ def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1
     srv = did.did_server_create(so)
     gen = torch.Generator(device="cuda")
     side = torch.cuda.Stream()
-    queued_x_cap = 100 << 30  # client-side cap on generated, not yet admitted data
+    # client-side cap on generated, not yet admitted data: the device holds it beside the
+    # server's budget and the released jobs' memory the server keeps for reuse (up to 48 GB)
+    total = torch.cuda.get_device_properties(torch.cuda.current_device()).total_memory
+    queued_x_cap = int(min(100 << 30, max(4 << 30, total - so.hbm_budget - (56 << 30))))
     pending = list(range(n_jobs))
     live = {}  # job id -> (index, X tensor, submit time)
     lat, iters, qwait = [], [], []
@@ -762,7 +765,12 @@ def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1
                     i, X, ts = live[jid]
                     if st in (did.DID_JOB_DONE, did.DID_JOB_FAILED):
                         if st == did.DID_JOB_FAILED:
-                            raise RuntimeError(f"job {i} failed")
+                            try:  # the reason the job failed
+                                did.did_server_result(srv, jid)
+                                why = ""
+                            except did.DidError as e:
+                                why = str(e)
+                            raise RuntimeError(f"job {i} failed: {why}")
                         lat.append(ts - jobs[i]["t"] + l)
                         iters.append(it)
                         qwait.append(q)

@@ -315,13 +315,19 @@ int did_batch_free(did_batch b);
  *                      retirement (-1 while not retired) and from submission to admission
  *                      (-1 while queued).
  *   did_server_result  copy a done job's B (M x K) and C (K x N) out, as did_factors.
+ *                      For a failed job it returns DID_ESTATE, and did_last_error()
+ *                      then gives the reason the job failed (an invalid X, a device
+ *                      allocation that failed at admission, ...).
  *   did_server_release forget a retired job and return its memory to the budget; its
  *                      handle is released at the next did_server_step (once the iteration
  *                      in flight has ended) or by did_server_free.  X is not read after
  *                      the job retired, so the caller may free it.  The server keeps the
  *                      device memory of released jobs (up to 48 GB) for later admissions,
  *                      which would otherwise allocate and free it job by job, and frees
- *                      it in did_server_free.
+ *                      it in did_server_free, or at once when an admission's device
+ *                      allocation fails (the admission then tries once more).  The budget
+ *                      is the server's share: device memory the caller holds (inputs not
+ *                      yet submitted, other allocations) must fit beside it.
  *   did_server_memory  bytes charged to the budget now and at most so far.
  * A server, like a handle, is driven from one thread.  Admission is strictly first-in
  * first-out: a head job that does not fit yet (budget, slots, or 64 running jobs of its

@@ -752,7 +752,8 @@ int did_server_result(did_server s, int64_t job, float* B, float* C) {
   auto it = s->jobs.find(job);
   if (it == s->jobs.end()) return fail(DID_EINVAL, "unknown job");
   Job& j = it->second;
-  if (j.state != DID_JOB_DONE || !j.h) return fail(DID_ESTATE, "job has no result (not done, failed or released)");
+  if (j.state == DID_JOB_FAILED) return fail(DID_ESTATE, "job failed: " + j.error);
+  if (j.state != DID_JOB_DONE || !j.h) return fail(DID_ESTATE, "job has no result (not done or released)");
   return did_factors(j.h, B, C);
 }
 

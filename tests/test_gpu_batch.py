@@ -361,6 +361,9 @@ def test_server_fails_a_job_whose_x_is_invalid():
             assert steps < 100
         assert states == {0: did.DID_JOB_DONE, 1: did.DID_JOB_FAILED, 2: did.DID_JOB_DONE}
         assert did.did_server_poll(s, ids[0])[1] == 4
+        with pytest.raises(did.DidError) as err:  # the failed job's reason
+            did.did_server_result(s, ids[1])
+        assert err.value.code == did.DID_ESTATE and "finite and nonnegative" in str(err.value)
     finally:
         did.did_server_free(s)
 
