@@ -720,6 +720,8 @@ def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1
     # server's budget and the released jobs' memory the server keeps for reuse (up to 48 GB)
     total = torch.cuda.get_device_properties(torch.cuda.current_device()).total_memory
     queued_x_cap = int(min(100 << 30, max(4 << 30, total - so.hbm_budget - (56 << 30))))
+    if pregen:  # the inputs are resident already: nothing to hold back
+        queued_x_cap = 1 << 62
     pending = list(range(n_jobs))
     live = {}  # job id -> (index, X tensor, submit time)
     lat, iters, qwait = [], [], []
