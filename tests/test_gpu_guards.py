@@ -51,6 +51,8 @@ def _check_clean(h, label):
     (8, 700, 8, did.DID_F32, 0, 1, did.DID_ALG_DID),        # thin 8 x 8
     (16, 700, 4, did.DID_F32, 0, 1, did.DID_ALG_DID),       # thin 16 x 4
     (5, 1000, 3, did.DID_F32, 0, 1, did.DID_ALG_DBCD),      # DBCD ablation
+    (40, 1, 1, did.DID_F32, 0, 1, did.DID_ALG_DID),         # a single column of X
+    (20, 20, 20, did.DID_F32, 1, 1, did.DID_ALG_DID),       # K = M = N, tile order
 ])
 def test_paths_stay_inside_their_buffers(guards, M, N, K, xd, tiled, refresh, alg):
     torch = require_gpu()

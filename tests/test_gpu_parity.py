@@ -135,6 +135,36 @@ def test_edge_shapes_parity(M, N, K):
     check_trajectory(np.append(out["hist"], out["f"]), fo, label=f"edge {M}x{N} K={K}")
 
 
+@pytest.mark.parametrize("M,N,K", [
+    (40, 1, 1),     # a single column of X (one partial tile); an exact fit after one iteration
+    (20, 20, 20),   # K = M = N
+    (64, 100, 64),  # K = M at the largest supported K
+    (100, 33, 33),  # K = N, just above one tile of columns
+])
+def test_degenerate_shapes_parity(M, N, K):
+    """K as large as min(M, N) allows (the engine rejects more), on planted data.  Factors
+    after one iteration to the usual bars; the objective to 1e-4 relative over 5
+    iterations, plus, where the oracle fits X exactly (f -> 0), an absolute floor of
+    M N (eps32 max|X|)^2: float32 rounding of the residual, which the oracle (float64)
+    does not have."""
+    torch = require_gpu()
+    rng = np.random.default_rng(M * 7 + N + K)
+    X = rng.random((M, K)) @ rng.random((K, N)) + np.abs(0.01 * rng.standard_normal((M, N)))
+    X32 = to_f32_colmajor(X)
+    announce(f"degenerate shape M={M} N={N} K={K}")
+    out = run_gpu(torch, X32, K, iters=(1, 5))
+    B0, C0 = out["init"]
+    B1o, C1o, _ = _oracle_from(X32, B0, C0, 1)
+    check_factors(out[1][0], B1o, out[1][1], C1o, label=f"degenerate {M}x{N} K={K}")
+    _, _, fo = _oracle_from(X32, B0, C0, 5)
+    fg = np.append(out["hist"], out["f"])
+    floor = M * N * (np.finfo(np.float32).eps * float(np.max(X32))) ** 2
+    excess = np.abs(fg - fo) - 1e-4 * fo
+    print(f"[trajectory] degenerate {M}x{N} K={K}: f oracle {fo[-1]:.3e} gpu {fg[-1]:.3e}, "
+          f"largest excess over 1e-4 relative {float(np.max(excess)):.2e} (floor {floor:.2e})", flush=True)
+    assert np.all(excess <= floor), (fg, fo, floor)
+
+
 def _fp32_sensitivity(X32, B0, C0, draws=3):
     """How far the oracle's one-iteration factors move when X is perturbed at the scale of
     float32 rounding of the residual, eps32 * max|B0 C0|: the floor any float32 engine
