@@ -641,6 +641,9 @@ int did_server_submit(did_server s, const void* X, int64_t M, int64_t N, int32_t
 int did_server_step(did_server s, int32_t* n_running, int32_t* n_queued, int32_t* n_finished) {
   int rc = check_server(s);
   if (rc) return rc;
+  // admissions allocate, and take pooled arenas, on the server's device whatever device
+  // the calling thread has made current since did_server_create
+  DeviceGuard g(s->b->dev);
   int32_t finished = 0;
   if (s->inflight) {
     s->inflight = false;
@@ -783,6 +786,7 @@ int did_server_memory(did_server s, int64_t* used, int64_t* peak) {
 
 int did_server_free(did_server s) {
   if (!s) return DID_OK;
+  DeviceGuard g(s->b->dev);  // a server always has its batch (did_server_create)
   if (s->b) {
     (void)did_batch_sync(s->b);
     for (int64_t id : s->running) (void)did_batch_remove(s->b, s->jobs[id].h);
