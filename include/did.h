@@ -304,6 +304,11 @@ int did_batch_free(did_batch b);
  *   x_tiled      1: float32 jobs keep X in tile order (did_opts.x_tiled), which makes
  *                their iterations faster and adds 8 bytes per (padded) entry of X to
  *                their footprint; 0 (default): float32 jobs read the borrowed X as given
+ *   arena_reserve_gib  GiB of device memory reserved when the server is created, from
+ *                which admitted jobs' buffers are carved (first fit) before any other
+ *                device allocation; default 0 (none).  Jobs then start without a
+ *                hipMalloc, whose cost varies with the device's state.  The reserve is
+ *                held until did_server_free, beside what the pool keeps.
  *   stream       hipStream_t for all server work (NULL: one owned by the server)
  * Job states: DID_JOB_QUEUED, DID_JOB_RUNNING, DID_JOB_DONE, DID_JOB_FAILED.
  *   did_server_submit  queue a job (x_dtype DID_F32 or DID_BF16; the init seed as in
@@ -329,6 +334,12 @@ int did_batch_free(did_batch b);
  *                      is the server's share: device memory the caller holds (inputs not
  *                      yet submitted, other allocations) must fit beside it.
  *   did_server_memory  bytes charged to the budget now and at most so far.
+ *   did_server_arena_stats  how admissions got their device memory so far: arenas
+ *                      allocated (hipMalloc), arenas taken from the pool of released
+ *                      jobs' memory, pooled arenas freed (beyond the pool's limit, or
+ *                      to retry a failed allocation), and the bytes pooled now (any
+ *                      pointer may be NULL).  Allocations and frees wait for the device
+ *                      to drain, so many of them in a serving run cost throughput.
  * A server, like a handle, is driven from one thread.  Admission is strictly first-in
  * first-out: a head job that does not fit yet (budget, slots, or 64 running jobs of its
  * K class and X storage) holds back the jobs behind it.
@@ -340,6 +351,7 @@ typedef struct did_server_opts {
   int32_t max_iter;
   double rel_tol;
   int32_t x_tiled;
+  int32_t arena_reserve_gib;
   void* stream;
 } did_server_opts;
 typedef struct did_server_ctx* did_server;
@@ -353,6 +365,7 @@ int did_server_poll(did_server s, int64_t job, int32_t* state, int32_t* iters, d
 int did_server_result(did_server s, int64_t job, float* B, float* C);
 int did_server_release(did_server s, int64_t job);
 int did_server_memory(did_server s, int64_t* used, int64_t* peak);
+int did_server_arena_stats(did_server s, int64_t* allocs, int64_t* reuses, int64_t* frees, int64_t* pooled_bytes);
 int did_server_free(did_server s);
 
 /*

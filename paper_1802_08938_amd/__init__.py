@@ -25,7 +25,8 @@ __all__ = [
     "did_batch_create", "did_batch_add", "did_batch_remove", "did_batch_size", "did_batch_iterate",
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_opts", "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step",
-    "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
+    "did_server_poll", "did_server_result", "did_server_release", "did_server_memory", "did_server_arena_stats",
+    "did_server_free",
     "DID_JOB_QUEUED", "DID_JOB_RUNNING", "DID_JOB_DONE", "DID_JOB_FAILED", "did_debug_inject_fault",
     "did_debug_check_guards", "did_iterate_static", "DID_STATIC_SCRATCH_BYTES", "DID_GUARD_ZONE_BYTES",
 ]
@@ -46,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "did_batch_create", "did_batch_add", "did_batch_remove", "did_batch_size", "did_batch_iterate",
     "did_batch_objectives", "did_batch_sync", "did_batch_free",
     "did_server_default_opts", "did_server_create", "did_server_submit", "did_server_step", "did_server_poll",
-    "did_server_result", "did_server_release", "did_server_memory", "did_server_free",
+    "did_server_result", "did_server_release", "did_server_memory", "did_server_arena_stats", "did_server_free",
     "did_debug_inject_fault", "did_debug_check_guards", "did_iterate_static",
 )
 
@@ -89,7 +90,7 @@ class did_server_opts(ctypes.Structure):
         ("max_iter", ctypes.c_int32),
         ("rel_tol", ctypes.c_double),
         ("x_tiled", ctypes.c_int32),
-        ("col_waves", ctypes.c_int32),
+        ("arena_reserve_gib", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -143,6 +144,8 @@ def lib():
         "did_server_result": [vp, i64, vp, vp],
         "did_server_release": [vp, i64],
         "did_server_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "did_server_arena_stats": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i64)],
         "did_server_free": [vp],
         "did_debug_inject_fault": [vp],
         "did_debug_check_guards": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)],
@@ -380,6 +383,13 @@ def did_server_memory(s):
     u, p = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().did_server_memory(s, ctypes.byref(u), ctypes.byref(p)))
     return u.value, p.value
+
+
+def did_server_arena_stats(s):
+    """(arenas allocated, arenas reused from the pool, pooled arenas freed, bytes pooled)."""
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(lib().did_server_arena_stats(s, *(ctypes.byref(x) for x in v)))
+    return tuple(x.value for x in v)
 
 
 def did_server_free(s):

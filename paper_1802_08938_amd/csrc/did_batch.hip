@@ -567,7 +567,7 @@ int did_server_create(const did_server_opts* opts, did_server* out) {
   did_server_default_opts(&o);
   if (opts) o = *opts;
   if (o.hbm_budget <= 0 || o.max_active < 1 || o.max_active > 4 * kMaxBatch || o.max_iter < 1 ||
-      !(o.rel_tol >= 0.0) || (o.x_tiled != 0 && o.x_tiled != 1))
+      !(o.rel_tol >= 0.0) || (o.x_tiled != 0 && o.x_tiled != 1) || o.arena_reserve_gib < 0)
     return fail(DID_EINVAL, "bad server options");
   did_server_ctx* s = new (std::nothrow) did_server_ctx();
   if (!s) return fail(DID_ENOMEM, "host allocation failed");
@@ -588,6 +588,9 @@ int did_server_create(const did_server_opts* opts, did_server* out) {
     return fail(DID_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
   }
   int rc = did_batch_create(s->st, &s->b);
+  if (!rc && o.arena_reserve_gib > 0) {
+    if ((rc = didengine::pool_reserve_slab(&s->pool, (size_t)o.arena_reserve_gib << 30))) did_batch_free(s->b);
+  }
   if (rc) {
     (void)hipStreamDestroy(s->adm_st);
     if (s->own_stream) (void)hipStreamDestroy(s->st);
@@ -784,6 +787,16 @@ int did_server_memory(did_server s, int64_t* used, int64_t* peak) {
   return DID_OK;
 }
 
+int did_server_arena_stats(did_server s, int64_t* allocs, int64_t* reuses, int64_t* frees, int64_t* pooled_bytes) {
+  int rc = check_server(s);
+  if (rc) return rc;
+  if (allocs) *allocs = s->pool.allocs;
+  if (reuses) *reuses = s->pool.reuses;
+  if (frees) *frees = s->pool.frees;
+  if (pooled_bytes) *pooled_bytes = (int64_t)s->pool.bytes;
+  return DID_OK;
+}
+
 int did_server_free(did_server s) {
   if (!s) return DID_OK;
   DeviceGuard g(s->b->dev);  // a server always has its batch (did_server_create)
@@ -795,6 +808,7 @@ int did_server_free(did_server s) {
     if (kv.second.h) did_free(kv.second.h);
   for (did_handle h : s->retired) did_free(h);
   didengine::pool_free_all(&s->pool);
+  didengine::pool_free_slab(&s->pool);  // every handle, and so every arena carved from it, is gone
   did_batch_free(s->b);
   if (s->adm_st) (void)hipStreamDestroy(s->adm_st);
   if (s->own_stream) (void)hipStreamDestroy(s->st);

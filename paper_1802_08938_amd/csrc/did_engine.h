@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -16,10 +17,19 @@ struct did_batch_ctx;
 // Device arenas kept for reuse by the handles of one serving loop: a handle made with a
 // pool carves its buffers from the smallest pooled arena that fits (wasting at most half of
 // it) and gives its arena back at release; the pool frees its largest arenas beyond limit.
+//
+// A serving loop may also reserve one slab of device memory when it is created; arenas are
+// then carved from the slab first (first fit, adjacent free ranges merged at release), so
+// that admissions call no hipMalloc while the slab has room.
 struct ArenaPool {
   std::vector<std::pair<void*, size_t>> free;  // (pointer, capacity)
   size_t bytes = 0;
   size_t limit = size_t(48) << 30;
+  // arenas allocated for admissions, taken from the pool or the slab, and freed
+  int64_t allocs = 0, reuses = 0, frees = 0;
+  unsigned char* slab = nullptr;
+  size_t slab_cap = 0;
+  std::map<size_t, size_t> slab_free;  // offset -> length of each free range of the slab
 };
 
 struct did_ctx {
@@ -74,6 +84,7 @@ struct did_ctx {
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_off = 0;
   ArenaPool* pool = nullptr;  // the serving loop's pool the arena comes from and returns to
+  bool arena_in_slab = false;  // carved from the pool's slab (returned to the slab at release)
   // made by a serving loop: X's validation result and the set-up work stay queued on the
   // stream (no host wait); check_deferred reads the result once the stream has drained
   bool defer_checks = false;
@@ -125,7 +136,9 @@ int iterate_mfma(did_ctx* h, int32_t n);   // n iterations of the MFMA path on h
 // nonnegative, DID_OK otherwise (also for handles made without deferral).
 int init_deferred(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed, const did_opts* opts,
                   did_handle* out, ArenaPool* pool = nullptr);
-void pool_free_all(ArenaPool* pool);  // free every pooled arena
+void pool_free_all(ArenaPool* pool);  // free every pooled arena (not the slab)
+int pool_reserve_slab(ArenaPool* pool, size_t bytes);  // allocate the slab (DID_ENOMEM if it fails)
+void pool_free_slab(ArenaPool* pool);                  // once no arena of the slab is in use
 int check_deferred(did_ctx* h);
 
 // Make a device current for the duration of a call.

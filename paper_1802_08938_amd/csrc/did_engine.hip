@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -138,7 +139,24 @@ void release(did_ctx* h) {
   h->prof_events.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
-  if (h->pool && h->arena) {  // back to the serving loop's pool; trim its largest beyond the limit
+  if (h->pool && h->arena && h->arena_in_slab) {  // back to the slab, merged with free neighbours
+    auto& fr = h->pool->slab_free;
+    size_t off = (size_t)(h->arena - h->pool->slab), len = h->arena_cap;
+    auto nx = fr.lower_bound(off);
+    if (nx != fr.end() && nx->first == off + len) {
+      len += nx->second;
+      nx = fr.erase(nx);
+    }
+    if (nx != fr.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        len += pv->second;
+        fr.erase(pv);
+      }
+    }
+    fr.emplace(off, len);
+  } else if (h->pool && h->arena) {  // back to the serving loop's pool; trim its largest beyond the limit
     ArenaPool& P = *h->pool;
     P.free.emplace_back(h->arena, h->arena_cap);
     P.bytes += h->arena_cap;
@@ -147,6 +165,7 @@ void release(did_ctx* h) {
       for (size_t i = 1; i < P.free.size(); ++i)
         if (P.free[i].second > P.free[bi].second) bi = i;
       (void)hipFree(P.free[bi].first);
+      ++P.frees;
       P.bytes -= P.free[bi].second;
       P.free.erase(P.free.begin() + (ptrdiff_t)bi);
     }
@@ -281,7 +300,24 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
                        64 * (256 + (h->guards ? (size_t)DID_GUARD_ZONE_BYTES : 0));
     void* q = nullptr;
     size_t qcap = cap;
-    if (h->pool) {  // the smallest pooled arena that fits without wasting more than half of it
+    bool pooled = false;
+    if (h->pool && h->pool->slab) {  // first fit in the slab
+      auto& fr = h->pool->slab_free;
+      const size_t need = (cap + 255) & ~size_t(255);
+      for (auto it = fr.begin(); it != fr.end(); ++it) {
+        if (it->second < need) continue;
+        const size_t off = it->first, len = it->second;
+        fr.erase(it);
+        if (len > need) fr.emplace(off + need, len - need);
+        q = h->pool->slab + off;
+        qcap = need;
+        h->arena_in_slab = true;
+        pooled = true;
+        ++h->pool->reuses;
+        break;
+      }
+    }
+    if (h->pool && !q) {  // the smallest pooled arena that fits without wasting more than half of it
       size_t bi = h->pool->free.size();
       for (size_t i = 0; i < h->pool->free.size(); ++i) {
         const size_t c = h->pool->free[i].second;
@@ -292,6 +328,8 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
         qcap = h->pool->free[bi].second;
         h->pool->bytes -= qcap;
         h->pool->free.erase(h->pool->free.begin() + (ptrdiff_t)bi);
+        ++h->pool->reuses;
+        pooled = true;
       }
     }
     if (!q && hipMalloc(&q, cap) != hipSuccess) {
@@ -310,6 +348,7 @@ int setup(did_ctx* h, const void* Xv, int64_t M, int64_t N, int32_t K, const did
       if (!q) return fail(DID_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
     }
     if (!h->pool) h->allocs.push_back(q);  // a pooled arena goes back to the pool at release
+    else if (!pooled) ++h->pool->allocs;
     h->arena = static_cast<unsigned char*>(q);
     h->arena_cap = qcap;
     h->arena_off = 0;
@@ -580,9 +619,33 @@ int init_deferred(const void* X, int64_t M, int64_t N, int32_t K, uint64_t seed,
   return init_common(X, M, N, K, seed, nullptr, nullptr, opts, out, true, pool);
 }
 
+int pool_reserve_slab(ArenaPool* pool, size_t bytes) {
+  bytes &= ~size_t(255);
+  void* p = nullptr;
+  if (bytes == 0) return DID_OK;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DID_ENOMEM, "device allocation of the " + std::to_string(bytes) + "-byte arena reserve failed");
+  }
+  pool->slab = static_cast<unsigned char*>(p);
+  pool->slab_cap = bytes;
+  pool->slab_free.clear();
+  pool->slab_free.emplace(0, bytes);
+  return DID_OK;
+}
+
+void pool_free_slab(ArenaPool* pool) {
+  if (!pool || !pool->slab) return;
+  (void)hipFree(pool->slab);
+  pool->slab = nullptr;
+  pool->slab_cap = 0;
+  pool->slab_free.clear();
+}
+
 void pool_free_all(ArenaPool* pool) {
   if (!pool) return;
   for (auto& a : pool->free) (void)hipFree(a.first);
+  pool->frees += (int64_t)pool->free.size();
   pool->free.clear();
   pool->bytes = 0;
 }

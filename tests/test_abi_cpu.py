@@ -45,7 +45,9 @@ def test_default_opts_and_struct_layout():
     assert ctypes.sizeof(did.did_opts) == 48
     so = did.did_server_default_opts()
     assert (so.hbm_budget, so.max_active, so.max_iter, so.rel_tol) == (200 << 30, 64, 50, 1e-4)
+    assert (so.x_tiled, so.arena_reserve_gib) == (0, 0) and so.stream is None
     assert ctypes.sizeof(did.did_server_opts) == 40
+    assert did.did_server_opts.arena_reserve_gib.offset == 28 and did.did_server_opts.stream.offset == 32
 
 
 @pytest.mark.parametrize("M,N,K,msg", [
@@ -138,6 +140,10 @@ def test_batch_and_server_null_arguments():
     h = ctypes.c_void_p()
     assert L.did_server_create(ctypes.byref(so), ctypes.byref(h)) == did.DID_EINVAL
     assert "server options" in did.did_last_error()
+    so = did.did_server_default_opts()
+    so.arena_reserve_gib = -1
+    assert L.did_server_create(ctypes.byref(so), ctypes.byref(h)) == did.DID_EINVAL
+    assert L.did_server_arena_stats(None, None, None, None, None) == did.DID_EINVAL
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -408,13 +408,14 @@ def test_server_released_jobs_return_device_memory():
     assert base - torch.cuda.mem_get_info()[0] < need / 4
 
 
-@pytest.mark.parametrize("tiled", [0, 1])
-def test_server_reused_arenas_give_the_same_results(tiled):
+@pytest.mark.parametrize("tiled,reserve", [(0, 0), (1, 0), (1, 1)])
+def test_server_reused_arenas_give_the_same_results(tiled, reserve):
     """One job at a time, two shapes in turn, the second a little smaller: from the third
     job on, each admission takes the device memory a released job left behind (still
     holding that job's values), so every buffer must be set before it is read.  Each result
     equals the same job run alone, bitwise, and the server holds about two jobs' memory at
-    the end instead of one per job."""
+    the end instead of one per job.  With a reserve (1 GiB), every job is carved from it:
+    no allocation at all, and the freed ranges are merged and carved again."""
     torch = require_gpu()
     shapes = [(400, 3000, 40), (380, 2900, 36)] * 4
     X = [device_x(torch, to_f32_colmajor(serving_x(M, N, K, seed=120 + i))) for i, (M, N, K) in enumerate(shapes)]
@@ -426,6 +427,7 @@ def test_server_reused_arenas_give_the_same_results(tiled):
     so.max_active = 1
     so.max_iter = 3
     so.rel_tol = 0.0
+    so.arena_reserve_gib = reserve
     s = did.did_server_create(so)
     res = {}
     try:
@@ -454,7 +456,15 @@ def test_server_reused_arenas_give_the_same_results(tiled):
         o.x_tiled = tiled
         need = max(did.did_mem_estimate(M, N, K, o, x_on_device=True) for M, N, K in shapes)
         held = base - torch.cuda.mem_get_info()[0]
-        assert held < 3 * need, (held, need)  # eight jobs, about two arenas
+        allocs, reuses, frees, pooled = did.did_server_arena_stats(s)
+        if reserve:
+            assert (allocs, reuses, frees, pooled) == (0, len(shapes), 0, 0)
+            assert held < (reserve << 30) + 3 * need, (held, need)
+        else:
+            assert held < 3 * need, (held, need)  # eight jobs, about two arenas
+            assert allocs + reuses == len(shapes) and reuses >= len(shapes) - 3 and frees == 0, (allocs, reuses,
+                                                                                                  frees)
+            assert 0 < pooled < held
     finally:
         did.did_server_free(s)
     for i, (M, N, K) in enumerate(shapes):
