@@ -326,8 +326,9 @@ int did_batch_free(did_batch b);
  *   did_server_release forget a retired job and return its memory to the budget; its
  *                      handle is released at the next did_server_step (once the iteration
  *                      in flight has ended) or by did_server_free.  X is not read after
- *                      the job retired, so the caller may free it.  The server keeps the
- *                      device memory of released jobs (up to 48 GB) for later admissions,
+ *                      the job retired, so the caller may free it.  Memory carved from the
+ *                      reserve (arena_reserve_gib) goes back to it; the server keeps the
+ *                      other device memory of released jobs (up to 48 GB) for later admissions,
  *                      which would otherwise allocate and free it job by job, and frees
  *                      it in did_server_free, or at once when an admission's device
  *                      allocation fails (the admission then tries once more).  The budget
