@@ -693,7 +693,7 @@ def run_batch(args, torch, did):
 PREGEN_CAP = 120 << 30  # X of all jobs generated before the clock starts when it fits
 
 
-def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1e-4):
+def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1e-4, reserve_gib=-1):
     """Poisson arrivals (200 jobs/s) into the server; latency from the scheduled arrival to
     retirement.  Returns a dict of throughput, latency and queue figures.  When the jobs'
     X fit in PREGEN_CAP they are all generated on the device before the clock starts (the
@@ -714,7 +714,7 @@ def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1
     # with the inputs resident before the clock, the server reserves 64 GiB at creation for
     # its jobs' buffers (about 45 GB in use at the peak of the 300-job run), so that no
     # admission inside the timed region allocates device memory
-    so.arena_reserve_gib = 64 if pregen else 0
+    so.arena_reserve_gib = (64 if pregen else 0) if reserve_gib < 0 else reserve_gib
     stream = torch.cuda.Stream()
     so.stream = stream.cuda_stream
     srv = did.did_server_create(so)
@@ -821,7 +821,8 @@ def serve_measure(torch, did, n_jobs, slots, bf16, tiled, max_iter=50, rel_tol=1
 def run_serve(args, torch, did):
     cfg = WORKLOADS["serve"]
     n_jobs = args.serve_jobs or cfg["jobs"]
-    r = serve_measure(torch, did, n_jobs, args.serve_slots, args.serve_bf16, not args.x_given)
+    r = serve_measure(torch, did, n_jobs, args.serve_slots, args.serve_bf16, not args.x_given,
+                      reserve_gib=args.serve_reserve)
     line = {
         "metric": METRIC,
         "value": r["solves_per_s"],
@@ -931,6 +932,9 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=0, help="serve workload: number of jobs (default 1000)")
     ap.add_argument("--serve-slots", type=int, default=64, help="serve workload: batch slots")
     ap.add_argument("--serve-bf16", action="store_true", help="serve workload: store each job's X as bf16")
+    ap.add_argument("--serve-reserve", type=int, default=-1,
+                    help="GiB the server reserves at creation for its jobs' buffers (default: 64 when the "
+                         "inputs are generated before the clock, else 0)")
     ap.add_argument("--x-given", action="store_true",
                     help="float32 X read as given (column-major) instead of kept in tile order")
     ap.add_argument("--serve-tiled", action="store_true",
@@ -1085,14 +1089,16 @@ def main():
         # float32 jobs keep X in tile order like the other forms (each job's two tiled copies
         # are made at its admission, inside the timed region), unless --x-given
         tiled = not args.x_given
-        line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled)
+        line["served_form"] = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled,
+                                            reserve_gib=args.serve_reserve)
         line["served_form"]["note"] = ("a shortened run of the served workload: the first jobs of the same "
                                        "Poisson schedule (200 jobs/s), 200 GB budget, all inputs resident in "
                                        "HBM before the clock starts; " +
                                        ("X kept in tile order, copied at admission" if tiled else "X read as given"))
         # the same jobs with a stopping rule loose enough to fire: retirements free slots
         # mid-mix and the queue is admitted as they do
-        es = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled, rel_tol=1e-2)
+        es = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled, rel_tol=1e-2,
+                           reserve_gib=args.serve_reserve)
         line["served_form"]["early_stop"] = {k: es[k] for k in (
             "rel_tol", "solves_per_s", "latency_p50_s", "latency_p99_s", "iterations_mean",
             "share_stopped_by_rel_tol", "max_queue_depth")}
