@@ -155,13 +155,14 @@ def test_batch_rejections():
         did.did_free(h)
 
 
-@pytest.mark.parametrize("tiled", [0, 1])
-def test_server_results_equal_alone_and_budget_holds(tiled):
+@pytest.mark.parametrize("tiled,reserve", [(0, 0), (1, 0), (1, 1)])
+def test_server_results_equal_alone_and_budget_holds(tiled, reserve):
     """Jobs of uneven shape arrive over several steps; the budget admits about two at a
     time, so later jobs queue and are admitted as earlier ones retire and are released.
     Every result equals the same job run alone (X column-major) for the same number of
-    iterations, also when the server keeps X in tile order; the charged memory never
-    exceeds the budget, and jobs are admitted first-in first-out."""
+    iterations, also when the server keeps X in tile order, and when it carves the jobs'
+    buffers from a reserve (released out of order, ranges merged and carved again); the
+    charged memory never exceeds the budget, and jobs are admitted first-in first-out."""
     torch = require_gpu()
     jobs = [(300, 2000, 10), (500, 1200, 40), (200, 4000, 64), (640, 900, 5), (128, 3000, 33), (350, 2500, 20)]
     o0 = did.did_default_opts()
@@ -174,7 +175,8 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
     so.max_active = 4
     so.max_iter = 30
     so.rel_tol = 1e-3
-    announce(f"server, budget {so.hbm_budget} bytes")
+    so.arena_reserve_gib = reserve
+    announce(f"server, budget {so.hbm_budget} bytes, reserve {reserve} GiB")
     s = did.did_server_create(so)
     X = {}
     ids = []
@@ -216,6 +218,8 @@ def test_server_results_equal_alone_and_budget_holds(tiled):
         used, peak = did.did_server_memory(s)
         assert used == 0 and 0 < peak <= so.hbm_budget
         assert peak_running <= so.max_active
+        if reserve:  # every job carved from the reserve
+            assert did.did_server_arena_stats(s)[:3] == (0, len(jobs), 0)
         assert admit_order == sorted(admit_order)  # first in, first out
     finally:
         did.did_server_free(s)
