@@ -336,8 +336,8 @@ int did_batch_free(did_batch b);
  *                      yet submitted, other allocations) must fit beside it.
  *   did_server_memory  bytes charged to the budget now and at most so far.
  *   did_server_arena_stats  how admissions got their device memory so far: arenas
- *                      allocated (hipMalloc), arenas taken from the pool of released
- *                      jobs' memory, pooled arenas freed (beyond the pool's limit, or
+ *                      allocated (hipMalloc), arenas carved from the reserve or taken
+ *                      from the pool of released jobs' memory, pooled arenas freed (beyond the pool's limit, or
  *                      to retry a failed allocation), and the bytes pooled now (any
  *                      pointer may be NULL).  Allocations and frees wait for the device
  *                      to drain, so many of them in a serving run cost throughput.
