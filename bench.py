@@ -1095,7 +1095,8 @@ def main():
                                        "Poisson schedule (200 jobs/s), 200 GB budget, all inputs resident in "
                                        "HBM before the clock starts; " +
                                        ("X kept in tile order, copied at admission" if tiled else "X read as given") +
-                                       "; the jobs' buffers carved from a reserve made when the server starts")
+                                       ("; the jobs' buffers carved from a reserve made when the server starts"
+                                        if line["served_form"]["arenas"]["reserve_gib"] > 0 else ""))
         # the same jobs with a stopping rule loose enough to fire: retirements free slots
         # mid-mix and the queue is admitted as they do
         es = serve_measure(torch, did, args.serve_jobs or 300, args.serve_slots, False, tiled, rel_tol=1e-2,
